@@ -1,0 +1,220 @@
+"""Seeded synthetic inputs for the moving-mesh finite-volume step.
+
+This module is shared by the HIP path, the CPU oracle, the tests and the
+benchmark.  It only draws point positions and primitive fields
+(rho, vx, vy, vz, P); it holds none of the method's arithmetic (no volumes,
+no charges, no fluxes).  Every generator is deterministic in its seed
+(numpy PCG64).
+
+The paper's own initial conditions are tiled glass files (Sec. 5
+introduction), which are not available; jittered cubic lattices and Poisson
+points of the same shapes and sizes stand in for them.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Default scheme parameters.  eta = 1 (Lagrangian mesh), chi = 1 and
+# zeta = 0.25 (Sec. 4.2), theta = 0.49 (Sec. 5.1), floors far below every
+# workload's density and pressure.
+DEFAULT_PARAMS = dict(
+    gamma=5.0 / 3.0,
+    cfl=0.3,
+    eta=1.0,
+    chi=1.0,
+    zeta=0.25,
+    theta=0.49,
+    rho_floor=1e-12,
+    p_floor=1e-14,
+)
+
+
+@dataclass
+class Workload:
+    """One synthetic simulation input.
+
+    pos   : float64 [n, 3], every coordinate in [0, box).
+    prim  : float64 [n, 5], columns rho, vx, vy, vz, P.
+    box   : periodic box lengths.
+    params: scheme parameters (gamma, cfl, eta, chi, zeta, theta, floors).
+    steps : number of steps the workload is defined for.
+    energy_cells / energy_amount: optional point deposit of total energy,
+        added to the charge E of each listed cell after the first
+        tessellation.
+    """
+
+    name: str
+    pos: np.ndarray
+    prim: np.ndarray
+    box: tuple
+    params: dict
+    steps: int
+    energy_cells: np.ndarray | None = None
+    energy_amount: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+
+def _params(**over):
+    p = dict(DEFAULT_PARAMS)
+    p.update(over)
+    return p
+
+
+def _wrap_inside(pos: np.ndarray, box) -> np.ndarray:
+    """Move coordinates into [0, L) (only ever needed for jitter at edges)."""
+    L = np.asarray(box, dtype=np.float64)
+    pos = np.where(pos < 0.0, pos + L, pos)
+    pos = np.where(pos >= L, pos - L, pos)
+    return np.ascontiguousarray(pos, dtype=np.float64)
+
+
+def jittered_lattice(shape, box, jitter=1e-3, seed=0) -> np.ndarray:
+    """Cubic lattice with nx*ny*nz points at ((i + 1/2) h) plus uniform
+    jitter in [-jitter*h, +jitter*h] per axis (h the lattice spacing of that
+    axis).  Point order is x fastest, then y, then z."""
+    nx, ny, nz = (int(s) for s in shape)
+    L = np.asarray(box, dtype=np.float64)
+    h = L / np.array([nx, ny, nz], dtype=np.float64)
+    iz, iy, ix = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    base = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    base = (base + 0.5) * h
+    rng = np.random.default_rng(seed)
+    jit = rng.uniform(-jitter, jitter, size=base.shape) * h
+    return _wrap_inside(base + jit, box)
+
+
+def poisson_points(n, box, seed=0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    L = np.asarray(box, dtype=np.float64)
+    return _wrap_inside(rng.uniform(0.0, 1.0, size=(int(n), 3)) * L, box)
+
+
+def bcc_lattice(m, box=(1.0, 1.0, 1.0), offset=0.25) -> np.ndarray:
+    """Body-centred cubic lattice: m^3 cube corners plus m^3 body centres
+    (2 m^3 points), cubic side a = L/m.  `offset` (in units of a) shifts the
+    whole lattice away from the box walls.  No jitter: the Voronoi cell of
+    every point is the same truncated octahedron."""
+    L = np.asarray(box, dtype=np.float64)
+    a = L / m
+    iz, iy, ix = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    base = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    corners = (base + offset) * a
+    centres = (base + offset + 0.5) * a
+    return _wrap_inside(np.concatenate([corners, centres], axis=0), box)
+
+
+# ---------------------------------------------------------------------------
+# The five workloads.  Sizes default to the full configurations; the tests
+# call them with smaller shapes of the same structure.
+# ---------------------------------------------------------------------------
+
+def c1_uniform_random_velocity(n_side=16, seed=1) -> Workload:
+    """Unit cube, n_side^3 jittered lattice, gamma = 5/3, rho = 1, P = 1,
+    velocities uniform in [-0.1, 0.1]^3, one step at CFL 0.3."""
+    box = (1.0, 1.0, 1.0)
+    pos = jittered_lattice((n_side,) * 3, box, seed=seed)
+    n = pos.shape[0]
+    rng = np.random.default_rng(seed + 1000)
+    prim = np.empty((n, 5))
+    prim[:, 0] = 1.0
+    prim[:, 1:4] = rng.uniform(-0.1, 0.1, size=(n, 3))
+    prim[:, 4] = 1.0
+    return Workload("c1_uniform_random_velocity", pos, prim, box,
+                    _params(gamma=5.0 / 3.0), steps=1,
+                    meta=dict(shape=(n_side,) * 3))
+
+
+def c2_sod(shape=(256, 64, 64), seed=2, box=(4.0, 1.0, 1.0)) -> Workload:
+    """Periodic Sod shock tube: x < L/2: rho = 1, P = 1; x >= L/2:
+    rho = 0.125, P = 0.1; v = 0, gamma = 1.4, Lagrangian mesh, 50 steps."""
+    pos = jittered_lattice(shape, box, seed=seed)
+    n = pos.shape[0]
+    prim = np.zeros((n, 5))
+    left = pos[:, 0] < 0.5 * box[0]
+    prim[:, 0] = np.where(left, 1.0, 0.125)
+    prim[:, 4] = np.where(left, 1.0, 0.1)
+    return Workload("c2_sod", pos, prim, box, _params(gamma=1.4), steps=50,
+                    meta=dict(shape=tuple(shape)))
+
+
+def c3_point_blast(n_side=128, seed=3, n_hot=32) -> Workload:
+    """Unit cube, n_side^3 jittered lattice, rho = 1, P = 1e-5, v = 0,
+    gamma = 5/3; total energy 1 shared equally by the n_hot generators
+    nearest the box centre; 100 steps."""
+    box = (1.0, 1.0, 1.0)
+    pos = jittered_lattice((n_side,) * 3, box, seed=seed)
+    n = pos.shape[0]
+    prim = np.zeros((n, 5))
+    prim[:, 0] = 1.0
+    prim[:, 4] = 1e-5
+    r2 = np.sum((pos - 0.5) ** 2, axis=1)
+    hot = np.argsort(r2, kind="stable")[:n_hot]
+    return Workload("c3_point_blast", pos, prim, box, _params(gamma=5.0 / 3.0),
+                    steps=100, energy_cells=np.sort(hot).astype(np.int64),
+                    energy_amount=1.0 / n_hot, meta=dict(shape=(n_side,) * 3))
+
+
+def c4_kelvin_helmholtz(k, n_min=1000, n_max=200000, base_seed=4000) -> Workload:
+    """Serving request k: unit cube, N drawn log-uniform in [n_min, n_max],
+    rounded to a cube n^3; slab |y - 0.5| < 0.25 has rho = 2, vx = +0.5,
+    outside rho = 1, vx = -0.5; P = 2.5; vy = 0.01 sin(4 pi x); 20 steps."""
+    seed = base_seed + int(k)
+    rng = np.random.default_rng(seed)
+    n_target = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+    side = max(2, int(round(n_target ** (1.0 / 3.0))))
+    box = (1.0, 1.0, 1.0)
+    pos = jittered_lattice((side,) * 3, box, seed=seed)
+    n = pos.shape[0]
+    inner = np.abs(pos[:, 1] - 0.5) < 0.25
+    prim = np.zeros((n, 5))
+    prim[:, 0] = np.where(inner, 2.0, 1.0)
+    prim[:, 1] = np.where(inner, 0.5, -0.5)
+    prim[:, 2] = 0.01 * np.sin(4.0 * np.pi * pos[:, 0])
+    prim[:, 4] = 2.5
+    return Workload(f"c4_kh_{k}", pos, prim, box, _params(gamma=5.0 / 3.0),
+                    steps=20, meta=dict(shape=(side,) * 3, request=int(k)))
+
+
+def uniform_state(pos, box, rho=1.0, vel=(0.0, 0.0, 0.0), P=1.0, gamma=5.0 / 3.0,
+                  name="uniform", **over) -> Workload:
+    """Uniform density, velocity and pressure on a given point set."""
+    n = pos.shape[0]
+    prim = np.empty((n, 5))
+    prim[:, 0] = rho
+    prim[:, 1:4] = np.asarray(vel, dtype=np.float64)
+    prim[:, 4] = P
+    return Workload(name, np.ascontiguousarray(pos), prim, tuple(box),
+                    _params(gamma=gamma, **over), steps=10)
+
+
+def random_smooth_state(pos, box, seed=0, amp=0.2, gamma=5.0 / 3.0, name="smooth",
+                        **over) -> Workload:
+    """A smooth periodic non-uniform state (sums of low sine modes) used by
+    parity tests: every component varies, nothing is near a floor."""
+    rng = np.random.default_rng(seed)
+    L = np.asarray(box, dtype=np.float64)
+    x = pos / L
+    n = pos.shape[0]
+    prim = np.empty((n, 5))
+    base = [1.0, 0.0, 0.0, 0.0, 1.0]
+    for c in range(5):
+        acc = np.full(n, base[c])
+        for _ in range(3):
+            kv = rng.integers(-2, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            a = rng.uniform(-amp, amp) * (0.5 if c in (0, 4) else 1.0)
+            acc += a * np.sin(2 * np.pi * (x @ kv) + ph)
+        prim[:, c] = acc
+    return Workload(name, np.ascontiguousarray(pos), prim, tuple(box),
+                    _params(gamma=gamma, **over), steps=5)
+
+
+def mean_spacing(n, box) -> float:
+    return float((box[0] * box[1] * box[2] / n) ** (1.0 / 3.0))
