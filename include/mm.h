@@ -1,0 +1,214 @@
+/*
+ * mm.h -- C ABI of the MI355X moving-mesh finite-volume step.
+ *
+ * The library computes one explicit step of the arbitrary Lagrangian-Eulerian
+ * finite-volume scheme of Chang, Wadsley & Quinn (2017), "A moving mesh
+ * hydrodynamic solver for ChaNGa", on one AMD Instinct MI355X (gfx950):
+ *   periodic Voronoi tessellation of the mesh-generating points (Sec. 3),
+ *   cell volumes, centroids, face areas and face centres,
+ *   least-squares gradients with the S10 slope limiter (Sec. 4.1),
+ *   the half-step predictor (Sec. 4.1),
+ *   limited linear reconstruction to the face centres (Sec. 4.1),
+ *   HLLC fluxes in the frame of each moving face (Sec. 4, items 1-5),
+ *   the conserved-charge update (Sec. 4, eq. "time evolution"),
+ *   mesh velocities and the CFL timestep (Sec. 4.2), and the drift.
+ *
+ * Conventions shared by every call:
+ *   - Pointers named "dev" are device pointers on the context's device; the
+ *     caller owns them and the library never frees them.  Pointers named
+ *     "host" are host memory.
+ *   - Per-point arrays are row-major, in the caller's point order:
+ *     positions [n][3] (x, y, z), primitives [n][5] (rho, vx, vy, vz, P),
+ *     charges Q [n][5] (mass, momentum x/y/z, total energy, i.e. the
+ *     integral of (rho, rho v, rho e) over the cell, Sec. 4), conserved
+ *     densities U [n][5] = Q / V, gradients [n][5][3] (d U_q / d x_a),
+ *     mesh velocities [n][3].
+ *   - U and gradients are double for MM_FP64 and float for MM_MIXED;
+ *     positions, charges, mesh velocities and charge changes are always
+ *     double.
+ *   - All work is enqueued on the HIP stream given to mm_create, in order.
+ *     Calls that report a status computed on the device (mm_tessellate,
+ *     mm_cell_state, mm_step) wait for that stream once, at their end, to
+ *     read a small status block; the others return without waiting.
+ *   - The context owns every internal buffer, all reserved by mm_create for
+ *     n_capacity points; no call after mm_create allocates device memory.
+ *   - Errors are returned as mm_status codes; mm_last_error() gives a
+ *     message.  No C++ exception crosses this interface.  A context is not
+ *     thread-safe; use one context per host thread.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_ctx mm_ctx;
+
+typedef enum {
+  MM_OK = 0,
+  MM_EINVAL = -1,       /* bad argument: null pointer, n > capacity, point outside [0, L) or not finite */
+  MM_ENOMEM = -2,       /* device allocation failed in mm_create */
+  MM_ECAPACITY = -3,    /* a fixed per-cell or per-mesh capacity was exceeded (see mm_last_error) */
+  MM_EDEGENERATE = -4,  /* tessellation failed: incomplete cell, asymmetric faces or box too small */
+  MM_ENONFINITE = -5,   /* a state became NaN or infinite */
+  MM_EHIP = -6,         /* a HIP runtime call failed */
+  MM_ESTATE = -7        /* call out of order, e.g. mm_gradients before any mm_tessellate */
+} mm_status;
+
+enum { MM_FP64 = 0, MM_MIXED = 1 };
+enum { MM_HLLC = 0 };
+
+/* Scheme parameters.  Defaults (mm_default_params): gamma = 5/3, cfl = 0.3,
+ * eta = 1 (Lagrangian mesh, Sec. 4.2), chi = 1 and zeta = 0.25 (roundness
+ * correction, Sec. 4.2), theta = 0.49 (Duffell-MacFadyen factor, Sec. 4.1
+ * and Sec. 5.1; theta <= 0 switches it off), rho_floor = 1e-12,
+ * p_floor = 1e-14 (floors, Sec. 4.1), limit_mask = 3. */
+typedef struct {
+  double box[3];             /* periodic box lengths L (Sec. 4.4: periodic boundaries) */
+  double gamma;              /* ideal-gas adiabatic index */
+  double cfl;                /* CFL coefficient of the per-cell timestep (Sec. 4.2) */
+  double eta;                /* mesh velocity w = eta v + dw (Sec. 4.2) */
+  double chi;                /* roundness correction speed in units of c_s (Sec. 4.2) */
+  double zeta;               /* roundness correction distance in units of R (Sec. 4.2) */
+  double theta;              /* Duffell-MacFadyen limiter parameter (Sec. 4.1) */
+  double rho_floor;          /* density floor (Sec. 4.1) */
+  double p_floor;            /* pressure floor (Sec. 4.1) */
+  int32_t precision;         /* MM_FP64, or MM_MIXED: gradients, predictor, reconstruction and
+                                Riemann solves in float; geometry and charge sums in double */
+  int32_t riemann;           /* MM_HLLC */
+  int32_t limit_mask;        /* S10 limiter: bit 0 on the time-n gradient, bit 1 on the half-step one */
+  int32_t predictor_frame;   /* 0: rate following the generator, -div F + w . grad U; 1: Eulerian -div F */
+} mm_params;
+
+/* Per-step report, filled by mm_step (and partly by mm_tessellate). */
+typedef struct {
+  double dt;                 /* timestep used: min(dt_max, dt_cfl) */
+  double dt_cfl;             /* CFL timestep min_i dt_i (Sec. 4.2) */
+  int64_t n_faces;           /* unique faces of the tessellation */
+  int32_t max_faces_cell;    /* largest number of faces of one cell */
+  int32_t deferred_cells;    /* cells re-run with a wider neighbour stencil */
+  int64_t floor_hits[4];     /* floors fired: [0] cell states at the start, [1] half-step states,
+                                [2] face states, [3] charges after the update (Sec. 4.1) */
+  int32_t flags;             /* internal failure bits (0 when the step succeeded) */
+  int32_t reserved;
+} mm_step_info;
+
+/* Device views of the current tessellation, in the library's internal
+ * (bucket-sorted) cell order.  Valid until the next mm_tessellate or
+ * mm_step on the context; read-only for the caller. */
+typedef struct {
+  int64_t n;                 /* cells */
+  int64_t n_faces;           /* unique faces */
+  const int32_t *perm;       /* dev [n]: internal cell s holds caller point perm[s] */
+  const double *pos;         /* dev [n][3]: generator positions, internal order */
+  const double *geo;         /* dev [n][4]: volume V, then centroid minus generator (3) */
+  const void *faces;         /* dev [n_faces] records of 48 bytes: int32 i, j (internal cells, i the
+                                owner), int32 image code of j as (kx+1) + 3(ky+1) + 9(kz+1), int32 pad,
+                                double area A, double[3] face centroid minus r_i */
+} mm_mesh_view;
+
+/* Fills *p with the defaults listed above and box = (1, 1, 1). */
+void mm_default_params(mm_params *p);
+
+/* Creates a context on the current HIP device.  n_capacity bounds n in every
+ * later call; face_capacity bounds the number of unique faces (0 selects
+ * 12 n_capacity, enough for jittered lattices (about 8 per cell) and Poisson
+ * points (about 7.8 per cell)).  hip_stream is a hipStream_t (NULL: the null
+ * stream).  *out receives the context.  Errors: MM_EINVAL, MM_ENOMEM, MM_EHIP. */
+mm_status mm_create(mm_ctx **out, const mm_params *p, int64_t n_capacity, int64_t face_capacity,
+                    void *hip_stream);
+
+/* Releases the context and all its device memory (after waiting for its stream). */
+mm_status mm_destroy(mm_ctx *ctx);
+
+/* Replaces the scheme parameters (box, gamma, ...).  precision may not change. */
+mm_status mm_set_params(mm_ctx *ctx, const mm_params *p);
+
+/* Periodic Voronoi tessellation of n generators (Sec. 3: each cell is cut
+ * from the box around its generator by the bisector planes of the
+ * neighbours, nearest first, until no farther neighbour can cut it).
+ * pos: dev [n][3], each coordinate in [0, L).  Keeps the mesh in the
+ * context for mm_mesh_view/mm_mesh_export/mm_init_charges/mm_cell_state/
+ * mm_gradients/mm_predict/mm_fluxes.  info (host, may be NULL) receives
+ * n_faces, max_faces_cell and deferred_cells.  Waits for the stream.
+ * Errors: MM_EINVAL (bad n or positions), MM_ECAPACITY, MM_EDEGENERATE. */
+mm_status mm_tessellate(mm_ctx *ctx, int64_t n, const double *pos, mm_step_info *info);
+
+/* Device views of the last tessellation (see mm_mesh_view). */
+mm_status mm_get_mesh_view(const mm_ctx *ctx, mm_mesh_view *out);
+
+/* Copies the last tessellation out in caller order (all dev, caller-owned):
+ * V [n], centroid [n][3] (absolute), and the unique faces, each once:
+ * face_i, face_j [face_cap] caller indices (face_i is the owner side),
+ * face_code [face_cap] periodic image of j, face_A [face_cap],
+ * face_f [face_cap][3] absolute face centroid r_i + (f - r_i), which may lie
+ * outside the box.  *n_faces (host) receives the count; MM_ECAPACITY if it
+ * exceeds face_cap (nothing is written then).  Any output may be NULL. */
+mm_status mm_mesh_export(mm_ctx *ctx, double *V, double *centroid, int64_t face_cap, int32_t *face_i,
+                         int32_t *face_j, int32_t *face_code, double *face_A, double *face_f,
+                         int64_t *n_faces);
+
+/* Charges from primitives after a tessellation (Sec. 4.3: the cell holds the
+ * primitive state of its generator): Q_i = U(prim_i) V_i.
+ * prim: dev [n][5] double, Q: dev [n][5] double. */
+mm_status mm_init_charges(mm_ctx *ctx, const double *prim, double *Q);
+
+/* Cell state at the start of a step (Sec. 4; Sec. 4.1 floors; Sec. 4.2):
+ * U = Q/V with floors, mesh velocities w and dt_cfl = min_i dt_i.
+ * Q: dev [n][5] double; U: dev [n][5] (precision type); w: dev [n][3]
+ * double; dt_cfl, floor_hits: host (may be NULL).  Waits for the stream. */
+mm_status mm_cell_state(mm_ctx *ctx, const double *Q, void *U, double *w, double *dt_cfl,
+                        int64_t *floor_hits);
+
+/* Least-squares gradients about the cell centroids, optionally S10-limited
+ * (Sec. 4.1).  U: dev [n][5], grad: dev [n][5][3], both of the precision
+ * type.  limit: 0 or 1. */
+mm_status mm_gradients(mm_ctx *ctx, const void *U, void *grad, int32_t limit);
+
+/* Half-step predictor (Sec. 4.1): U_half = U + dt/2 (-div F(U, grad U)
+ * + w . grad U), then floors.  U, grad, U_half of the precision type,
+ * w: dev [n][3] double. */
+mm_status mm_predict(mm_ctx *ctx, const void *U, const void *grad, const double *w, double dt,
+                     void *U_half);
+
+/* Face fluxes and their sum per cell (Sec. 4, items 1-5 and eq. "time
+ * evolution"; Sec. 4.1 reconstruction): for each face, the face velocity,
+ * limited reconstruction of U_half from both sides to the face centre,
+ * face floors, HLLC in the face frame, boost back; then
+ * dQ_i = - sum_faces dt A F (F from i toward its neighbour).
+ * U_half [n][5], grad_half [n][5][3] of the precision type; w [n][3] and
+ * dQ [n][5] double; all dev. */
+mm_status mm_fluxes(mm_ctx *ctx, const void *U_half, const void *grad_half, const double *w, double dt,
+                    double *dQ);
+
+/* One whole step (Sec. 2 outline): tessellate pos, cell states, timestep
+ * dt = min(dt_max, dt_cfl), gradient, predictor, half-step gradient, face
+ * fluxes, update of Q with floors, drift pos += w dt with periodic wrap.
+ * pos: dev [n][3] in/out; w: dev [n][3] out (the mesh velocities used);
+ * Q: dev [n][5] in/out; info: host out (may be NULL).  Waits for the
+ * stream once, at the end. */
+mm_status mm_step(mm_ctx *ctx, int64_t n, double *pos, double *w, double *Q, double dt_max,
+                  mm_step_info *info);
+
+/* Message for the last error on this context (static storage of the context). */
+const char *mm_last_error(const mm_ctx *ctx);
+
+/* Library version string. */
+const char *mm_version(void);
+
+/* Stage timing of mm_step, for profiling.  When enabled, mm_step records HIP
+ * events on the context stream around its stages: [0] sort, [1] cell
+ * construction, [2] mesh assembly, [3] cell states, [4] gradient + predictor,
+ * [5] half-step gradient, [6] face fluxes, [7] update + drift.
+ * mm_get_stage_ms writes up to n_stages milliseconds of the last step. */
+mm_status mm_set_stage_timing(mm_ctx *ctx, int32_t enable);
+mm_status mm_get_stage_ms(const mm_ctx *ctx, double *ms, int32_t n_stages);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

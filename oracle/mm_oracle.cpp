@@ -34,7 +34,9 @@
 //           floors paragraph; values are not given by the paper).
 //   R-box   the starting cell is the box r_i +- L/2, the exact Voronoi cell
 //           of i's own periodic images (Sec. 3, "large rectangular cell").
-//   R-area  faces with area <= 1e-14 V^(2/3) are dropped.
+//   R-area  a face is kept iff its computed area is positive.  (A threshold
+//           relative to each cell's own volume would differ between the two
+//           cells of a face and keep a face on one side only.)
 //   R-dt    dt = min(dt_max, min_i dt_i); no power-of-two rungs (Sec. 4.2).
 //   R-w     the mesh velocity of a step is evaluated from the state at the
 //           start of the step and used both for the face velocities and
@@ -260,7 +262,7 @@ void finish_cell(const Poly& P, CellOut& out) {
       A += a;
       S = S + (a / 3.0) * (F.v[0] + F.v[k] + F.v[k + 1]);
     }
-    if (!(A > 0)) { out.status = 1; continue; }
+    if (!(A > 0)) continue;   // R-area: a plane that only touches the cell
     const V3 f = (1.0 / A) * S;
     const double dist = 0.5 * std::sqrt(norm2(pl.d));   // generator-to-face distance
     // Pyramid with apex at the generator: volume A*dist/3, centroid 3/4 of
@@ -286,11 +288,9 @@ void finish_cell(const Poly& P, CellOut& out) {
   size_t half_edges = 0;
   for (const Face& F : P.faces) half_edges += F.v.size();
   out.nvert = (int)(2 + half_edges / 2 - P.faces.size());
-  // R-area: drop faces of negligible area; order faces by (j, image code).
-  const double amin = 1e-14 * std::pow(V, 2.0 / 3.0);
+  // Faces ordered by (j, image code).
   std::vector<size_t> idx;
-  for (size_t q = 0; q < fg.size(); ++q)
-    if (fg[q].A > amin) idx.push_back(q);
+  for (size_t q = 0; q < fg.size(); ++q) idx.push_back(q);
   std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
     const Plane& pa = P.planes[fg[a].plane];
     const Plane& pb = P.planes[fg[b].plane];

@@ -1,0 +1,637 @@
+// Finite-volume kernels of the moving-mesh step (Sec. 4 of the paper), in
+// the library's internal (bucket-sorted) cell order.  State arrays are
+// cell-major rows (U [n][5], gradients [n][5][3]) so a gather of one
+// neighbour reads one contiguous row.  R is double (MM_FP64) or float
+// (MM_MIXED: state arithmetic in float, geometry and charge sums in double).
+#include <algorithm>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+__device__ inline double dt_of(const DevStatus* src, double dt_fixed) {
+  if (!src) return dt_fixed;
+  const double d = __longlong_as_double((long long)src->dt_bits);
+  return fmin(d, dt_fixed);
+}
+
+// Sum of one integer per thread over the block, added to *dst by thread 0.
+__device__ void block_add(unsigned long long v, unsigned long long* dst) {
+  __shared__ unsigned long long red[kThreads / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
+    if (t) atomicAdd(dst, t);
+  }
+}
+
+// Floors of Sec. 4.1 on conserved densities: a density below the floor is
+// raised keeping velocity and pressure; a pressure below the floor is raised
+// keeping density and velocity.  Returns 1 if any floor fired.
+template <typename T>
+__device__ inline int apply_floors(T U[5], T g1, T rho_floor, T p_floor) {
+  int hit = 0;
+  const T rho = U[0];
+  if (rho < rho_floor) {
+    T vx = 0, vy = 0, vz = 0, P = p_floor;
+    if (rho > T(0)) {
+      vx = U[1] / rho;
+      vy = U[2] / rho;
+      vz = U[3] / rho;
+      P = g1 * (U[4] - T(0.5) * (U[1] * vx + U[2] * vy + U[3] * vz));
+    }
+    P = P > p_floor ? P : p_floor;
+    U[0] = rho_floor;
+    U[1] = rho_floor * vx;
+    U[2] = rho_floor * vy;
+    U[3] = rho_floor * vz;
+    U[4] = P / g1 + T(0.5) * rho_floor * (vx * vx + vy * vy + vz * vz);
+    hit = 1;
+  }
+  const T ke = T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0];
+  const T P = g1 * (U[4] - ke);
+  if (P < p_floor) {
+    U[4] = p_floor / g1 + ke;
+    hit = 1;
+  }
+  return hit;
+}
+
+// Time derivative of the state from its gradient (Sec. 4.1): -div F(U) by
+// the chain rule, plus w . grad U when following the generator.
+// g[3q + d] = d U_q / d x_d.
+template <typename T>
+__device__ inline void state_rate(const T U[5], const T g[15], const T wv[3], T g1, bool moving, T out[5]) {
+  const T rho = U[0];
+  const T v[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+  const T vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  const T P = g1 * (U[4] - T(0.5) * rho * vv);
+  T dP[3], divv = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    dP[d] = g1 * (g[12 + d] - (v[0] * g[3 + d] + v[1] * g[6 + d] + v[2] * g[9 + d]) + T(0.5) * vv * g[d]);
+    divv += (g[3 * (1 + d) + d] - v[d] * g[d]) / rho;
+  }
+  T div[5];
+  div[0] = g[3 + 0] + g[6 + 1] + g[9 + 2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    div[1 + a] = v[0] * g[3 * (1 + a)] + v[1] * g[3 * (1 + a) + 1] + v[2] * g[3 * (1 + a) + 2] + U[1 + a] * divv +
+                 dP[a];
+  div[4] = v[0] * (g[12] + dP[0]) + v[1] * (g[13] + dP[1]) + v[2] * (g[14] + dP[2]) + (U[4] + P) * divv;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    T adv = 0;
+    if (moving) adv = wv[0] * g[3 * q] + wv[1] * g[3 * q + 1] + wv[2] * g[3 * q + 2];
+    out[q] = adv - div[q];
+  }
+}
+
+// Euler flux along unit normal n of a face-frame state (rho, v, P).
+template <typename T>
+__device__ inline void euler_flux(T rho, const T v[3], T P, const T n[3], T g1, T F[5]) {
+  const T u = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
+  const T E = P / g1 + T(0.5) * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  F[0] = rho * u;
+  F[1] = rho * u * v[0] + P * n[0];
+  F[2] = rho * u * v[1] + P * n[1];
+  F[3] = rho * u * v[2] + P * n[2];
+  F[4] = (E + P) * u;
+}
+
+// Flux across a face with unit normal n moving with velocity wt (Sec. 4,
+// items 3-5): both lab-frame states are boosted to the face frame, HLLC with
+// Davis wave-speed bounds gives the face-frame flux, and the flux is boosted
+// back (mass flux unchanged; momentum + wt F_rho; energy + wt.F_m +
+// |wt|^2/2 F_rho).
+template <typename T>
+__device__ inline void moving_hllc(const T UL[5], const T UR[5], const T n[3], const T wt[3], T gamma, T F[5]) {
+  const T g1 = gamma - T(1);
+  T vL[3], vR[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vL[a] = UL[1 + a] / UL[0];
+    vR[a] = UR[1 + a] / UR[0];
+  }
+  const T PL = g1 * (UL[4] - T(0.5) * (UL[1] * vL[0] + UL[2] * vL[1] + UL[3] * vL[2]));
+  const T PR = g1 * (UR[4] - T(0.5) * (UR[1] * vR[0] + UR[2] * vR[1] + UR[3] * vR[2]));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vL[a] -= wt[a];
+    vR[a] -= wt[a];
+  }
+  const T rL = UL[0], rR = UR[0];
+  const T uL = vL[0] * n[0] + vL[1] * n[1] + vL[2] * n[2];
+  const T uR = vR[0] * n[0] + vR[1] * n[1] + vR[2] * n[2];
+  const T cL = sqrt(gamma * PL / rL), cR = sqrt(gamma * PR / rR);
+  const T SL = fmin(uL - cL, uR - cR);
+  const T SR = fmax(uL + cL, uR + cR);
+  T Ff[5];
+  if (SL >= T(0)) {
+    euler_flux(rL, vL, PL, n, g1, Ff);
+  } else if (SR < T(0)) {
+    euler_flux(rR, vR, PR, n, g1, Ff);
+  } else {
+    const T Ss = (PR - PL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
+    const bool left = Ss >= T(0);
+    const T rK = left ? rL : rR, uK = left ? uL : uR, PK = left ? PL : PR, SK = left ? SL : SR;
+    const T* vK = left ? vL : vR;
+    T FK[5];
+    euler_flux(rK, vK, PK, n, g1, FK);
+    const T EK = PK / g1 + T(0.5) * rK * (vK[0] * vK[0] + vK[1] * vK[1] + vK[2] * vK[2]);
+    const T fac = rK * (SK - uK) / (SK - Ss);
+    const T du = Ss - uK;
+    Ff[0] = FK[0] + SK * (fac - rK);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Ff[1 + a] = FK[1 + a] + SK * (fac * (vK[a] + du * n[a]) - rK * vK[a]);
+    Ff[4] = FK[4] + SK * (fac * (EK / rK + du * (Ss + PK / (rK * (SK - uK)))) - EK);
+  }
+  const T w2 = wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2];
+  F[0] = Ff[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[1 + a] = Ff[1 + a] + wt[a] * Ff[0];
+  F[4] = Ff[4] + wt[0] * Ff[1] + wt[1] * Ff[2] + wt[2] * Ff[3] + T(0.5) * w2 * Ff[0];
+}
+
+// Duffell-MacFadyen factor on one face (Sec. 4.1): the extrapolation D from
+// the centroid to the face may not exceed theta times the jump dU to the
+// neighbour, nor oppose its sign.
+template <typename T>
+__device__ inline T dm_factor(T theta, T dU, T D) {
+  if (theta <= T(0) || D == T(0)) return T(1);
+  T b = theta * dU / D;
+  b = b > T(0) ? b : T(0);
+  return b < T(1) ? b : T(1);
+}
+
+// ---------------------------------------------------------------------------
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_cell_state(HydroParams hp, int64_t n, const double* __restrict__ Qc,
+                                                         const int32_t* __restrict__ perm,
+                                                         const double* __restrict__ geo, double* __restrict__ Qs,
+                                                         R* __restrict__ U, double* __restrict__ w, DevStatus* st) {
+  __shared__ double red[kThreads / 64];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double dti = 1e300;
+  int hit = 0, bad = 0;
+  if (s < n) {
+    const int64_t q = perm[s];
+    double Q[5], u[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Q[k] = Qc[5 * q + k];
+    if (Qs) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) Qs[5 * s + k] = Q[k];
+    }
+    const double V = geo[4 * s];
+    const double crx = geo[4 * s + 1], cry = geo[4 * s + 2], crz = geo[4 * s + 3];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) u[k] = Q[k] / V;
+    const double g1 = hp.gamma - 1.0;
+    hit = apply_floors(u, g1, hp.rho_floor, hp.p_floor);
+    // Mesh velocity and timestep (Sec. 4.2).
+    const double rho = u[0];
+    const double vx = u[1] / rho, vy = u[2] / rho, vz = u[3] / rho;
+    const double P = g1 * (u[4] - 0.5 * (u[1] * vx + u[2] * vy + u[3] * vz));
+    const double cs = sqrt(hp.gamma * P / rho);
+    const double Rr = cbrt(3.0 * V / (4.0 * kPi));
+    const double dn = sqrt(crx * crx + cry * cry + crz * crz);
+    double ramp;
+    if (dn < 0.9 * hp.zeta * Rr) ramp = 0.0;
+    else if (dn <= 1.1 * hp.zeta * Rr) ramp = (dn - 0.9 * hp.zeta * Rr) / (0.2 * hp.zeta * Rr);
+    else ramp = 1.0;
+    double dwx = 0.0, dwy = 0.0, dwz = 0.0;
+    if (dn > 0.0 && ramp > 0.0) {
+      dwx = hp.chi * cs * ramp * crx / dn;
+      dwy = hp.chi * cs * ramp * cry / dn;
+      dwz = hp.chi * cs * ramp * crz / dn;
+    }
+    const double wx = hp.eta * vx + dwx, wy = hp.eta * vy + dwy, wz = hp.eta * vz + dwz;
+    const double rx = vx - wx, ry = vy - wy, rz = vz - wz;
+    dti = hp.cfl * Rr / (cs + sqrt(rx * rx + ry * ry + rz * rz));
+    w[3 * s] = wx;
+    w[3 * s + 1] = wy;
+    w[3 * s + 2] = wz;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) U[5 * s + k] = (R)u[k];
+    if (!(dti > 0.0 && dti < 1e300)) {
+      bad = 1;
+      dti = 1e300;
+    }
+  }
+  double m = dti;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) t = fmin(t, red[k]);
+    if (t < 1e300) atomicMin(&st->dt_bits, (unsigned long long)__double_as_longlong(t));
+  }
+  block_add((unsigned long long)hit, &st->floor_hits[0]);
+  if (bad) {
+    atomicOr(&st->flags, F_NONFINITE);
+    atomicMin(&st->bad_cell, (int)s);
+  }
+}
+
+// Least-squares gradient about the centroids with the S10 limiter (Sec. 4.1);
+// with U_half set, the half-step predictor is applied in the same pass.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_gradient(HydroParams hp, int64_t n, const R* __restrict__ U,
+                                                       const unsigned long long* __restrict__ off,
+                                                       const NbrEntry* __restrict__ nbr,
+                                                       const double* __restrict__ minv, int limit, R* __restrict__ G,
+                                                       const double* __restrict__ w, const DevStatus* dt_src,
+                                                       double dt_fixed, R* __restrict__ Uh, DevStatus* st) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int hit = 0;
+  if (s < n) {
+    const int64_t e0 = (int64_t)(off[s] >> 32), e1 = (int64_t)(off[s + 1] >> 32);
+    R ui[5], umax[5], umin[5], b[15];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      ui[q] = U[5 * s + q];
+      umax[q] = ui[q];
+      umin[q] = ui[q];
+    }
+#pragma unroll
+    for (int k = 0; k < 15; ++k) b[k] = R(0);
+    for (int64_t e = e0; e < e1; ++e) {
+      const NbrEntry E = nbr[e];
+      const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2], wg = (R)E.wgt;
+      const R* uo = U + 5 * (int64_t)E.o;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const R v = uo[q];
+        const R t = wg * (v - ui[q]);
+        b[3 * q] += t * dx;
+        b[3 * q + 1] += t * dy;
+        b[3 * q + 2] += t * dz;
+        umax[q] = v > umax[q] ? v : umax[q];
+        umin[q] = v < umin[q] ? v : umin[q];
+      }
+    }
+    const double* mi = minv + 6 * s;
+    const R m00 = (R)mi[0], m01 = (R)mi[1], m02 = (R)mi[2], m11 = (R)mi[3], m12 = (R)mi[4], m22 = (R)mi[5];
+    R g[15];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const R bx = b[3 * q], by = b[3 * q + 1], bz = b[3 * q + 2];
+      g[3 * q] = m00 * bx + m01 * by + m02 * bz;
+      g[3 * q + 1] = m01 * bx + m11 * by + m12 * bz;
+      g[3 * q + 2] = m02 * bx + m12 * by + m22 * bz;
+    }
+    if (limit) {
+      R alpha[5] = {R(1), R(1), R(1), R(1), R(1)};
+      for (int64_t e = e0; e < e1; ++e) {
+        const NbrEntry E = nbr[e];
+        const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const R D = g[3 * q] * dx + g[3 * q + 1] * dy + g[3 * q + 2] * dz;
+          R psi = R(1);
+          if (D > R(0)) psi = (umax[q] - ui[q]) / D;
+          else if (D < R(0)) psi = (umin[q] - ui[q]) / D;
+          alpha[q] = psi < alpha[q] ? psi : alpha[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        g[3 * q] *= alpha[q];
+        g[3 * q + 1] *= alpha[q];
+        g[3 * q + 2] *= alpha[q];
+      }
+    }
+    if (G) {
+#pragma unroll
+      for (int k = 0; k < 15; ++k) G[15 * s + k] = g[k];
+    }
+    if (Uh) {
+      const double dt = dt_of(dt_src, dt_fixed);
+      const R wv[3] = {(R)w[3 * s], (R)w[3 * s + 1], (R)w[3 * s + 2]};
+      R rt[5], uh[5];
+      state_rate(ui, g, wv, (R)(hp.gamma - 1.0), hp.predictor_frame == 0, rt);
+      const R hdt = (R)(0.5 * dt);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) uh[q] = ui[q] + hdt * rt[q];
+      hit = apply_floors(uh, (R)(hp.gamma - 1.0), (R)hp.rho_floor, (R)hp.p_floor);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) Uh[5 * s + q] = uh[q];
+    }
+  }
+  if (Uh) block_add((unsigned long long)hit, &st->floor_hits[1]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_predict(HydroParams hp, int64_t n, const R* __restrict__ U,
+                                                      const R* __restrict__ G, const double* __restrict__ w,
+                                                      const DevStatus* dt_src, double dt_fixed, R* __restrict__ Uh,
+                                                      DevStatus* st) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int hit = 0;
+  if (s < n) {
+    R ui[5], g[15], rt[5], uh[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) ui[q] = U[5 * s + q];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) g[k] = G[15 * s + k];
+    const R wv[3] = {(R)w[3 * s], (R)w[3 * s + 1], (R)w[3 * s + 2]};
+    const double dt = dt_of(dt_src, dt_fixed);
+    state_rate(ui, g, wv, (R)(hp.gamma - 1.0), hp.predictor_frame == 0, rt);
+    const R hdt = (R)(0.5 * dt);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) uh[q] = ui[q] + hdt * rt[q];
+    hit = apply_floors(uh, (R)(hp.gamma - 1.0), (R)hp.rho_floor, (R)hp.p_floor);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Uh[5 * s + q] = uh[q];
+  }
+  block_add((unsigned long long)hit, &st->floor_hits[1]);
+}
+
+// One thread per unique face (Sec. 4 items 1-5, Sec. 4.1 reconstruction):
+// phi = dt A F, F the lab-frame flux from the owner i toward j.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_flux(HydroParams hp, int64_t nf_host,
+                                                   const unsigned long long* __restrict__ nf_dev,
+                                                   const Face* __restrict__ faces,
+                                                   const double* __restrict__ spos, const double* __restrict__ geo,
+                                                   const R* __restrict__ Uh, const R* __restrict__ Gh,
+                                                   const double* __restrict__ w, const DevStatus* dt_src,
+                                                   double dt_fixed, R* __restrict__ phi, DevStatus* st) {
+  const int64_t nf = nf_dev ? std::min<int64_t>((int64_t)*nf_dev, nf_host) : nf_host;
+  int hit = 0;
+  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+    const Face F = faces[f];
+    const int64_t i = F.i, j = F.j;
+    int kx, ky, kz;
+    decode(F.code, kx, ky, kz);
+    // Geometry in double: r_j + s - r_i, face centre and centroid offsets.
+    const double drx = (spos[3 * j] + kx * hp.L[0]) - spos[3 * i];
+    const double dry = (spos[3 * j + 1] + ky * hp.L[1]) - spos[3 * i + 1];
+    const double drz = (spos[3 * j + 2] + kz * hp.L[2]) - spos[3 * i + 2];
+    const double len = sqrt(drx * drx + dry * dry + drz * drz);
+    const double nx = drx / len, ny = dry / len, nz = drz / len;
+    const double wix = w[3 * i], wiy = w[3 * i + 1], wiz = w[3 * i + 2];
+    const double wjx = w[3 * j], wjy = w[3 * j + 1], wjz = w[3 * j + 2];
+    // Face velocity (Sec. 4 item 1): bisector's normal speed at the face
+    // centre plus the mean generator velocity.
+    const double sn = ((wix - wjx) * (F.f[0] - 0.5 * drx) + (wiy - wjy) * (F.f[1] - 0.5 * dry) +
+                       (wiz - wjz) * (F.f[2] - 0.5 * drz)) / len;
+    const R wt[3] = {(R)(sn * nx + 0.5 * (wix + wjx)), (R)(sn * ny + 0.5 * (wiy + wjy)),
+                     (R)(sn * nz + 0.5 * (wiz + wjz))};
+    const R nrm[3] = {(R)nx, (R)ny, (R)nz};
+    // f - c_i and f - (c_j + s), with f and c relative to the generators.
+    const R fi[3] = {(R)(F.f[0] - geo[4 * i + 1]), (R)(F.f[1] - geo[4 * i + 2]), (R)(F.f[2] - geo[4 * i + 3])};
+    const R fj[3] = {(R)(F.f[0] - drx - geo[4 * j + 1]), (R)(F.f[1] - dry - geo[4 * j + 2]),
+                     (R)(F.f[2] - drz - geo[4 * j + 3])};
+    const R theta = (R)hp.theta;
+    R UL[5], UR[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const R ui = Uh[5 * i + q], uj = Uh[5 * j + q];
+      const R* gi = Gh + 15 * i + 3 * q;
+      const R* gj = Gh + 15 * j + 3 * q;
+      const R Di = gi[0] * fi[0] + gi[1] * fi[1] + gi[2] * fi[2];
+      const R Dj = gj[0] * fj[0] + gj[1] * fj[1] + gj[2] * fj[2];
+      UL[q] = ui + dm_factor(theta, uj - ui, Di) * Di;
+      UR[q] = uj + dm_factor(theta, ui - uj, Dj) * Dj;
+    }
+    const R g1 = (R)(hp.gamma - 1.0);
+    hit += apply_floors(UL, g1, (R)hp.rho_floor, (R)hp.p_floor);
+    hit += apply_floors(UR, g1, (R)hp.rho_floor, (R)hp.p_floor);
+    R Fx[5];
+    moving_hllc(UL, UR, nrm, wt, (R)hp.gamma, Fx);
+    const R scale = (R)(dt_of(dt_src, dt_fixed) * F.A);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) phi[5 * f + q] = scale * Fx[q];
+  }
+  block_add((unsigned long long)hit, &st->floor_hits[2]);
+}
+
+// Per-cell sum of the face fluxes through the CSR list in a fixed order:
+// the owner side loses phi, the neighbour side gains it (Sec. 4, eq. "time
+// evolution").  Accumulation in double.
+template <typename R>
+__device__ inline void cell_flux_sum(int64_t s, const unsigned long long* off, const int32_t* csr, const R* phi,
+                                     double acc[5]) {
+  const int64_t e0 = (int64_t)(off[s] >> 32), e1 = (int64_t)(off[s + 1] >> 32);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) acc[q] = 0.0;
+  for (int64_t e = e0; e < e1; ++e) {
+    const int32_t cf = csr[e];
+    const int64_t fid = cf & 0x7fffffff;
+    const double sg = cf < 0 ? 1.0 : -1.0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc[q] += sg * (double)phi[5 * fid + q];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_update(HydroParams hp, int64_t n, const unsigned long long* __restrict__ off,
+                                                     const int32_t* __restrict__ csr, const R* __restrict__ phi,
+                                                     const double* __restrict__ geo, const int32_t* __restrict__ perm,
+                                                     const double* __restrict__ Qs, double* __restrict__ Qc,
+                                                     const double* __restrict__ spos, const double* __restrict__ w,
+                                                     double* __restrict__ posc, double* __restrict__ wc,
+                                                     const DevStatus* dt_src, double dt_max, DevStatus* st) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int hit = 0, bad = 0;
+  if (s < n) {
+    double acc[5], Q[5];
+    cell_flux_sum(s, off, csr, phi, acc);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Q[q] = Qs[5 * s + q] + acc[q];
+    // Floors at the cell centre after the step, with the time-n volume.
+    const double V = geo[4 * s];
+    double u[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) u[q] = Q[q] / V;
+    if (apply_floors(u, hp.gamma - 1.0, hp.rho_floor, hp.p_floor)) {
+      hit = 1;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) Q[q] = u[q] * V;
+    }
+    const int64_t c = perm[s];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      Qc[5 * c + q] = Q[q];
+      if (!isfinite(Q[q])) bad = 1;
+    }
+    // Drift by the full step with periodic wrap.
+    const double dt = dt_of(dt_src, dt_max);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double wa = w[3 * s + a];
+      double x = spos[3 * s + a] + wa * dt;
+      if (x < 0.0) x += hp.L[a];
+      if (x >= hp.L[a]) x -= hp.L[a];
+      posc[3 * c + a] = x;
+      wc[3 * c + a] = wa;
+    }
+  }
+  block_add((unsigned long long)hit, &st->floor_hits[3]);
+  if (bad) {
+    atomicOr(&st->flags, F_NONFINITE);
+    atomicMin(&st->bad_cell, (int)s);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_accumulate(int64_t n, const unsigned long long* __restrict__ off,
+                                                         const int32_t* __restrict__ csr, const R* __restrict__ phi,
+                                                         const int32_t* __restrict__ perm, double* __restrict__ dQc) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  double acc[5];
+  cell_flux_sum(s, off, csr, phi, acc);
+  const int64_t c = perm[s];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) dQc[5 * c + q] = acc[q];
+}
+
+template <typename R>
+__global__ void k_gather_rows(const R* __restrict__ src, const int32_t* __restrict__ perm, int64_t n, int width,
+                              R* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * width) return;
+  const int64_t s = t / width, k = t - s * width;
+  dst[t] = src[(int64_t)perm[s] * width + k];
+}
+
+template <typename R>
+__global__ void k_scatter_rows(const R* __restrict__ src, const int32_t* __restrict__ perm, int64_t n, int width,
+                               R* __restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * width) return;
+  const int64_t s = t / width, k = t - s * width;
+  dst[(int64_t)perm[s] * width + k] = src[t];
+}
+
+// Charges from primitives (Sec. 4.3): Q = (rho, rho v, P/(gamma-1) + rho v^2/2) V.
+__global__ void k_init_charges(HydroParams hp, int64_t n, const double* __restrict__ prim,
+                               const int32_t* __restrict__ perm, const double* __restrict__ geo,
+                               double* __restrict__ Q) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t c = perm[s];
+  const double V = geo[4 * s];
+  const double rho = prim[5 * c], vx = prim[5 * c + 1], vy = prim[5 * c + 2], vz = prim[5 * c + 3],
+               P = prim[5 * c + 4];
+  const double ke = 0.5 * rho * (vx * vx + vy * vy + vz * vz);
+  Q[5 * c] = rho * V;
+  Q[5 * c + 1] = rho * vx * V;
+  Q[5 * c + 2] = rho * vy * V;
+  Q[5 * c + 3] = rho * vz * V;
+  Q[5 * c + 4] = (P / (hp.gamma - 1.0) + ke) * V;
+}
+
+}  // namespace
+
+template <typename R>
+void launch_cell_state(const HydroParams& hp, int64_t n, const double* Q_caller, const int32_t* perm,
+                       const double* geo, double* Qs, R* U, double* w, DevStatus* st_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_cell_state<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, Q_caller, perm,
+                     geo, Qs, U, w, st_dev);
+}
+
+template <typename R>
+void launch_gradient(const HydroParams& hp, int64_t n, const R* U, const unsigned long long* csr_off,
+                     const NbrEntry* nbr, const double* minv, int limit, R* G, const double* w,
+                     const DevStatus* dt_src, double dt_fixed, R* U_half, DevStatus* st_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_gradient<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, U, csr_off, nbr,
+                     minv, limit, G, w, dt_src, dt_fixed, U_half, st_dev);
+}
+
+template <typename R>
+void launch_predict(const HydroParams& hp, int64_t n, const R* U, const R* G, const double* w,
+                    const DevStatus* dt_src, double dt_fixed, R* U_half, DevStatus* st_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_predict<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, U, G, w, dt_src,
+                     dt_fixed, U_half, st_dev);
+}
+
+template <typename R>
+void launch_flux(const HydroParams& hp, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
+                 const double* spos, const double* geo, const R* Uh, const R* Gh, const double* w,
+                 const DevStatus* dt_src, double dt_fixed, R* phi, DevStatus* st_dev, hipStream_t st) {
+  if (nf_host <= 0) return;
+  // Grid-stride: with a device count the grid only needs to cover the bound.
+  const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(nf_host, kThreads), 1 << 16);
+  hipLaunchKernelGGL(k_flux<R>, dim3(blocks), dim3(kThreads), 0, st, hp, nf_host, nf_dev, faces, spos, geo, Uh, Gh,
+                     w, dt_src, dt_fixed, phi, st_dev);
+}
+
+template <typename R>
+void launch_update(const HydroParams& hp, int64_t n, const unsigned long long* csr_off, const int32_t* csr,
+                   const R* phi, const double* geo, const int32_t* perm, const double* Qs, double* Q_caller,
+                   const double* spos, const double* w, double* pos_caller, double* w_caller,
+                   const DevStatus* dt_src, double dt_max, DevStatus* st_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_update<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, csr_off, csr, phi, geo,
+                     perm, Qs, Q_caller, spos, w, pos_caller, w_caller, dt_src, dt_max, st_dev);
+}
+
+template <typename R>
+void launch_accumulate(int64_t n, const unsigned long long* csr_off, const int32_t* csr, const R* phi,
+                       const int32_t* perm, double* dQ_caller, hipStream_t st) {
+  hipLaunchKernelGGL(k_accumulate<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, csr_off, csr, phi,
+                     perm, dQ_caller);
+}
+
+template <typename R>
+void launch_gather_rows(const R* src_caller, const int32_t* perm, int64_t n, int width, R* dst, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows<R>, dim3(blocks_for(n * width, kThreads)), dim3(kThreads), 0, st, src_caller, perm,
+                     n, width, dst);
+}
+
+template <typename R>
+void launch_scatter_rows(const R* src, const int32_t* perm, int64_t n, int width, R* dst_caller, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scatter_rows<R>, dim3(blocks_for(n * width, kThreads)), dim3(kThreads), 0, st, src, perm, n,
+                     width, dst_caller);
+}
+
+void launch_init_charges(const HydroParams& hp, int64_t n, const double* prim_caller, const int32_t* perm,
+                         const double* geo, double* Q_caller, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_init_charges, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, prim_caller, perm,
+                     geo, Q_caller);
+}
+
+#define MM_INSTANTIATE(R)                                                                                          \
+  template void launch_cell_state<R>(const HydroParams&, int64_t, const double*, const int32_t*, const double*,   \
+                                     double*, R*, double*, DevStatus*, hipStream_t);                              \
+  template void launch_gradient<R>(const HydroParams&, int64_t, const R*, const unsigned long long*,              \
+                                   const NbrEntry*, const double*, int, R*, const double*, const DevStatus*,      \
+                                   double, R*, DevStatus*, hipStream_t);                                          \
+  template void launch_predict<R>(const HydroParams&, int64_t, const R*, const R*, const double*,                 \
+                                  const DevStatus*, double, R*, DevStatus*, hipStream_t);                         \
+  template void launch_flux<R>(const HydroParams&, int64_t, const unsigned long long*, const Face*, const double*, \
+                               const double*, const R*, const R*, const double*, const DevStatus*, double, R*,   \
+                               DevStatus*, hipStream_t);                                                          \
+  template void launch_update<R>(const HydroParams&, int64_t, const unsigned long long*, const int32_t*,          \
+                                 const R*, const double*, const int32_t*, const double*, double*, const double*,  \
+                                 const double*, double*, double*, const DevStatus*, double, DevStatus*,           \
+                                 hipStream_t);                                                                    \
+  template void launch_accumulate<R>(int64_t, const unsigned long long*, const int32_t*, const R*, const int32_t*, \
+                                     double*, hipStream_t);                                                       \
+  template void launch_gather_rows<R>(const R*, const int32_t*, int64_t, int, R*, hipStream_t);                   \
+  template void launch_scatter_rows<R>(const R*, const int32_t*, int64_t, int, R*, hipStream_t);
+
+MM_INSTANTIATE(double)
+MM_INSTANTIATE(float)
+
+}  // namespace mm

@@ -1,0 +1,205 @@
+// Mesh assembly after the tessellation: unique faces (each stored once, by
+// the cell with the lower internal index), the per-cell face lists (CSR) used
+// to apply every face flux to both of its cells with opposite signs (Sec. 4,
+// eq. "time evolution"), the per-cell neighbour entries of the least-squares
+// gradient (centroid displacements and weights, Sec. 4.1) and the inverse of
+// each cell's 3x3 least-squares matrix.  Also the exports of the mesh to the
+// caller's point order.
+#include "mm_internal.h"
+
+namespace mm {
+
+namespace {
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// One thread per cell.  The packed prefix sum off[] holds, for cell s, the
+// index of its first unique face in the low 32 bits and of its first CSR
+// entry in the high 32 bits.
+__global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ spos, const double* __restrict__ geo,
+                                                    int64_t n, GridParams g, const StageNbr* __restrict__ stage_nb,
+                                                    const StageGeo* __restrict__ stage_geo,
+                                                    const unsigned long long* __restrict__ counts,
+                                                    const unsigned long long* __restrict__ off, int64_t face_cap,
+                                                    Face* __restrict__ faces, int32_t* __restrict__ csr,
+                                                    NbrEntry* __restrict__ nbr, double* __restrict__ minv,
+                                                    DevStatus* st) {
+  __shared__ int smax[256];
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int nf = 0;
+  if (s < n) {
+    const unsigned long long cnt = counts[s];
+    nf = (int)(cnt >> 32);
+    const unsigned long long o = off[s];
+    const int64_t face_base = (int64_t)(o & 0xffffffffull);
+    const int64_t csr_base = (int64_t)(o >> 32);
+    const double rx = spos[3 * s], ry = spos[3 * s + 1], rz = spos[3 * s + 2];
+    const double cix = geo[4 * s + 1], ciy = geo[4 * s + 2], ciz = geo[4 * s + 3];
+    double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
+    int bad = 0;
+    if (csr_base + nf > 2 * face_cap) {   // directed faces beyond the CSR capacity
+      nf = 0;
+      bad |= F_FACECAP;
+    }
+    for (int e = 0; e < nf; ++e) {
+      const StageNbr Nb = stage_nb[s * kMaxFaces + e];
+      const StageGeo F = stage_geo[s * kMaxFaces + e];
+      const int j = Nb.j;
+      const int code = Nb.meta & 255;
+      const bool owned = (Nb.meta >> 8) & 1;
+      const int orank = Nb.meta >> 16;
+      int kx, ky, kz;
+      decode(code, kx, ky, kz);
+      // centroid displacement d = (c_j + s) - c_i = (r_j + s - r_i) + (c_j - r_j) - (c_i - r_i)
+      const double drx = (spos[3 * (int64_t)j] + kx * g.L[0]) - rx;
+      const double dry = (spos[3 * (int64_t)j + 1] + ky * g.L[1]) - ry;
+      const double drz = (spos[3 * (int64_t)j + 2] + kz * g.L[2]) - rz;
+      const double dx = drx + geo[4 * (int64_t)j + 1] - cix;
+      const double dy = dry + geo[4 * (int64_t)j + 2] - ciy;
+      const double dz = drz + geo[4 * (int64_t)j + 3] - ciz;
+      const double wgt = F.A / (dx * dx + dy * dy + dz * dz);
+      NbrEntry E;
+      E.o = j;
+      E.pad = 0;
+      E.d[0] = dx;
+      E.d[1] = dy;
+      E.d[2] = dz;
+      E.wgt = wgt;
+      nbr[csr_base + e] = E;
+      m00 += wgt * dx * dx;
+      m01 += wgt * dx * dy;
+      m02 += wgt * dx * dz;
+      m11 += wgt * dy * dy;
+      m12 += wgt * dy * dz;
+      m22 += wgt * dz * dz;
+      int32_t entry = 0;
+      if (owned) {
+        const int64_t fid = face_base + orank;
+        if (fid < face_cap) {
+          Face out;
+          out.i = (int32_t)s;
+          out.j = j;
+          out.code = code;
+          out.pad = 0;
+          out.A = F.A;
+          out.f[0] = F.f[0];
+          out.f[1] = F.f[1];
+          out.f[2] = F.f[2];
+          faces[fid] = out;
+          entry = (int32_t)fid;
+        } else {
+          bad |= F_FACECAP;
+        }
+      } else {
+        // The same face in the neighbour's list: neighbour s, opposite image.
+        const int want = 26 - code;
+        const int nfj = (int)(counts[j] >> 32);
+        int found_meta = -1;
+        for (int t = 0; t < nfj; ++t) {
+          const StageNbr G = stage_nb[(int64_t)j * kMaxFaces + t];
+          if (G.j == (int)s && (G.meta & 255) == want) {
+            found_meta = G.meta;
+            break;
+          }
+        }
+        if (found_meta < 0 || !((found_meta >> 8) & 1)) {
+          bad |= F_ASYM;
+          st->asym_cell = (int)s;
+          st->asym_nbr = j;
+        } else {
+          const int64_t fid = (int64_t)(off[j] & 0xffffffffull) + (found_meta >> 16);
+          if (fid < face_cap) entry = (int32_t)(fid | 0x80000000ll);
+          else bad |= F_FACECAP;
+        }
+      }
+      csr[csr_base + e] = entry;
+    }
+    // Inverse of the symmetric least-squares matrix by its adjugate.
+    const double a00 = m11 * m22 - m12 * m12;
+    const double a01 = m02 * m12 - m01 * m22;
+    const double a02 = m01 * m12 - m02 * m11;
+    const double a11 = m00 * m22 - m02 * m02;
+    const double a12 = m02 * m01 - m00 * m12;
+    const double a22 = m00 * m11 - m01 * m01;
+    const double det = m00 * a00 + m01 * a01 + m02 * a02;
+    double* mi = minv + 6 * s;
+    if (nf > 0) {
+      mi[0] = a00 / det;
+      mi[1] = a01 / det;
+      mi[2] = a02 / det;
+      mi[3] = a11 / det;
+      mi[4] = a12 / det;
+      mi[5] = a22 / det;
+    } else {
+      for (int k = 0; k < 6; ++k) mi[k] = 0.0;
+    }
+    if (bad) {
+      atomicOr(&st->flags, bad);
+      atomicMin(&st->bad_cell, (int)s);
+    }
+  }
+  smax[threadIdx.x] = nf;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && smax[0] > 0) atomicMax(&st->max_faces, smax[0]);
+}
+
+__global__ void k_copy_totals(const unsigned long long* off, int64_t n, DevStatus* st) {
+  if (threadIdx.x == 0) {
+    st->n_faces = off[n] & 0xffffffffull;
+    st->n_csr = off[n] >> 32;
+  }
+}
+
+__global__ void k_export_cells(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ spos,
+                               const double* __restrict__ geo, double* V, double* centroid) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t q = perm[s];
+  if (V) V[q] = geo[4 * s];
+  if (centroid) {
+    for (int a = 0; a < 3; ++a) centroid[3 * q + a] = spos[3 * s + a] + geo[4 * s + 1 + a];
+  }
+}
+
+__global__ void k_export_faces(int64_t nf, const int32_t* __restrict__ perm, const double* __restrict__ spos,
+                               const Face* __restrict__ faces, int32_t* fi, int32_t* fj, int32_t* fc, double* fA,
+                               double* ff) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const Face F = faces[f];
+  if (fi) fi[f] = perm[F.i];
+  if (fj) fj[f] = perm[F.j];
+  if (fc) fc[f] = F.code;
+  if (fA) fA[f] = F.A;
+  if (ff) {
+    for (int a = 0; a < 3; ++a) ff[3 * f + a] = spos[3 * (int64_t)F.i + a] + F.f[a];
+  }
+}
+
+}  // namespace
+
+void launch_build_mesh(const double* spos, const double* geo, int64_t n, const GridParams& g,
+                       const StageNbr* stage_nb, const StageGeo* stage_geo, const unsigned long long* counts,
+                       const unsigned long long* off,
+                       int64_t face_cap, Face* faces, int32_t* csr, NbrEntry* nbr, double* minv,
+                       DevStatus* st_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_build_mesh, dim3(blocks_for(n, 256)), dim3(256), 0, st, spos, geo, n, g, stage_nb, stage_geo, counts, off,
+                     face_cap, faces, csr, nbr, minv, st_dev);
+  hipLaunchKernelGGL(k_copy_totals, dim3(1), dim3(64), 0, st, off, n, st_dev);
+}
+
+void launch_export_mesh(int64_t n, int64_t nf, const int32_t* perm, const double* spos, const double* geo,
+                        const Face* faces, double* V, double* centroid, int32_t* fi, int32_t* fj, int32_t* fc,
+                        double* fA, double* ff, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_export_cells, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, perm, spos, geo, V, centroid);
+  if (nf > 0)
+    hipLaunchKernelGGL(k_export_faces, dim3(blocks_for(nf, 256)), dim3(256), 0, st, nf, perm, spos, faces, fi, fj,
+                       fc, fA, ff);
+}
+
+}  // namespace mm

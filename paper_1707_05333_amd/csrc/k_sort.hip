@@ -1,0 +1,236 @@
+// Grid hash and counting sort of the mesh-generating points, plus the
+// prefix-sum and fill kernels the rest of the path uses.
+//
+// The sort realises the neighbour search the paper leaves to a tree
+// (Sec. 3: "rapid nearest-neighbor search"): points are binned into a
+// periodic grid of buckets, bucket-major with x fastest, so that the
+// candidate stencil of a cell reads contiguous runs of positions.  Inside a
+// bucket points keep their caller order, which makes the internal order, and
+// every result downstream of it, independent of atomic scheduling.
+#include "mm_internal.h"
+
+namespace mm {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline unsigned long long wave_incl_scan(unsigned long long x) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ unsigned long long block_excl_scan(unsigned long long x, unsigned long long* total) {
+  __shared__ unsigned long long wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const unsigned long long inc = wave_incl_scan(x);
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  unsigned long long base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / 64; ++k) {
+    if (k < wid) base += wsum[k];
+    tot += wsum[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const unsigned long long* in, int64_t n,
+                                                              unsigned long long* part) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  unsigned long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  unsigned long long tot;
+  block_excl_scan(s, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the per-tile sums in place, by one block.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(unsigned long long* part, int64_t m) {
+  unsigned long long carry = 0;
+  for (int64_t base = 0; base < m; base += kScanTile) {
+    unsigned long long v[kScanItems];
+    unsigned long long s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+      v[k] = (i < m) ? part[i] : 0ull;
+      s += v[k];
+    }
+    unsigned long long tot;
+    unsigned long long run = carry + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+      if (i < m) part[i] = run;
+      run += v[k];
+    }
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const unsigned long long* in, int64_t n,
+                                                            const unsigned long long* part,
+                                                            unsigned long long* out) {
+  __shared__ unsigned long long tile[kScanTile];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k * kScanThreads + threadIdx.x;
+    tile[k * kScanThreads + threadIdx.x] = (i < n) ? in[i] : 0ull;
+  }
+  __syncthreads();
+  unsigned long long v[kScanItems];
+  unsigned long long s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = tile[threadIdx.x * kScanItems + k];
+    s += v[k];
+  }
+  unsigned long long tot;
+  unsigned long long run = part[blockIdx.x] + block_excl_scan(s, &tot);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    tile[threadIdx.x * kScanItems + k] = run;
+    run += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + k * kScanThreads + threadIdx.x;
+    if (i < n) out[i] = tile[k * kScanThreads + threadIdx.x];
+  }
+  // The last tile also writes the grand total at out[n].
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanThreads - 1) out[n] = run;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_status_reset(DevStatus* s) {
+  if (threadIdx.x == 0) {
+    s->dt_bits = 0x7ff0000000000000ull;   // +inf
+    s->flags = 0;
+    s->n_deferred = 0;
+    s->max_faces = 0;
+    s->bad_cell = 0x7fffffff;
+    for (int k = 0; k < 4; ++k) s->floor_hits[k] = 0;
+    s->n_faces = 0;
+    s->n_csr = 0;
+    s->asym_cell = -1;
+    s->asym_nbr = -1;
+  }
+}
+
+__global__ void k_hash(const double* __restrict__ pos, int64_t n, GridParams g, int32_t* __restrict__ key,
+                       unsigned long long* bcount, DevStatus* st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+  const bool ok = (x >= 0.0) && (x < g.L[0]) && (y >= 0.0) && (y < g.L[1]) && (z >= 0.0) && (z < g.L[2]);
+  int k = 0;
+  if (ok) {
+    const int bx = bucket_coord(x, g.inv_hb[0], g.nb[0]);
+    const int by = bucket_coord(y, g.inv_hb[1], g.nb[1]);
+    const int bz = bucket_coord(z, g.inv_hb[2], g.nb[2]);
+    k = bx + g.nb[0] * (by + g.nb[1] * bz);
+  } else {
+    atomicOr(&st->flags, F_BADPOS);
+    atomicMin(&st->bad_cell, (int)i);
+  }
+  key[i] = k;
+  atomicAdd(&bcount[k], 1ull);
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ key, int64_t n, const unsigned long long* __restrict__ boff,
+                          unsigned long long* cursor, int32_t* __restrict__ perm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = key[i];
+  const unsigned long long slot = boff[k] + atomicAdd(&cursor[k], 1ull);
+  perm[slot] = (int32_t)i;
+}
+
+// Restores caller order inside each bucket (buckets hold a handful of points).
+__global__ void k_bucket_order(const unsigned long long* __restrict__ boff, int64_t nbt, int32_t* perm) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbt) return;
+  const int64_t lo = (int64_t)boff[b], hi = (int64_t)boff[b + 1];
+  for (int64_t a = lo + 1; a < hi; ++a) {
+    const int32_t v = perm[a];
+    int64_t c = a - 1;
+    while (c >= lo && perm[c] > v) {
+      perm[c + 1] = perm[c];
+      --c;
+    }
+    perm[c + 1] = v;
+  }
+}
+
+__global__ void k_gather_pos(const double* __restrict__ pos, const int32_t* __restrict__ perm, int64_t n,
+                             double* __restrict__ spos) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t q = perm[s];
+  spos[3 * s] = pos[3 * q];
+  spos[3 * s + 1] = pos[3 * q + 1];
+  spos[3 * s + 2] = pos[3 * q + 2];
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+
+void scan_u64(const unsigned long long* in, unsigned long long* out, int64_t n, unsigned long long* tmp,
+              hipStream_t st) {
+  if (n <= 0) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, out, 0ull, (int64_t)1);
+    return;
+  }
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kScanThreads), 0, st, in, n, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, tmp, tiles);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)tiles), dim3(kScanThreads), 0, st, in, n, tmp, out);
+}
+
+void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
+}
+
+void launch_status_reset(DevStatus* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, st, s);
+}
+
+void launch_sort(const double* pos, int64_t n, const GridParams& g, unsigned long long* bcount,
+                 unsigned long long* boff, unsigned long long* scan_tmp, int32_t* key, int32_t* perm,
+                 double* spos, DevStatus* st_dev, hipStream_t st) {
+  launch_fill_u64(bcount, 0ull, g.nbt, st);
+  hipLaunchKernelGGL(k_hash, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, n, g, key, bcount, st_dev);
+  scan_u64(bcount, boff, g.nbt, scan_tmp, st);
+  launch_fill_u64(bcount, 0ull, g.nbt, st);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, key, n, boff, bcount, perm);
+  hipLaunchKernelGGL(k_bucket_order, dim3(blocks_for(g.nbt, 256)), dim3(256), 0, st, boff, (int64_t)g.nbt, perm);
+  hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, perm, n, spos);
+}
+
+}  // namespace mm

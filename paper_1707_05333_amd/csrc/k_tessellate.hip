@@ -1,0 +1,608 @@
+// Periodic Voronoi tessellation by half-space clipping, one wavefront per
+// cell (Sec. 3 of the paper: start from a box around the generator, cut it by
+// the bisector plane of each neighbour in order of distance, and stop once
+// the next neighbour is farther than twice the farthest vertex).
+//
+// Cell representation (all in the wavefront's LDS slice).  A convex cell is
+// stored by its dual: every face is a plane slot (normal d = r_j + s - r_i
+// relative to the generator, offset h = |d|^2/2), and every vertex is a
+// triangle of three plane slots, the planes that meet there.  Triangles are
+// oriented consistently, so each directed pair of planes (x -> y) belongs to
+// exactly one live triangle; the table E[x][y] stores it.  Cutting by a new
+// plane p:
+//   * each lane tests its two vertex slots against p (d_p . v > h_p, plain
+//     FP64, no epsilon) and a ballot gives the removed set;
+//   * an edge (x -> y) of a removed triangle whose neighbour E[y][x] survives
+//     lies on the boundary of the removed cap, and gets the new triangle
+//     (x, y, p) in a free slot: the fan of new vertices around the new face;
+//   * new vertices are intersections of three planes (Cramer's rule).
+// Vertex tests and triangle creation are lane-parallel; only the walk over
+// the distance-ordered candidates is serial.
+//
+// Epilogue: lane p walks the polygon of face p through E (from its lowest
+// triangle slot, so sums are deterministic) and integrates its area and area
+// centroid as a fan from that first vertex; the cell volume is the sum of
+// the pyramids A |d| / 6 over faces and the centroid the pyramids' weighted
+// centroids (3/4 of the way from the generator to each face centroid).
+#include <algorithm>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+namespace {
+
+constexpr int kWaves = 2;   // cells (wavefronts) per workgroup
+
+struct __align__(16) TessLds {
+  double4 pl[kPlanes];                 // plane: d.x, d.y, d.z, h
+  double vx[kVerts], vy[kVerts], vz[kVerts];
+  double4 cd[kCands];                  // candidate image: d, |d|^2
+  uint32_t tri[kVerts];                // a | b << 8 | c << 16
+  int32_t pcand[kPlanes];              // neighbour of each plane slot (j << 5 | image code); -1 - k for box plane k
+  int32_t cjk[kCands];                 // candidate: j << 5 | image code
+  int32_t first[kPlanes];
+  uint8_t E[kPlanes * kPlanes];
+  uint8_t order[kCands];
+  uint8_t freelist[kVerts];
+};
+
+struct TessArgs {
+  const double* spos;
+  int64_t n;
+  GridParams g;
+  const unsigned long long* boff;
+  StageNbr* stage_nb;
+  StageGeo* stage_geo;
+  unsigned long long* counts;
+  double* geo;
+  double* rmax2;
+  int32_t* deferred;
+  DevStatus* st;
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ unsigned long long lanes_below() { return (1ull << __lane_id()) - 1ull; }
+
+// Exclusive prefix sum over the wave of small non-negative values
+// (x < 2^BITS), from one ballot per bit; *total gets the wave's sum.
+template <int BITS>
+__device__ __forceinline__ int wave_excl_scan_small(int x, int* total) {
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const unsigned long long m = __ballot((x >> b) & 1);
+    pre += __popcll(m & lanes_below()) << b;
+    tot += __popcll(m) << b;
+  }
+  *total = tot;
+  return pre;
+}
+
+// Wave-wide reductions with DPP lane moves (no LDS round trip): within each
+// row of 16 lanes by quad permutes and row rotations, then across rows by
+// the row broadcasts; lane 63 ends with the result, read as a scalar.
+#define MM_DPP_REDUCE(OP, x)                                                        \
+  do {                                                                              \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));  \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));  \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xF, 0xF, false)); \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false)); \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false)); \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false)); \
+  } while (0)
+
+__device__ __forceinline__ unsigned op_max(unsigned a, unsigned b) { return a > b ? a : b; }
+__device__ __forceinline__ unsigned op_or(unsigned a, unsigned b) { return a | b; }
+
+__device__ __forceinline__ unsigned wave_umax32(unsigned x) {
+  MM_DPP_REDUCE(op_max, x);
+  return (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+__device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  MM_DPP_REDUCE(op_or, lo);
+  MM_DPP_REDUCE(op_or, hi);
+  return ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)hi, 63) << 32) |
+         (unsigned)__builtin_amdgcn_readlane((int)lo, 63);
+}
+
+// Upper bound of the wave's largest non-negative value: each value is
+// rounded up to float, whose bit patterns order like the values.
+__device__ __forceinline__ double wave_max_bound(double x) {
+  const unsigned b = __float_as_uint(__double2float_ru(x));
+  return (double)__uint_as_float(wave_umax32(b));
+}
+
+// Butterfly sum: every lane ends with the bitwise-same result.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ unsigned long long plane_bits(uint32_t t) {
+  return (1ull << (t & 255u)) | (1ull << ((t >> 8) & 255u)) | (1ull << ((t >> 16) & 255u));
+}
+
+// Vertex where planes a, b, c meet: solve [a; b; c] v = (a.w, b.w, c.w).
+__device__ __forceinline__ void intersect3(const double4 a, const double4 b, const double4 c, double& x, double& y,
+                                           double& z) {
+  const double bcx = b.y * c.z - b.z * c.y, bcy = b.z * c.x - b.x * c.z, bcz = b.x * c.y - b.y * c.x;
+  const double cax = c.y * a.z - c.z * a.y, cay = c.z * a.x - c.x * a.z, caz = c.x * a.y - c.y * a.x;
+  const double abx = a.y * b.z - a.z * b.y, aby = a.z * b.x - a.x * b.z, abz = a.x * b.y - a.y * b.x;
+  const double inv = 1.0 / (a.x * bcx + a.y * bcy + a.z * bcz);
+  x = (a.w * bcx + b.w * cax + c.w * abx) * inv;
+  y = (a.w * bcy + b.w * cay + c.w * aby) * inv;
+  z = (a.w * bcz + b.w * caz + c.w * abz) * inv;
+}
+
+__device__ void fail_cell(const TessArgs& A, int s, int bit) {
+  if (__lane_id() == 0) {
+    atomicOr(&A.st->flags, bit);
+    atomicMin(&A.st->bad_cell, s);
+    A.counts[s] = 0ull;
+    A.geo[4 * (int64_t)s] = 0.0;
+  }
+}
+
+// Per-lane view of the cell under construction: lane k holds vertex slots
+// k and k + 64 (triangle and position); the live masks and the squared
+// farthest-vertex distance are wave-uniform.
+struct CellRegs {
+  unsigned long long L0, L1;
+  uint32_t t0, t1;
+  double v0x, v0y, v0z, v1x, v1y, v1z;
+  double rmax2;
+};
+
+// Starting cell: the box r +- L/2, bounded by the bisectors of the
+// generator's six axis images (the "large rectangular cell" of Sec. 3).
+__device__ void init_box(TessLds& S, const GridParams& g, CellRegs& C) {
+  const int lane = __lane_id();
+  if (lane < 6) {
+    const int ax = lane >> 1;
+    const double sg = (lane & 1) ? -1.0 : 1.0;
+    double d[3] = {0.0, 0.0, 0.0};
+    d[ax] = sg * g.L[ax];
+    S.pl[lane] = make_double4(d[0], d[1], d[2], 0.5 * (g.L[ax] * g.L[ax]));
+    S.pcand[lane] = -1 - lane;
+  }
+  if (lane < 8) {
+    const int sx = (lane & 1) ? -1 : 1, sy = (lane & 2) ? -1 : 1, sz = (lane & 4) ? -1 : 1;
+    const int px = sx > 0 ? 0 : 1, py = sy > 0 ? 2 : 3, pz = sz > 0 ? 4 : 5;
+    int a1 = py, a2 = pz;
+    if (sx * sy * sz < 0) { a1 = pz; a2 = py; }   // orientation: det(d_a, d_b, d_c) > 0
+    S.tri[lane] = (uint32_t)(px | (a1 << 8) | (a2 << 16));
+    S.vx[lane] = sx * (0.5 * g.L[0]);
+    S.vy[lane] = sy * (0.5 * g.L[1]);
+    S.vz[lane] = sz * (0.5 * g.L[2]);
+    S.E[px * kPlanes + a1] = (uint8_t)lane;
+    S.E[a1 * kPlanes + a2] = (uint8_t)lane;
+    S.E[a2 * kPlanes + px] = (uint8_t)lane;
+  }
+  wave_sync();
+  C.L0 = 0xffull;
+  C.L1 = 0ull;
+  C.t0 = S.tri[lane];
+  C.t1 = S.tri[lane + 64];
+  C.v0x = S.vx[lane]; C.v0y = S.vy[lane]; C.v0z = S.vz[lane];
+  C.v1x = S.vx[lane + 64]; C.v1y = S.vy[lane + 64]; C.v1z = S.vz[lane + 64];
+  C.rmax2 = wave_max_bound(lane < 8 ? C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z : 0.0);
+}
+
+// Smallest stencil half-width whose buckets contain every image closer than
+// sqrt(r2) to the generator.
+__device__ int ring_for(const GridParams& g, const double edge[3], double r2) {
+  const double r = sqrt(r2);
+  int ring = 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ring = max(ring, (int)ceil((r - edge[a]) / g.hb[a]));
+  return ring;
+}
+
+// Gathers the neighbour images with lo2 <= |d|^2 < hi2 from the stencil of
+// half-width `ring` into LDS (at most kCands of them); returns their number.
+// Lanes take one bucket each and step through its points together.  The
+// generator's own images are not gathered: the box planes stand for them.
+__device__ int gather(TessLds& S, const TessArgs& A, const int s, const double r[3], const int b[3], const int ring,
+                      const double lo2, const double hi2) {
+  const GridParams& g = A.g;
+  const int W = 2 * ring + 1, W3 = W * W * W;
+  int nc = 0;
+  for (int chunk = 0; chunk < W3; chunk += 64) {
+    const int o = chunk + __lane_id();
+    int bst = 0, cnt = 0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    int code = 13;
+    if (o < W3) {
+      const int oo[3] = {o % W - ring, (o / W) % W - ring, o / (W * W) - ring};
+      int kk[3], bb[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int t = b[a] + oo[a];
+        kk[a] = t < 0 ? -1 : (t >= g.nb[a] ? 1 : 0);
+        bb[a] = t - kk[a] * g.nb[a];
+      }
+      const int key = bb[0] + g.nb[0] * (bb[1] + g.nb[1] * bb[2]);
+      const unsigned long long b0 = A.boff[key];
+      bst = (int)b0;
+      cnt = (int)(A.boff[key + 1] - b0);
+      code = code_of(kk[0], kk[1], kk[2]);
+      sx = kk[0] * g.L[0];
+      sy = kk[1] * g.L[1];
+      sz = kk[2] * g.L[2];
+    }
+    const int maxc = (int)wave_umax32((unsigned)cnt);
+    for (int k = 0; k < maxc; ++k) {
+      bool keep = false;
+      double dx = 0, dy = 0, dz = 0, d2 = 0;
+      const int j = bst + k;
+      if (k < cnt && j != s) {
+        dx = (A.spos[3 * (int64_t)j] + sx) - r[0];
+        dy = (A.spos[3 * (int64_t)j + 1] + sy) - r[1];
+        dz = (A.spos[3 * (int64_t)j + 2] + sz) - r[2];
+        d2 = dx * dx + dy * dy + dz * dz;
+        keep = (d2 >= lo2) && (d2 < hi2);
+      }
+      const unsigned long long mk = __ballot(keep);
+      if (keep) {
+        const int idx = nc + __popcll(mk & lanes_below());
+        if (idx < kCands) {
+          S.cd[idx] = make_double4(dx, dy, dz, d2);
+          S.cjk[idx] = (j << 5) | code;
+        }
+      }
+      nc += __popcll(mk);
+    }
+  }
+  wave_sync();
+  return nc;
+}
+
+// Orders the gathered candidates by distance (ties: gather order).
+__device__ void sort_candidates(TessLds& S, const int nc) {
+  for (int c = __lane_id(); c < nc; c += 64) {
+    const double key = S.cd[c].w;
+    int rank = 0;
+    for (int m = 0; m < nc; ++m) {
+      const double km = S.cd[m].w;
+      rank += (km < key) || (km == key && m < c);
+    }
+    S.order[rank] = (uint8_t)c;
+  }
+  wave_sync();
+}
+
+// Cuts the cell by the ordered candidates, stopping at the first one farther
+// than twice the farthest vertex (Sec. 3).  Returns 0 or a failure bit.
+__device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
+  const int lane = __lane_id();
+  for (int k = 0; k < nc; ++k) {
+    const int c = S.order[k];
+    const double4 q = S.cd[c];
+    if (q.w >= 4.0 * C.rmax2) break;   // farther images cannot cut the cell
+    const double h = 0.5 * q.w;
+    const bool live0 = (C.L0 >> lane) & 1ull, live1 = (C.L1 >> lane) & 1ull;
+    const bool out0 = live0 && (q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h);
+    const bool out1 = live1 && (q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h);
+    const unsigned long long M0 = __ballot(out0), M1 = __ballot(out1);
+    if ((M0 | M1) == 0ull) continue;
+
+    // Plane slot for the new face: lowest slot no surviving vertex uses.
+    const bool kept0 = live0 && !out0, kept1 = live1 && !out1;
+    unsigned long long u = 0ull;
+    if (kept0) u |= plane_bits(C.t0);
+    if (kept1) u |= plane_bits(C.t1);
+    const unsigned long long used = wave_or(u);
+    if (used == ~0ull) return F_PLANES;
+    const int p = __builtin_ctzll(~used);
+
+    // Boundary of the removed cap: edges of removed vertices whose
+    // neighbour across the edge survives (bit k of bm: edge k of the slot).
+    const unsigned long long L0 = C.L0, L1 = C.L1;
+    auto is_kept = [&](int t) -> bool {
+      const bool lv = t < 64 ? ((L0 >> t) & 1ull) : ((L1 >> (t - 64)) & 1ull);
+      const bool ot = t < 64 ? ((M0 >> t) & 1ull) : ((M1 >> (t - 64)) & 1ull);
+      return lv && !ot;
+    };
+    auto boundary = [&](uint32_t T) -> int {
+      const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
+      int m = 0;
+      if (is_kept(S.E[bq * kPlanes + a] & (kVerts - 1))) m |= 1;
+      if (is_kept(S.E[cq * kPlanes + bq] & (kVerts - 1))) m |= 2;
+      if (is_kept(S.E[a * kPlanes + cq] & (kVerts - 1))) m |= 4;
+      return m;
+    };
+    const int bm0 = out0 ? boundary(C.t0) : 0;
+    const int bm1 = out1 ? boundary(C.t1) : 0;
+    const int nbl = __popc(bm0) + __popc(bm1);
+    int B;
+    const int pre = wave_excl_scan_small<3>(nbl, &B);
+
+    const unsigned long long F0 = ~L0 | M0, F1 = ~L1 | M1;   // free slots after the cut
+    const int nf0 = __popcll(F0);
+    if (B > nf0 + __popcll(F1)) return F_VERTS;
+    const int r0 = __popcll(F0 & lanes_below());
+    const int r1 = nf0 + __popcll(F1 & lanes_below());
+    if ((F0 >> lane) & 1ull) S.freelist[r0] = (uint8_t)lane;
+    if ((F1 >> lane) & 1ull) S.freelist[r1] = (uint8_t)(lane + 64);
+    if (lane == 0) {
+      S.pl[p] = make_double4(q.x, q.y, q.z, h);
+      S.pcand[p] = S.cjk[c];   // the neighbour itself: later shells reuse the candidate slots
+    }
+    wave_sync();   // every E lookup above is done before any write below
+
+    int e = pre;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const uint32_t T = sl ? C.t1 : C.t0;
+      const int bm = sl ? bm1 : bm0;
+      const int ta = T & 255, tb = (T >> 8) & 255, tc = (T >> 16) & 255;
+#pragma unroll
+      for (int k3 = 0; k3 < 3; ++k3) {
+        if (!((bm >> k3) & 1)) continue;
+        const int x = k3 == 0 ? ta : (k3 == 1 ? tb : tc);
+        const int y = k3 == 0 ? tb : (k3 == 1 ? tc : ta);
+        const int ns = S.freelist[e++];
+        S.tri[ns] = (uint32_t)(x | (y << 8) | (p << 16));
+        double nx, ny, nz;
+        intersect3(S.pl[x], S.pl[y], S.pl[p], nx, ny, nz);
+        S.vx[ns] = nx;
+        S.vy[ns] = ny;
+        S.vz[ns] = nz;
+        S.E[x * kPlanes + y] = (uint8_t)ns;
+        S.E[y * kPlanes + p] = (uint8_t)ns;
+        S.E[p * kPlanes + x] = (uint8_t)ns;
+      }
+    }
+    wave_sync();
+
+    const bool nl0 = kept0 || (((F0 >> lane) & 1ull) && r0 < B);
+    const bool nl1 = kept1 || (((F1 >> lane) & 1ull) && r1 < B);
+    C.L0 = __ballot(nl0);
+    C.L1 = __ballot(nl1);
+    C.t0 = S.tri[lane];
+    C.t1 = S.tri[lane + 64];
+    C.v0x = S.vx[lane]; C.v0y = S.vy[lane]; C.v0z = S.vz[lane];
+    C.v1x = S.vx[lane + 64]; C.v1y = S.vy[lane + 64]; C.v1z = S.vz[lane + 64];
+    double m2 = 0.0;
+    if (nl0) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
+    if (nl1) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
+    C.rmax2 = wave_max_bound(m2);
+  }
+  return 0;
+}
+
+// Faces, volume and centroid of the finished cell; writes the cell's outputs.
+__device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const CellRegs& C) {
+  const int lane = __lane_id();
+  const bool live0 = (C.L0 >> lane) & 1ull, live1 = (C.L1 >> lane) & 1ull;
+  S.first[lane] = kVerts;
+  wave_sync();
+  if (live0) {
+    atomicMin(&S.first[C.t0 & 255], lane);
+    atomicMin(&S.first[(C.t0 >> 8) & 255], lane);
+    atomicMin(&S.first[(C.t0 >> 16) & 255], lane);
+  }
+  if (live1) {
+    atomicMin(&S.first[C.t1 & 255], lane + 64);
+    atomicMin(&S.first[(C.t1 >> 8) & 255], lane + 64);
+    atomicMin(&S.first[(C.t1 >> 16) & 255], lane + 64);
+  }
+  wave_sync();
+  unsigned long long ul = 0ull;
+  if (live0) ul |= plane_bits(C.t0);
+  if (live1) ul |= plane_bits(C.t1);
+  const unsigned long long usedL = wave_or(ul);
+
+  // Lane p integrates the polygon of face p as a fan from its first vertex:
+  // the walk goes counter-clockwise seen from outside, so the area along the
+  // outward normal is positive.
+  const int p = lane;
+  const bool valid = (usedL >> p) & 1ull;
+  double Af = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, dl = 0.0;
+  bool walk_bad = false;
+  if (valid) {
+    const double4 P = S.pl[p];
+    dl = sqrt(2.0 * P.w);
+    const double nx = P.x / dl, ny = P.y / dl, nz = P.z / dl;
+    const int tstart = S.first[p];
+    const double ox = S.vx[tstart], oy = S.vy[tstart], oz = S.vz[tstart];
+    int t = tstart, it = 0;
+    double as = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    do {
+      const uint32_t T = S.tri[t];
+      const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
+      const int z = (a == p) ? cq : (bq == p ? a : bq);
+      const int tn = S.E[p * kPlanes + z] & (kVerts - 1);
+      const double x1 = S.vx[t] - ox, y1 = S.vy[t] - oy, z1 = S.vz[t] - oz;
+      const double x2 = S.vx[tn] - ox, y2 = S.vy[tn] - oy, z2 = S.vz[tn] - oz;
+      const double ar = 0.5 * ((y1 * z2 - z1 * y2) * nx + (z1 * x2 - x1 * z2) * ny + (x1 * y2 - y1 * x2) * nz);
+      as += ar;
+      mx += ar * (x1 + x2);
+      my += ar * (y1 + y2);
+      mz += ar * (z1 + z2);
+      t = tn;
+      ++it;
+    } while (t != tstart && it < kVerts);
+    walk_bad = (t != tstart);
+    Af = as;
+    fx = ox + mx / (3.0 * as);
+    fy = oy + my / (3.0 * as);
+    fz = oz + mz / (3.0 * as);
+  }
+  if (__ballot(walk_bad)) return F_WALK;
+  // A plane that only touches the cell gives no face (non-positive area).
+  const bool keep = valid && Af > 0.0;
+  const double vol = keep ? Af * dl / 6.0 : 0.0;
+  const double V = wave_sum(vol);
+  const double cxr = wave_sum(0.75 * vol * fx) / V;
+  const double cyr = wave_sum(0.75 * vol * fy) / V;
+  const double czr = wave_sum(0.75 * vol * fz) / V;
+  if (!(V > 0.0)) return F_VOLUME;
+
+  int j = s, code = 13;
+  if (keep) {
+    const int pc = S.pcand[p];
+    if (pc >= 0) {
+      j = pc >> 5;
+      code = pc & 31;
+    } else {
+      const int bp = -1 - pc;   // box plane: axis bp/2, sign by parity
+      const int step = (bp >> 1) == 0 ? 1 : ((bp >> 1) == 1 ? 3 : 9);
+      code = (bp & 1) ? 13 - step : 13 + step;
+    }
+  }
+  const bool owned = keep && (j > s || (j == s && code > 13));
+  const unsigned long long MK = __ballot(keep), MO = __ballot(owned);
+  if (keep) {
+    const int idx = __popcll(MK & lanes_below());
+    const int orank = __popcll(MO & lanes_below());
+    StageNbr nb;
+    nb.j = j;
+    nb.meta = code | ((owned ? 1 : 0) << 8) | (orank << 16);
+    A.stage_nb[(int64_t)s * kMaxFaces + idx] = nb;
+    StageGeo& F = A.stage_geo[(int64_t)s * kMaxFaces + idx];
+    F.A = Af;
+    F.f[0] = fx;
+    F.f[1] = fy;
+    F.f[2] = fz;
+  }
+  if (lane == 0) {
+    A.counts[s] = ((unsigned long long)__popcll(MK) << 32) | (unsigned long long)__popcll(MO);
+    double* gp = A.geo + 4 * (int64_t)s;
+    gp[0] = V;
+    gp[1] = cxr;
+    gp[2] = cyr;
+    gp[3] = czr;
+  }
+  return 0;
+}
+
+__device__ void defer_cell(const TessArgs& A, int s, double rmax2) {
+  if (__lane_id() == 0) {
+    const int idx = atomicAdd(&A.st->n_deferred, 1);
+    A.deferred[idx] = s;
+    A.rmax2[s] = rmax2;
+  }
+}
+
+// Builds the cell of internal generator s.
+// pass 1: candidates within the grid's filter radius; a cell whose
+//   candidates do not cover twice its farthest vertex (or overflow the
+//   candidate slots) is deferred.
+// pass 2: distance shells [lo, hi) processed in order, each gathered from a
+//   stencil wide enough for it and narrowed until it fits the candidate
+//   slots, until twice the farthest vertex lies inside the shells done.  The
+//   first shell ends at twice the pass-1 farthest vertex, which bounds the
+//   true one (the pass-1 cell contains the true cell).
+__device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int pass) {
+  const GridParams& g = A.g;
+  const double r[3] = {A.spos[3 * (int64_t)s], A.spos[3 * (int64_t)s + 1], A.spos[3 * (int64_t)s + 2]};
+  int b[3];
+  double edge[3];   // distance from the generator to its bucket's nearer wall, per axis
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    b[a] = bucket_coord(r[a], g.inv_hb[a], g.nb[a]);
+    const double t = r[a] - b[a] * g.hb[a];
+    edge[a] = fmax(0.0, fmin(t, g.hb[a] - t));
+  }
+  CellRegs C;
+  init_box(S, g, C);
+
+  if (pass == 1) {
+    double reach = 1e300;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) reach = fmin(reach, g.ring * g.hb[a] + edge[a]);
+    const double hi2 = fmin(reach * reach, g.r_filter * g.r_filter);
+    const int nc = gather(S, A, s, r, b, g.ring, 0.0, hi2);
+    if (nc > kCands) {
+      defer_cell(A, s, -1.0);
+      return;
+    }
+    sort_candidates(S, nc);
+    if (int bad = clip_candidates(S, nc, C)) {
+      fail_cell(A, s, bad);
+      return;
+    }
+    if (!(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12))) {
+      defer_cell(A, s, C.rmax2);
+      return;
+    }
+  } else {
+    const double rm2 = A.rmax2[s];
+    double lo2 = 0.0;
+    double hi2 = rm2 > 0.0 ? 4.0 * rm2 * (1.0 + 1e-9) : g.r_filter * g.r_filter;
+    bool done = false;
+    for (int shell = 0; shell < 32 && !done; ++shell) {
+      const int ring = ring_for(g, edge, hi2);
+      if (ring > g.nb[0] || ring > g.nb[1] || ring > g.nb[2]) {
+        fail_cell(A, s, F_BOX);
+        return;
+      }
+      int nc = gather(S, A, s, r, b, ring, lo2, hi2);
+      for (int tries = 0; nc > kCands && tries < 40; ++tries) {
+        hi2 = lo2 + 0.5 * (hi2 - lo2);
+        nc = gather(S, A, s, r, b, ring, lo2, hi2);
+      }
+      if (nc > kCands) {
+        fail_cell(A, s, F_CANDS);
+        return;
+      }
+      sort_candidates(S, nc);
+      if (int bad = clip_candidates(S, nc, C)) {
+        fail_cell(A, s, bad);
+        return;
+      }
+      if (4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)) {
+        done = true;
+      } else {
+        lo2 = hi2;
+        hi2 = 4.0 * C.rmax2 * (1.0 + 1e-9);
+      }
+    }
+    if (!done) {
+      fail_cell(A, s, F_INCOMPLETE);
+      return;
+    }
+  }
+  if (int bad = finish_cell(S, A, s, C)) fail_cell(A, s, bad);
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_tess_pass1(TessArgs A) {
+  __shared__ TessLds lds[kWaves];
+  const int w = threadIdx.x >> 6;
+  const int64_t s = (int64_t)blockIdx.x * kWaves + w;
+  if (s >= A.n) return;
+  tess_cell(lds[w], A, (int)s, 1);
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_tess_pass2(TessArgs A) {
+  __shared__ TessLds lds[kWaves];
+  const int w = threadIdx.x >> 6;
+  const int nd = A.st->n_deferred;
+  for (int64_t it = (int64_t)blockIdx.x * kWaves + w; it < nd; it += (int64_t)gridDim.x * kWaves)
+    tess_cell(lds[w], A, A.deferred[it], 2);
+}
+
+}  // namespace
+
+void launch_tessellate(const double* spos, int64_t n, const GridParams& g, const unsigned long long* boff,
+                       StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
+                       double* rmax2,
+                       int32_t* deferred, DevStatus* st_dev, hipStream_t st) {
+  TessArgs A{spos, n, g, boff, stage_nb, stage_geo, counts, geo, rmax2, deferred, st_dev};
+  const unsigned blocks = (unsigned)((n + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(k_tess_pass1, dim3(blocks), dim3(64 * kWaves), 0, st, A);
+  const unsigned blocks2 = (unsigned)std::min<int64_t>(blocks, 1024);
+  hipLaunchKernelGGL(k_tess_pass2, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
+}
+
+}  // namespace mm

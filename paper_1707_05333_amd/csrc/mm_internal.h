@@ -1,0 +1,180 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// MI355X moving-mesh step.  Not part of the public interface (include/mm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+// ---------------------------------------------------------------------------
+// Fixed per-cell capacities of the tessellation kernel (one wavefront per
+// cell).  A cell may hold up to kPlanes live faces at once (one 64-bit mask),
+// kVerts vertices and kCands candidate neighbours inside its stencil.
+// ---------------------------------------------------------------------------
+constexpr int kPlanes = 64;
+constexpr int kVerts = 128;
+constexpr int kCands = 128;
+constexpr int kMaxFaces = kPlanes;   // staging slots per cell
+
+// Failure bits collected in DevStatus::flags.
+enum : int {
+  F_BADPOS = 1 << 0,      // position not finite or outside [0, L)
+  F_PLANES = 1 << 1,      // more than kPlanes live faces
+  F_VERTS = 1 << 2,       // more than kVerts vertices
+  F_CANDS = 1 << 3,       // more than kCands candidates in a stencil
+  F_INCOMPLETE = 1 << 4,  // stencil could not cover twice the farthest vertex
+  F_ASYM = 1 << 5,        // a face has no partner in the neighbour's list
+  F_FACECAP = 1 << 6,     // more unique faces than the face capacity
+  F_NONFINITE = 1 << 7,   // NaN or infinite state
+  F_WALK = 1 << 8,        // corrupted face cycle
+  F_VOLUME = 1 << 9,      // non-positive cell volume
+  F_BOX = 1 << 10,        // stencil wider than the periodic box allows
+};
+
+// Status block written by the kernels and read back once per step.
+struct DevStatus {
+  unsigned long long dt_bits;    // min over cells of dt_i as IEEE bits (dt_i > 0)
+  int flags;
+  int n_deferred;                // cells handed to the wide-stencil pass
+  int max_faces;
+  int bad_cell;                  // lowest internal cell index with a failure
+  unsigned long long floor_hits[4];
+  unsigned long long n_faces;    // unique faces (copy of the scan total)
+  unsigned long long n_csr;      // directed faces (copy of the scan total)
+  int asym_cell, asym_nbr;       // one face without a partner (internal cells), for diagnostics
+};
+
+// Periodic bucket grid for the neighbour search.
+struct GridParams {
+  int nb[3];        // buckets per axis
+  int nbt;          // total buckets
+  double hb[3];     // bucket size per axis
+  double inv_hb[3];
+  double L[3];      // box
+  int ring;         // stencil half-width (in buckets) of the first pass
+  double r_filter;  // first-pass candidate radius
+};
+
+// One face of a cell as written by the tessellation kernel (cell-local list),
+// split so that a search of a neighbour's list reads 8 bytes per entry.
+struct StageNbr {
+  int32_t j;        // neighbour cell (internal index)
+  int32_t meta;     // bits 0-7 image code, bit 8 owned, bits 16-31 rank among owned faces
+};
+struct StageGeo {
+  double A;         // area
+  double f[3];      // area centroid minus the generator
+};
+
+// Unique face, stored once by its owner.
+struct Face {
+  int32_t i, j;     // owner and neighbour (internal)
+  int32_t code;     // periodic image of j seen from i
+  int32_t pad;
+  double A;
+  double f[3];      // area centroid minus r_i
+};
+
+// Per-cell neighbour entry used by the gradient kernel: neighbour index,
+// centroid displacement d = c_j + s - c_i and LSQ weight A / |d|^2.
+struct NbrEntry {
+  int32_t o;
+  int32_t pad;
+  double d[3];
+  double wgt;
+};
+
+// Scheme parameters as the kernels need them.
+struct HydroParams {
+  double L[3];
+  double gamma, cfl, eta, chi, zeta, theta, rho_floor, p_floor;
+  int limit_mask;
+  int predictor_frame;
+};
+
+// Bucket of one coordinate; the sort and the tessellation must agree on it.
+// Not-a-number and out-of-box coordinates land in a valid bucket (the sort
+// flags them separately).
+inline __device__ int bucket_coord(double x, double inv_h, int nb) {
+  const double t = floor(x * inv_h);
+  return t >= 0.0 ? (t < (double)nb ? (int)t : nb - 1) : 0;
+}
+
+inline __host__ __device__ int code_of(int kx, int ky, int kz) { return (kx + 1) + 3 * (ky + 1) + 9 * (kz + 1); }
+inline __host__ __device__ void decode(int code, int& kx, int& ky, int& kz) {
+  kx = code % 3 - 1;
+  ky = (code / 3) % 3 - 1;
+  kz = code / 9 - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (each enqueues on `st`).
+// ---------------------------------------------------------------------------
+
+// Exclusive prefix sum of n uint64 values into out[0..n] (out[n] = total).
+// tmp must hold scan_tmp_elems(n) elements.
+size_t scan_tmp_elems(int64_t n);
+void scan_u64(const unsigned long long* in, unsigned long long* out, int64_t n, unsigned long long* tmp,
+              hipStream_t st);
+
+void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t st);
+void launch_status_reset(DevStatus* s, hipStream_t st);
+
+// Bucket sort of the generators (grid hash, counting sort, index order inside
+// a bucket).  Writes perm (internal -> caller), spos, bucket offsets boff.
+void launch_sort(const double* pos, int64_t n, const GridParams& g, unsigned long long* bcount,
+                 unsigned long long* boff, unsigned long long* scan_tmp, int32_t* key, int32_t* perm,
+                 double* spos, DevStatus* st_dev, hipStream_t st);
+
+// Tessellation: pass 1 over every cell, then the deferred cells.
+void launch_tessellate(const double* spos, int64_t n, const GridParams& g, const unsigned long long* boff,
+                       StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
+                       double* rmax2,
+                       int32_t* deferred, DevStatus* st_dev, hipStream_t st);
+
+// Faces, CSR, neighbour entries and inverse LSQ matrices from the staged lists.
+void launch_build_mesh(const double* spos, const double* geo, int64_t n, const GridParams& g,
+                       const StageNbr* stage_nb, const StageGeo* stage_geo, const unsigned long long* counts,
+                       const unsigned long long* off,
+                       int64_t face_cap, Face* faces, int32_t* csr, NbrEntry* nbr, double* minv,
+                       DevStatus* st_dev, hipStream_t st);
+
+// Hydro kernels, instantiated for double (MM_FP64) and float (MM_MIXED).
+template <typename R>
+void launch_cell_state(const HydroParams& hp, int64_t n, const double* Q_caller, const int32_t* perm,
+                       const double* geo, double* Qs, R* U, double* w, DevStatus* st_dev, hipStream_t st);
+template <typename R>
+void launch_gradient(const HydroParams& hp, int64_t n, const R* U, const unsigned long long* csr_off,
+                     const NbrEntry* nbr, const double* minv, int limit, R* G, const double* w,
+                     const DevStatus* dt_src, double dt_fixed, R* U_half, DevStatus* st_dev, hipStream_t st);
+template <typename R>
+void launch_predict(const HydroParams& hp, int64_t n, const R* U, const R* G, const double* w,
+                    const DevStatus* dt_src, double dt_fixed, R* U_half, DevStatus* st_dev, hipStream_t st);
+// nf_dev (device count, may be NULL) overrides nf_host, which then only
+// bounds the launch.
+template <typename R>
+void launch_flux(const HydroParams& hp, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
+                 const double* spos, const double* geo, const R* Uh, const R* Gh, const double* w,
+                 const DevStatus* dt_src, double dt_fixed, R* phi, DevStatus* st_dev, hipStream_t st);
+template <typename R>
+void launch_update(const HydroParams& hp, int64_t n, const unsigned long long* csr_off, const int32_t* csr,
+                   const R* phi, const double* geo, const int32_t* perm, const double* Qs, double* Q_caller,
+                   const double* spos, const double* w, double* pos_caller, double* w_caller,
+                   const DevStatus* dt_src, double dt_max, DevStatus* st_dev, hipStream_t st);
+template <typename R>
+void launch_accumulate(int64_t n, const unsigned long long* csr_off, const int32_t* csr, const R* phi,
+                       const int32_t* perm, double* dQ_caller, hipStream_t st);
+
+// Layout conversions between caller order and internal order.
+template <typename R>
+void launch_gather_rows(const R* src_caller, const int32_t* perm, int64_t n, int width, R* dst, hipStream_t st);
+template <typename R>
+void launch_scatter_rows(const R* src, const int32_t* perm, int64_t n, int width, R* dst_caller, hipStream_t st);
+void launch_init_charges(const HydroParams& hp, int64_t n, const double* prim_caller, const int32_t* perm,
+                         const double* geo, double* Q_caller, hipStream_t st);
+void launch_export_mesh(int64_t n, int64_t nf, const int32_t* perm, const double* spos, const double* geo,
+                        const Face* faces, double* V, double* centroid, int32_t* fi, int32_t* fj, int32_t* fc,
+                        double* fA, double* ff, hipStream_t st);
+
+}  // namespace mm

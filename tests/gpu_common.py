@@ -1,0 +1,61 @@
+"""Helpers shared by the GPU tests: run the HIP path through the binding and
+line its outputs up with the oracle's."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def mesh_pair(orc, pos, box, method="grid", **params):
+    """Tessellates pos with the HIP path and the oracle."""
+    import paper_1707_05333_amd as M
+    mm = M.MovingMesh(pos.shape[0], M.make_params(box=box, **params))
+    info = mm.tessellate(dev(pos))
+    om = orc.tessellate(pos, box, method=method, certificate=True)
+    return mm, info, om
+
+
+def compare_mesh(mm, om, rtol=1e-10):
+    """Bit-exact topology and geometry within rtol of the cell scale."""
+    ex = mm.mesh_export()
+    V, c = host(ex.V), host(ex.centroid)
+    fi, fj, fc = host(ex.face_i), host(ex.face_j), host(ex.face_code)
+    fA, ff = host(ex.face_A), host(ex.face_f)
+    n = om.n
+    own = om.face_owner()
+    key = {(int(a), int(b), int(k)): t for t, (a, b, k) in enumerate(zip(own, om.j, om.code))}
+    # every unique GPU face is one directed oracle face, and the oracle has
+    # exactly two directed faces per GPU face
+    assert 2 * len(fi) == len(om.j), f"face count {len(fi)} unique vs {len(om.j)} directed"
+    idx = np.empty(len(fi), dtype=np.int64)
+    for t, (a, b, k) in enumerate(zip(fi.tolist(), fj.tolist(), fc.tolist())):
+        o = key.get((a, b, k))
+        assert o is not None, f"GPU face ({a},{b},{k}) not in the oracle tessellation"
+        assert (b, a, 26 - k) in key
+        idx[t] = o
+    assert len(set(idx.tolist())) == len(idx)
+    h = float(np.mean(om.V) ** (1 / 3))
+    np.testing.assert_allclose(V, om.V, rtol=rtol, atol=0)
+    assert np.abs(c - om.c).max() <= rtol * h
+    assert np.abs(fA - om.A[idx]).max() <= rtol * h * h
+    assert np.abs(ff - om.f[idx]).max() <= rtol * h
+    return ex
+
+
+def scaled_err(a, b):
+    """Max |a - b| per column divided by the column's max |b| (or 1)."""
+    a = np.asarray(a, dtype=np.float64).reshape(a.shape[0], -1)
+    b = np.asarray(b, dtype=np.float64).reshape(b.shape[0], -1)
+    scale = np.maximum(np.abs(b).max(axis=0), 1e-300)
+    return float((np.abs(a - b).max(axis=0) / scale).max())

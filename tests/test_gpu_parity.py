@@ -1,0 +1,246 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Tessellation: the neighbour topology must match bit-exactly on certified
+non-degenerate inputs; volumes, centroids, areas and face centres within
+1e-10 of the cell scale.  States (FP64): within 1e-10 relative to each
+column's scale, element by element.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import compare_mesh, dev, host, mesh_pair, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _print_case(what, **kw):
+    print(f"[case] {what} {kw}", flush=True)
+
+
+TESS_CASES = [
+    ("c1_lattice_16", lambda: (W.jittered_lattice((16, 16, 16), (1, 1, 1), seed=1), (1, 1, 1))),
+    ("lattice_ragged_7x9x11", lambda: (W.jittered_lattice((7, 9, 11), (0.7, 0.9, 1.1), seed=3), (0.7, 0.9, 1.1))),
+    ("sod_strip_64x8x8", lambda: (W.jittered_lattice((64, 8, 8), (4, 0.5, 0.5), seed=2), (4, 0.5, 0.5))),
+    ("poisson_3001", lambda: (W.poisson_points(3001, (1, 1, 1), seed=4), (1, 1, 1))),
+    ("poisson_20000", lambda: (W.poisson_points(20000, (1, 2, 0.5), seed=6), (1, 2, 0.5))),
+    ("lattice_3", lambda: (W.jittered_lattice((3, 3, 3), (1, 1, 1), seed=5), (1, 1, 1))),
+    ("lattice_2x3x4", lambda: (W.jittered_lattice((2, 3, 4), (1, 1, 1), seed=8), (1, 1, 1))),
+]
+
+
+@pytest.mark.parametrize("name,make", TESS_CASES, ids=[c[0] for c in TESS_CASES])
+def test_tessellation_parity(orc, name, make):
+    pos, box = make()
+    _print_case("tessellation", name=name, n=pos.shape[0])
+    mm, info, om = mesh_pair(orc, pos, box, method="brute" if pos.shape[0] <= 64 else "grid")
+    assert om.status == 0
+    om_cert = orc.tessellate(pos, box, method="grid", certificate=True)
+    assert om_cert.delta_min > 1e-12, "input not certified non-degenerate"
+    compare_mesh(mm, om)
+    assert info["n_faces"] * 2 == len(om.j)
+
+
+def test_bcc_closed_form_on_gpu():
+    # Exact body-centred cubic lattice: every cell is the truncated
+    # octahedron (volume a^3/2, 6 squares a^2/8, 8 hexagons 3 sqrt(3) a^2/16,
+    # centroid at the generator).  The lattice is degenerate for the
+    # certificate, so only the unique geometry is compared.
+    import paper_1707_05333_amd as M
+    m = 5
+    a = 1.0 / m
+    pos = W.bcc_lattice(m)
+    _print_case("bcc", n=pos.shape[0])
+    mm = M.MovingMesh(pos.shape[0], M.make_params(box=(1, 1, 1)))
+    info = mm.tessellate(dev(pos))
+    ex = mm.mesh_export()
+    np.testing.assert_allclose(host(ex.V), a ** 3 / 2, rtol=1e-12)
+    assert np.abs(host(ex.centroid) - pos).max() < 1e-14
+    A = np.sort(host(ex.face_A))
+    assert info["n_faces"] == 7 * pos.shape[0]
+    np.testing.assert_allclose(A[: 3 * pos.shape[0]], a * a / 8, rtol=1e-12)
+    np.testing.assert_allclose(A[3 * pos.shape[0]:], 3 * math.sqrt(3) * a * a / 16, rtol=1e-12)
+
+
+@pytest.mark.parametrize("pos,box", [(np.array([[0.3, 0.6, 0.1]]), (2, 1, 0.5)),
+                                     (np.array([[0.3, 0.5, 0.5], [1.62, 0.5, 0.5]]), (2, 1, 1))],
+                         ids=["one_point", "two_points"])
+def test_tiny_sets_violate_box_precondition(pos, box):
+    # With one or two generators twice the farthest vertex exceeds the box,
+    # outside the scheme's periodic premise: the library refuses.
+    import paper_1707_05333_amd as M
+    _print_case("tiny", n=pos.shape[0])
+    mm = M.MovingMesh(pos.shape[0], M.make_params(box=box))
+    with pytest.raises(M.MMError) as e:
+        mm.tessellate(dev(pos))
+    assert e.value.name == "MM_EDEGENERATE"
+
+
+def _setup(orc, wl, precision="fp64", **over):
+    import paper_1707_05333_amd as M
+    params = dict(wl.params)
+    params.update(over)
+    mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, precision=precision, **params))
+    mm.tessellate(dev(wl.pos))
+    p = orc.make_params(wl.box, **params)
+    om = orc.tessellate(wl.pos, wl.box)
+    return mm, p, om
+
+
+def test_charges_state_gradient_predictor_flux_parity(orc):
+    box = (1.0, 1.0, 1.0)
+    wl = W.random_smooth_state(W.jittered_lattice((12, 12, 12), box, seed=11), box, seed=11, amp=0.3)
+    _print_case("components", n=wl.n)
+    mm, p, om = _setup(orc, wl)
+    # charges (Sec. 4.3)
+    Qg = host(mm.init_charges(dev(wl.prim)))
+    Qo = orc.init_charges(om, p, wl.prim)
+    assert scaled_err(Qg, Qo) < TOL
+    # cell state, mesh velocity, timestep (Sec. 4.2)
+    Ug, wg, dtg, hg = mm.cell_state(dev(Qo))
+    Uo, wo, dti, dto, ho = orc.cell_state(om, p, Qo)
+    assert hg == ho == 0
+    assert scaled_err(host(Ug), Uo) < TOL and scaled_err(host(wg), wo) < TOL
+    assert abs(dtg - dto) <= TOL * dto
+    # gradients with and without the S10 limiter (Sec. 4.1)
+    for limit in (False, True):
+        Gg = host(mm.gradients(dev(Uo), limit=limit))
+        Go = orc.gradient(om, p, Uo, limit=limit)
+        assert scaled_err(Gg, Go) < TOL, f"limit={limit}"
+    # predictor (Sec. 4.1)
+    dt = 0.5 * dto
+    Uhg = host(mm.predict(dev(Uo), dev(Go), dev(wo), dt))
+    Uho, _ = orc.predict(om, p, Uo, Go, wo, dt)
+    assert scaled_err(Uhg, Uho) < TOL
+    # face fluxes summed per cell (Sec. 4 items 1-5)
+    Gho = orc.gradient(om, p, Uho, limit=True)
+    dQg = host(mm.fluxes(dev(Uho), dev(Gho), dev(wo), dt))
+    dQo, _ = orc.fluxes(om, p, Uho, Gho, wo, dt)
+    assert scaled_err(dQg, dQo) < TOL
+
+
+def _run_steps(orc, wl, nsteps, precision="fp64", **over):
+    import paper_1707_05333_amd as M
+    import torch
+    params = dict(wl.params)
+    params.update(over)
+    p = orc.make_params(wl.box, **params)
+    om = orc.tessellate(wl.pos, wl.box)
+    Q0 = orc.init_charges(om, p, wl.prim)
+    if wl.energy_cells is not None:
+        Q0[wl.energy_cells, 4] += wl.energy_amount
+    mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, precision=precision, **params))
+    pos_g, Q_g = dev(wl.pos), dev(Q0)
+    w_g = torch.empty_like(pos_g)
+    pos_o, Q_o = wl.pos.copy(), Q0.copy()
+    for k in range(nsteps):
+        info = mm.step(pos_g, w_g, Q_g)
+        pos_o, Q_o, w_o, dt_o, cnt = orc.step(pos_o, Q_o, p)
+        assert abs(info["dt"] - dt_o) <= TOL * dt_o, f"step {k}: dt {info['dt']} vs {dt_o}"
+        assert info["floor_hits"] == list(cnt)
+    return host(pos_g), host(Q_g), host(w_g), pos_o, Q_o, w_o
+
+
+def test_step_parity_c1(orc):
+    wl = W.c1_uniform_random_velocity()
+    _print_case("step c1", n=wl.n)
+    pg, Qg, wg, po, Qo, wo = _run_steps(orc, wl, 1)
+    assert scaled_err(Qg, Qo) < TOL
+    assert np.abs(pg - po).max() < TOL
+    assert scaled_err(wg, wo) < TOL
+
+
+def test_step_parity_sod_strip(orc):
+    wl = W.c2_sod(shape=(64, 8, 8), box=(4.0, 0.5, 0.5))
+    _print_case("step sod strip", n=wl.n, steps=5)
+    pg, Qg, wg, po, Qo, wo = _run_steps(orc, wl, 5)
+    assert scaled_err(Qg, Qo) < TOL
+    assert np.abs(pg - po).max() < TOL
+
+
+def test_step_parity_poisson_smooth(orc):
+    box = (1.0, 1.0, 1.0)
+    wl = W.random_smooth_state(W.poisson_points(2500, box, seed=9), box, seed=9, amp=0.2)
+    _print_case("step poisson", n=wl.n, steps=2)
+    pg, Qg, wg, po, Qo, wo = _run_steps(orc, wl, 2)
+    assert scaled_err(Qg, Qo) < TOL
+    assert np.abs(pg - po).max() < TOL
+
+
+def test_step_parity_blast(orc):
+    wl = W.c3_point_blast(n_side=16)
+    _print_case("step blast", n=wl.n, steps=3)
+    pg, Qg, wg, po, Qo, wo = _run_steps(orc, wl, 3)
+    assert scaled_err(Qg, Qo) < TOL
+
+
+def test_uniform_state_and_conservation_on_gpu(orc):
+    import paper_1707_05333_amd as M
+    import torch
+    box = (1.0, 1.0, 1.0)
+    wl = W.uniform_state(W.jittered_lattice((10, 10, 10), box, seed=4), box, vel=(0.3, -0.2, 0.1))
+    _print_case("uniform", n=wl.n)
+    mm = M.MovingMesh(wl.n, M.make_params(box=box, **wl.params))
+    mm.tessellate(dev(wl.pos))
+    Q = mm.init_charges(dev(wl.prim))
+    U0 = host(Q) / host(mm.mesh_export().V)[:, None]
+    pos = dev(wl.pos)
+    w = torch.empty_like(pos)
+    S0 = host(Q).sum(axis=0)
+    for _ in range(10):
+        mm.step(pos, w, Q)
+    mm.tessellate(pos)
+    U1 = host(Q) / host(mm.mesh_export().V)[:, None]
+    assert np.abs(U1 / U0 - 1).max() < 1e-12
+    assert np.all(np.abs(host(Q).sum(axis=0) - S0) <= 1e-13 * np.abs(host(Q)).sum(axis=0))
+
+
+def test_deterministic_and_resumable(orc):
+    # Two runs give bitwise-identical states; a run split with a copy of
+    # (pos, Q) in between equals the uninterrupted run (restart, Sec. 4.3).
+    import paper_1707_05333_amd as M
+    import torch
+    wl = W.c2_sod(shape=(32, 8, 8), box=(4.0, 1.0, 1.0))
+    _print_case("determinism", n=wl.n)
+    p = orc.make_params(wl.box, **wl.params)
+    om = orc.tessellate(wl.pos, wl.box)
+    Q0 = orc.init_charges(om, p, wl.prim)
+
+    def run(nsteps, pos, Q):
+        mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, **wl.params))
+        w = torch.empty_like(pos)
+        for _ in range(nsteps):
+            mm.step(pos, w, Q)
+        return pos, Q
+
+    a = run(6, dev(wl.pos), dev(Q0))
+    b = run(6, dev(wl.pos), dev(Q0))
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    c = run(2, dev(wl.pos), dev(Q0))
+    c = run(4, c[0].cpu().clone().cuda(), c[1].cpu().clone().cuda())
+    assert torch.equal(a[0], c[0]) and torch.equal(a[1], c[1])
+
+
+def test_error_paths(orc):
+    import paper_1707_05333_amd as M
+    import torch
+    mm = M.MovingMesh(100, M.make_params(box=(1, 1, 1)))
+    bad = dev(np.array([[0.5, 0.5, 1.5]] + [[0.1 * (k % 9) + 0.05, 0.3, 0.4] for k in range(7)]))
+    with pytest.raises(M.MMError) as e:
+        mm.tessellate(bad)
+    assert e.value.name == "MM_EINVAL"
+    with pytest.raises(M.MMError) as e:
+        mm.tessellate(dev(W.jittered_lattice((5, 5, 5), (1, 1, 1))))   # 125 > capacity 100
+    assert e.value.name == "MM_EINVAL"
+    fresh = M.MovingMesh(10, M.make_params(box=(1, 1, 1)))
+    with pytest.raises(M.MMError) as e:
+        fresh.gradients(torch.zeros(0, 5, dtype=torch.float64, device="cuda"))
+    assert e.value.name == "MM_ESTATE"
+    small = M.MovingMesh(64, M.make_params(box=(1, 1, 1)), face_capacity=10)
+    with pytest.raises(M.MMError) as e:
+        small.tessellate(dev(W.jittered_lattice((4, 4, 4), (1, 1, 1), seed=1)))
+    assert e.value.name == "MM_ECAPACITY"
