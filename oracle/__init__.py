@@ -68,6 +68,8 @@ def lib():
         vp = ctypes.c_void_p
         L.orc_mesh_build.restype = vp
         L.orc_mesh_build.argtypes = [ctypes.c_int64, _dp, _dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.orc_mesh_build_subset.restype = vp
+        L.orc_mesh_build_subset.argtypes = [ctypes.c_int64, _dp, _dp, _i64p, ctypes.c_int64]
         L.orc_mesh_free.argtypes = [vp]
         L.orc_mesh_status.argtypes = [vp]
         L.orc_mesh_status.restype = ctypes.c_int32
@@ -158,12 +160,18 @@ class Mesh:
             pass
 
 
-def tessellate(pos, box, method="grid", certificate=False, exhaustive=False) -> Mesh:
+def tessellate(pos, box, method="grid", certificate=False, exhaustive=False, subset=None) -> Mesh:
+    """Oracle tessellation.  With `subset` (cell indices) only those cells
+    are built (grid path, certificate included); the others have no faces."""
     pos = _f64(pos)
     n = pos.shape[0]
     b = _f64(box)
-    h = lib().orc_mesh_build(n, _p(pos), _p(b), 1 if method == "grid" else 0,
-                             1 if certificate else 0, 1 if exhaustive else 0)
+    if subset is not None:
+        idx = np.ascontiguousarray(subset, dtype=np.int64)
+        h = lib().orc_mesh_build_subset(n, _p(pos), _p(b), idx.ctypes.data_as(_i64p), idx.shape[0])
+    else:
+        h = lib().orc_mesh_build(n, _p(pos), _p(b), 1 if method == "grid" else 0,
+                                 1 if certificate else 0, 1 if exhaustive else 0)
     L = lib()
     nf = int(L.orc_mesh_nfaces(h))
     V = np.empty(n); c = np.empty((n, 3)); vtet = np.empty(n); rmax = np.empty(n)

@@ -904,6 +904,26 @@ void* orc_mesh_build(int64_t n, const double* pos, const double* box, int32_t me
   return M;
 }
 
+// Only the cells listed in idx (grid path, with certificate); the other
+// cells are left empty.  For sampled checks on large point sets.
+void* orc_mesh_build_subset(int64_t n, const double* pos, const double* box, const int64_t* idx, int64_t m) {
+  Mesh* M = new Mesh();
+  M->n = n;
+  M->L = {box[0], box[1], box[2]};
+  M->r.resize(n);
+  for (int64_t i = 0; i < n; ++i) M->r[i] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+  M->cells.resize(n);
+  const Grid G = make_grid(*M, 8.0);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t t = 0; t < m; ++t) build_cell_grid(*M, G, (int)idx[t], M->cells[idx[t]], true);
+  for (int64_t t = 0; t < m; ++t) {
+    const CellOut& C = M->cells[idx[t]];
+    if (C.delta == C.delta) M->delta_min = std::min(M->delta_min, C.delta);
+    if (C.status) M->status = 1;
+  }
+  return M;
+}
+
 void orc_mesh_free(void* m) { delete (Mesh*)m; }
 int32_t orc_mesh_status(void* m) { return ((Mesh*)m)->status; }
 double orc_mesh_delta_min(void* m) { return ((Mesh*)m)->delta_min; }

@@ -32,7 +32,10 @@ namespace mm {
 
 namespace {
 
-constexpr int kWaves = 2;   // cells (wavefronts) per workgroup
+#ifndef MM_TESS_WAVES
+#define MM_TESS_WAVES 1
+#endif
+constexpr int kWaves = MM_TESS_WAVES;   // cells (wavefronts) per workgroup
 
 struct __align__(16) TessLds {
   double4 pl[kPlanes];                 // plane: d.x, d.y, d.z, h
@@ -45,6 +48,7 @@ struct __align__(16) TessLds {
   uint8_t E[kPlanes * kPlanes];
   uint8_t order[kCands];
   uint8_t freelist[kVerts];
+  uint16_t elist[kVerts];              // boundary edges of one cut: x | y << 8
 };
 
 struct TessArgs {
@@ -160,6 +164,7 @@ struct CellRegs {
   uint32_t t0, t1;
   double v0x, v0y, v0z, v1x, v1y, v1z;
   double rmax2;
+  int np;   // plane slots handed out so far
 };
 
 // Starting cell: the box r +- L/2, bounded by the bisectors of the
@@ -190,6 +195,7 @@ __device__ void init_box(TessLds& S, const GridParams& g, CellRegs& C) {
   wave_sync();
   C.L0 = 0xffull;
   C.L1 = 0ull;
+  C.np = 6;
   C.t0 = S.tri[lane];
   C.t1 = S.tri[lane + 64];
   C.v0x = S.vx[lane]; C.v0y = S.vy[lane]; C.v0z = S.vz[lane];
@@ -295,14 +301,20 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     const unsigned long long M0 = __ballot(out0), M1 = __ballot(out1);
     if ((M0 | M1) == 0ull) continue;
 
-    // Plane slot for the new face: lowest slot no surviving vertex uses.
+    // Plane slot for the new face: the next unused slot while there is one,
+    // then the lowest slot no surviving vertex uses.
     const bool kept0 = live0 && !out0, kept1 = live1 && !out1;
-    unsigned long long u = 0ull;
-    if (kept0) u |= plane_bits(C.t0);
-    if (kept1) u |= plane_bits(C.t1);
-    const unsigned long long used = wave_or(u);
-    if (used == ~0ull) return F_PLANES;
-    const int p = __builtin_ctzll(~used);
+    int p;
+    if (C.np < kPlanes) {
+      p = C.np++;
+    } else {
+      unsigned long long u = 0ull;
+      if (kept0) u |= plane_bits(C.t0);
+      if (kept1) u |= plane_bits(C.t1);
+      const unsigned long long used = wave_or(u);
+      if (used == ~0ull) return F_PLANES;
+      p = __builtin_ctzll(~used);
+    }
 
     // Boundary of the removed cap: edges of removed vertices whose
     // neighbour across the edge survives (bit k of bm: edge k of the slot).
@@ -337,20 +349,27 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
       S.pl[p] = make_double4(q.x, q.y, q.z, h);
       S.pcand[p] = S.cjk[c];   // the neighbour itself: later shells reuse the candidate slots
     }
-    wave_sync();   // every E lookup above is done before any write below
-
+    // Boundary edges into a list, in prefix order.
     int e = pre;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const uint32_t T = sl ? C.t1 : C.t0;
       const int bm = sl ? bm1 : bm0;
       const int ta = T & 255, tb = (T >> 8) & 255, tc = (T >> 16) & 255;
-#pragma unroll
-      for (int k3 = 0; k3 < 3; ++k3) {
-        if (!((bm >> k3) & 1)) continue;
-        const int x = k3 == 0 ? ta : (k3 == 1 ? tb : tc);
-        const int y = k3 == 0 ? tb : (k3 == 1 ? tc : ta);
-        const int ns = S.freelist[e++];
+      if (bm & 1) S.elist[e++] = (uint16_t)(ta | (tb << 8));
+      if (bm & 2) S.elist[e++] = (uint16_t)(tb | (tc << 8));
+      if (bm & 4) S.elist[e++] = (uint16_t)(tc | (ta << 8));
+    }
+    wave_sync();   // every E lookup above is done before any write below
+
+    // One new vertex per lane: the fan of triangles (x, y, p) around the
+    // new face, in the free slots.
+    for (int base = 0; base < B; base += 64) {
+      const int ee = base + lane;
+      if (ee < B) {
+        const int xy = S.elist[ee];
+        const int x = xy & 255, y = xy >> 8;
+        const int ns = S.freelist[ee];
         S.tri[ns] = (uint32_t)(x | (y << 8) | (p << 16));
         double nx, ny, nz;
         intersect3(S.pl[x], S.pl[y], S.pl[p], nx, ny, nz);
@@ -537,9 +556,14 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
       return;
     }
   } else {
+    // Shells [lo2, hi2) of growing radius.  Each next shell reaches twice
+    // the current farthest vertex but at most twice the previous radius, so
+    // a cell that still touched the starting box after the first pass does
+    // not ask for a stencil as wide as the box at once.
     const double rm2 = A.rmax2[s];
+    const double rf2 = g.r_filter * g.r_filter;
     double lo2 = 0.0;
-    double hi2 = rm2 > 0.0 ? 4.0 * rm2 * (1.0 + 1e-9) : g.r_filter * g.r_filter;
+    double hi2 = rm2 > 0.0 ? fmin(4.0 * rm2 * (1.0 + 1e-9), 4.0 * rf2) : rf2;
     bool done = false;
     for (int shell = 0; shell < 32 && !done; ++shell) {
       const int ring = ring_for(g, edge, hi2);
@@ -564,8 +588,9 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
       if (4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)) {
         done = true;
       } else {
+        const double grow = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
         lo2 = hi2;
-        hi2 = 4.0 * C.rmax2 * (1.0 + 1e-9);
+        hi2 = grow;
       }
     }
     if (!done) {

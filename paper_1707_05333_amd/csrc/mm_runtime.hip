@@ -38,6 +38,7 @@ struct mm_ctx {
   bool have_mesh = false;
   int64_t n_mesh = 0, n_faces = 0;
   GridParams grid{};
+  double rfac = 2.0;   // first-pass candidate radius in mean spacings (adapted per call)
   // Stage timing.
   bool timing = false;
   hipEvent_t ev[9] = {};
@@ -100,17 +101,18 @@ HydroParams hydro_params(const mm_params& p) {
   return h;
 }
 
-// Bucket grid for n points.  First-pass candidates are the images within
-// r_filter = 2.5 mean spacings (twice the farthest vertex of a cell of a
-// jittered lattice is about 1.75 spacings); buckets are r_filter / 2 wide so
-// a two-ring stencil covers the filter sphere.
-GridParams make_grid(const mm_params& p, int64_t n, int64_t nbcap) {
+// Bucket grid for n points.  Buckets are about one mean spacing wide
+// whatever the candidate radius, so the cell order (bucket, then caller
+// index) and with it every result do not depend on the radius.  First-pass
+// candidates are the images within r_filter = rfac mean spacings (twice the
+// farthest vertex of a cell of a jittered lattice is about 1.75 spacings);
+// the stencil half-width is the number of buckets that covers r_filter.
+GridParams make_grid(const mm_params& p, int64_t n, int64_t nbcap, double rfac) {
   GridParams g;
   const double vol = p.box[0] * p.box[1] * p.box[2];
   const double spacing = std::cbrt(vol / (double)n);
-  g.ring = 2;
-  g.r_filter = 2.5 * spacing;
-  double h = g.r_filter / g.ring;
+  g.r_filter = rfac * spacing;
+  double h = spacing;
   for (;;) {
     int64_t nbt = 1;
     for (int a = 0; a < 3; ++a) {
@@ -128,6 +130,8 @@ GridParams make_grid(const mm_params& p, int64_t n, int64_t nbcap) {
     g.inv_hb[a] = 1.0 / g.hb[a];
     g.L[a] = p.box[a];
   }
+  const double hmin = std::min(g.hb[0], std::min(g.hb[1], g.hb[2]));
+  g.ring = std::max(1, (int)std::ceil(g.r_filter / hmin * (1.0 - 1e-12)));
   // Few buckets along an axis: the stencil may not exceed the axis' buckets
   // (images beyond one box length are outside the scheme's premise).
   g.ring = std::min(g.ring, std::min(g.nb[0], std::min(g.nb[1], g.nb[2])));
@@ -188,13 +192,21 @@ mm_status readback(mm_ctx* c) {
   return MM_OK;
 }
 
+// The first-pass radius only changes how much work goes to the shell pass,
+// never the cells (clipping is always in order of distance): widen it when
+// many cells were deferred, narrow it slowly when none were.
+void adapt_filter(mm_ctx* c, int deferred, int64_t n) {
+  if (deferred > 0.02 * (double)n) c->rfac = std::min(c->rfac * 1.15, 3.0);
+  else if (deferred < 0.002 * (double)n) c->rfac = std::max(c->rfac * 0.98, 1.9);
+}
+
 void mark(mm_ctx* c, int k) {
   if (c->timing) (void)hipEventRecord(c->ev[k], c->stream);
 }
 
 // Enqueues sort, cell construction and mesh assembly for n positions.
 void enqueue_tessellation(mm_ctx* c, int64_t n, const double* pos) {
-  c->grid = make_grid(c->p, n, c->nbcap);
+  c->grid = make_grid(c->p, n, c->nbcap, c->rfac);
   mark(c, 0);
   launch_sort(pos, n, c->grid, c->bcount, c->boff, c->scan_tmp, c->key, c->perm, c->spos, c->st, c->stream);
   mark(c, 1);
@@ -355,6 +367,7 @@ mm_status mm_tessellate(mm_ctx* c, int64_t n, const double* pos, mm_step_info* i
   if (mm_status r = check_status(c, s)) return r;
   c->n_mesh = n;
   c->n_faces = (int64_t)s.n_faces;
+  adapt_filter(c, s.n_deferred, n);
   c->have_mesh = true;
   return MM_OK;
 }
@@ -549,6 +562,7 @@ mm_status mm_step(mm_ctx* c, int64_t n, double* pos, double* w, double* Q, doubl
   if (mm_status r = check_status(c, s)) return r;
   c->n_mesh = n;
   c->n_faces = (int64_t)s.n_faces;
+  adapt_filter(c, s.n_deferred, n);
   c->have_mesh = true;
   return MM_OK;
 }
