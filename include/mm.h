@@ -10,7 +10,7 @@
  *   the half-step predictor (Sec. 4.1),
  *   limited linear reconstruction to the face centres (Sec. 4.1),
  *   HLLC fluxes in the frame of each moving face (Sec. 4, items 1-5),
- *   the conserved-charge update (Sec. 4, eq. "time evolution"),
+ *   the conserved-charge update (Sec. 4, update of the charges),
  *   mesh velocities and the CFL timestep (Sec. 4.2), and the drift.
  *
  * Conventions shared by every call:
@@ -55,7 +55,8 @@ typedef enum {
   MM_EDEGENERATE = -4,  /* tessellation failed: incomplete cell, asymmetric faces or box too small */
   MM_ENONFINITE = -5,   /* a state became NaN or infinite */
   MM_EHIP = -6,         /* a HIP runtime call failed */
-  MM_ESTATE = -7        /* call out of order, e.g. mm_gradients before any mm_tessellate */
+  MM_ESTATE = -7,       /* call out of order, e.g. mm_gradients before any mm_tessellate */
+  MM_EFULL = -8         /* batch admission: not enough room now (retry after an eviction) */
 } mm_status;
 
 enum { MM_FP64 = 0, MM_MIXED = 1 };
@@ -106,7 +107,7 @@ typedef struct {
   const double *pos;         /* dev [n][3]: generator positions, internal order */
   const double *geo;         /* dev [n][4]: volume V, then centroid minus generator (3) */
   const void *faces;         /* dev [n_faces] records of 48 bytes: int32 i, j (internal cells, i the
-                                owner), int32 image code of j as (kx+1) + 3(ky+1) + 9(kz+1), int32 pad,
+                                owner), int32 image code of j as (kx+1) + 3(ky+1) + 9(kz+1), int32 0,
                                 double area A, double[3] face centroid minus r_i */
 } mm_mesh_view;
 
@@ -174,8 +175,8 @@ mm_status mm_gradients(mm_ctx *ctx, const void *U, void *grad, int32_t limit);
 mm_status mm_predict(mm_ctx *ctx, const void *U, const void *grad, const double *w, double dt,
                      void *U_half);
 
-/* Face fluxes and their sum per cell (Sec. 4, items 1-5 and eq. "time
- * evolution"; Sec. 4.1 reconstruction): for each face, the face velocity,
+/* Face fluxes and their sum per cell (Sec. 4, items 1-5 and the update of
+ * the charges; Sec. 4.1 reconstruction): for each face, the face velocity,
  * limited reconstruction of U_half from both sides to the face centre,
  * face floors, HLLC in the face frame, boost back; then
  * dQ_i = - sum_faces dt A F (F from i toward its neighbour).
@@ -206,6 +207,129 @@ const char *mm_version(void);
  * mm_get_stage_ms writes up to n_stages milliseconds of the last step. */
 mm_status mm_set_stage_timing(mm_ctx *ctx, int32_t enable);
 mm_status mm_get_stage_ms(const mm_ctx *ctx, double *ms, int32_t n_stages);
+
+/* ---------------------------------------------------------------------------
+ * Batched serving.
+ *
+ * A batch keeps many independent simulations resident on the device, each
+ * with its own periodic box, point count, parameters (precision excepted:
+ * one per batch) and timestep, and advances all of them together: one
+ * mm_batch_step runs every kernel of the step once, over the cells of all
+ * resident simulations (the paper's step, Sec. 2 outline, per simulation).
+ * Simulations are admitted while their device footprint fits the batch's
+ * memory budget and leave when evicted, so new ones join between the steps
+ * of those already in flight (continuous batching).  A simulation's results
+ * are bitwise the same alone and in any mix: its cells keep their relative
+ * order in every launch and no kernel combines data of two simulations.
+ * Positions and charges of a resident simulation live in the batch;
+ * mm_batch_read copies them out.  A batch is not thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct mm_batch mm_batch;
+
+/* Per-simulation report of one mm_batch_step. */
+typedef struct {
+  int32_t sim;               /* simulation id from mm_batch_admit */
+  int32_t status;            /* MM_OK, or the error of this simulation's step (it is then parked:
+                                no longer stepped, still resident until evicted) */
+  int64_t steps;             /* steps completed so far */
+  int64_t n;                 /* points */
+  double dt;                 /* timestep of this step */
+  double t;                  /* simulated time after the step */
+  int64_t floor_hits[4];     /* as in mm_step_info */
+  int32_t flags;             /* internal failure bits of this simulation */
+  int32_t reserved;
+} mm_sim_info;
+
+/* Device bytes one simulation of n points takes in a batch of the given
+ * precision (the unit of admission). */
+int64_t mm_batch_footprint(int32_t precision, int64_t n);
+
+/* Creates a batch on the current HIP device that reserves, once, the device
+ * memory for hbm_budget bytes of simulations (mm_batch_footprint each) and at
+ * most max_sims of them.  precision: MM_FP64 or MM_MIXED for every
+ * simulation of the batch.  hip_stream: hipStream_t (NULL: null stream).
+ * Errors: MM_EINVAL, MM_ENOMEM, MM_EHIP (message: mm_batch_last_error(NULL)). */
+mm_status mm_batch_create(mm_batch **out, int32_t precision, int64_t hbm_budget, int32_t max_sims,
+                          void *hip_stream);
+mm_status mm_batch_destroy(mm_batch *b);
+
+/* Admits a simulation of n points: p its parameters (p->precision must be
+ * the batch's), pos [n][3] its generator positions in [0, L), prim [n][5]
+ * its primitive state (rho, vx, vy, vz, P) at the generators, both in caller
+ * order, in device or host memory (copied; the caller keeps ownership),
+ * dt_max the cap of each of its timesteps.  Its charges are formed from the
+ * first tessellation of its first step (Sec. 4.3).  *sim receives its id.
+ * Errors: MM_EINVAL; MM_EFULL when its footprint, a slot range or a
+ * simulation slot is not free now; MM_ECAPACITY when it could never fit. */
+mm_status mm_batch_admit(mm_batch *b, const mm_params *p, int64_t n, const double *pos, const double *prim,
+                         double dt_max, int32_t *sim);
+
+/* One step of every resident simulation that has not failed, in one set of
+ * launches.  info (host, may be NULL) receives up to info_cap reports, one
+ * per simulation stepped, *n_info (may be NULL) their number.  Waits for
+ * the stream once.  Returns MM_OK when the launches ran; errors of single
+ * simulations are in their reports.  MM_ECAPACITY if a batch-wide capacity
+ * was exceeded (then every stepped simulation reports it). */
+mm_status mm_batch_step(mm_batch *b, mm_sim_info *info, int32_t info_cap, int32_t *n_info);
+
+/* Copies a simulation's state out, in its caller order: pos [n][3],
+ * Q [n][5] charges, w [n][3] mesh velocities of its last step; device or
+ * host memory, any may be NULL.  Waits for the copies.  MM_ESTATE before
+ * its first step. */
+mm_status mm_batch_read(mm_batch *b, int32_t sim, double *pos, double *Q, double *w);
+
+/* Removes a simulation and frees its room. */
+mm_status mm_batch_evict(mm_batch *b, int32_t sim);
+
+/* Occupancy: resident points and simulations, and the point capacity. */
+mm_status mm_batch_usage(const mm_batch *b, int64_t *cells, int64_t *cell_capacity, int32_t *sims);
+
+const char *mm_batch_last_error(const mm_batch *b);
+
+/* A request of the serving loop. */
+typedef struct {
+  double arrival;            /* seconds after the start of mm_serve (non-decreasing over requests) */
+  int64_t n;                 /* points */
+  const double *pos;         /* [n][3] device or host, caller order */
+  const double *prim;        /* [n][5] device or host */
+  mm_params params;
+  double dt_max;             /* cap of each timestep */
+  int32_t steps;             /* steps to run */
+  int32_t reserved;
+  double *pos_out;           /* [n][3] device or host: positions after the last step (may be NULL) */
+  double *Q_out;             /* [n][5] device or host: charges after the last step (may be NULL) */
+} mm_request;
+
+typedef struct {
+  double admitted;           /* seconds after the start */
+  double finished;
+  int32_t status;            /* MM_OK, or the error that ended the request */
+  int32_t steps;             /* steps completed */
+  double t;                  /* simulated time reached */
+} mm_request_result;
+
+typedef struct {
+  double wall;               /* seconds from the start to the last completion */
+  int64_t batch_steps;       /* mm_batch_step calls */
+  int64_t sim_steps;         /* simulation steps completed */
+  int64_t cell_updates;      /* sum over simulation steps of their points */
+  double cell_updates_per_s;
+  double step_p50, step_p99, step_mean;   /* ms, over simulation steps: the duration of the batch
+                                             step each took part in, readback included */
+  double turnaround_p50, turnaround_p99;  /* s, over requests: finished - arrival */
+  int32_t max_resident;      /* most simulations resident at once */
+  int32_t reserved;
+} mm_serve_stats;
+
+/* Serving loop over a request trace on an empty batch: requests are
+ * admitted first come, first served, as soon as they have arrived (wall
+ * clock from the call) and fit; every resident simulation advances one step
+ * per batch step; a simulation that completes its steps (or fails) is read
+ * out to pos_out/Q_out and evicted, and its room goes to the next arrivals.
+ * res [n_req] and stats (host) receive the outcome.  Returns MM_OK unless
+ * the loop itself could not run. */
+mm_status mm_serve(mm_batch *b, const mm_request *req, int32_t n_req, mm_request_result *res,
+                   mm_serve_stats *stats);
 
 #ifdef __cplusplus
 }

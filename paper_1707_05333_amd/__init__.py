@@ -17,7 +17,7 @@ from .build import LIB_PATH
 
 MM_FP64, MM_MIXED = 0, 1
 _STATUS = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_ECAPACITY", -4: "MM_EDEGENERATE",
-           -5: "MM_ENONFINITE", -6: "MM_EHIP", -7: "MM_ESTATE"}
+           -5: "MM_ENONFINITE", -6: "MM_EHIP", -7: "MM_ESTATE", -8: "MM_EFULL"}
 N_STAGES = 8
 STAGE_NAMES = ("sort", "cells", "mesh", "cell_state", "gradient_predict", "gradient_half", "flux", "update")
 
@@ -75,6 +75,69 @@ class MeshView(ctypes.Structure):
     ]
 
 
+class SimInfo(ctypes.Structure):
+    _fields_ = [
+        ("sim", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("steps", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("dt", ctypes.c_double),
+        ("t", ctypes.c_double),
+        ("floor_hits", ctypes.c_int64 * 4),
+        ("flags", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return dict(sim=self.sim, status=self.status, steps=self.steps, n=self.n, dt=self.dt, t=self.t,
+                    floor_hits=list(self.floor_hits), flags=self.flags)
+
+
+class Request(ctypes.Structure):
+    _fields_ = [
+        ("arrival", ctypes.c_double),
+        ("n", ctypes.c_int64),
+        ("pos", ctypes.c_void_p),
+        ("prim", ctypes.c_void_p),
+        ("params", Params),
+        ("dt_max", ctypes.c_double),
+        ("steps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("pos_out", ctypes.c_void_p),
+        ("Q_out", ctypes.c_void_p),
+    ]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [
+        ("admitted", ctypes.c_double),
+        ("finished", ctypes.c_double),
+        ("status", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("t", ctypes.c_double),
+    ]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [
+        ("wall", ctypes.c_double),
+        ("batch_steps", ctypes.c_int64),
+        ("sim_steps", ctypes.c_int64),
+        ("cell_updates", ctypes.c_int64),
+        ("cell_updates_per_s", ctypes.c_double),
+        ("step_p50", ctypes.c_double),
+        ("step_p99", ctypes.c_double),
+        ("step_mean", ctypes.c_double),
+        ("turnaround_p50", ctypes.c_double),
+        ("turnaround_p99", ctypes.c_double),
+        ("max_resident", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 # Functions declared in include/mm.h, with their ctypes signatures.
 _vp, _i64, _i32, _d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
 SIGNATURES = {
@@ -95,6 +158,17 @@ SIGNATURES = {
     "mm_version": (ctypes.c_char_p, []),
     "mm_set_stage_timing": (_i32, [_vp, _i32]),
     "mm_get_stage_ms": (_i32, [_vp, ctypes.POINTER(_d), _i32]),
+    "mm_batch_footprint": (_i64, [_i32, _i64]),
+    "mm_batch_create": (_i32, [ctypes.POINTER(_vp), _i32, _i64, _i32, _vp]),
+    "mm_batch_destroy": (_i32, [_vp]),
+    "mm_batch_admit": (_i32, [_vp, ctypes.POINTER(Params), _i64, _vp, _vp, _d, ctypes.POINTER(_i32)]),
+    "mm_batch_step": (_i32, [_vp, ctypes.POINTER(SimInfo), _i32, ctypes.POINTER(_i32)]),
+    "mm_batch_read": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "mm_batch_evict": (_i32, [_vp, _i32]),
+    "mm_batch_usage": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    "mm_batch_last_error": (ctypes.c_char_p, [_vp]),
+    "mm_serve": (_i32, [_vp, ctypes.POINTER(Request), _i32, ctypes.POINTER(RequestResult),
+                        ctypes.POINTER(ServeStats)]),
 }
 
 _lib = None
@@ -295,6 +369,122 @@ class MovingMesh:
         arr = (ctypes.c_double * N_STAGES)()
         self._check(self.lib.mm_get_stage_ms(self.ctx, arr, N_STAGES))
         return dict(zip(STAGE_NAMES, list(arr)))
+
+
+def batch_footprint(n: int, precision="mixed") -> int:
+    """Device bytes one simulation of n points takes in a batch."""
+    prec = MM_MIXED if precision in ("mixed", MM_MIXED) else MM_FP64
+    return int(load_library().mm_batch_footprint(prec, int(n)))
+
+
+class Batch:
+    """Many simulations resident together, stepped in shared launches."""
+
+    def __init__(self, hbm_budget: int, max_sims: int = 1024, precision="mixed", stream=None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.precision = MM_MIXED if precision in ("mixed", MM_MIXED) else MM_FP64
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        self.max_sims = int(max_sims)
+        self.b = ctypes.c_void_p()
+        rc = self.lib.mm_batch_create(ctypes.byref(self.b), self.precision, int(hbm_budget), self.max_sims,
+                                      ctypes.c_void_p(s.cuda_stream))
+        if rc != 0:
+            raise MMError(rc, "mm_batch_create failed: " + self.lib.mm_batch_last_error(None).decode())
+        self.n_of = {}
+
+    def _check(self, rc):
+        if rc != 0:
+            raise MMError(rc, self.lib.mm_batch_last_error(self.b).decode())
+
+    def close(self):
+        if getattr(self, "b", None) and self.b.value:
+            self.lib.mm_batch_destroy(self.b)
+            self.b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, params: Params, pos, prim, dt_max=math.inf) -> int:
+        """Admits a simulation (pos [n][3], prim [n][5] float64 CUDA tensors); returns its id."""
+        torch = self._torch
+        n = int(pos.shape[0])
+        sim = ctypes.c_int32()
+        self._check(self.lib.mm_batch_admit(self.b, ctypes.byref(params), n,
+                                            _ptr(pos, torch.float64, (n, 3), "pos"),
+                                            _ptr(prim, torch.float64, (n, 5), "prim"), float(dt_max),
+                                            ctypes.byref(sim)))
+        self.n_of[sim.value] = n
+        return sim.value
+
+    def try_admit(self, params: Params, pos, prim, dt_max=math.inf):
+        """As admit, but returns None when the batch is full now."""
+        try:
+            return self.admit(params, pos, prim, dt_max)
+        except MMError as e:
+            if e.name == "MM_EFULL":
+                return None
+            raise
+
+    def step(self) -> list:
+        """One step of every resident simulation; a report per simulation."""
+        info = (SimInfo * self.max_sims)()
+        k = ctypes.c_int32()
+        self._check(self.lib.mm_batch_step(self.b, info, self.max_sims, ctypes.byref(k)))
+        return [info[i].as_dict() for i in range(k.value)]
+
+    def read(self, sim: int):
+        """(pos, Q, w) of a resident simulation, as new CUDA tensors."""
+        torch = self._torch
+        if sim not in self.n_of:
+            self._check(self.lib.mm_batch_read(self.b, int(sim), None, None, None))
+            raise MMError(-1, f"simulation {sim} was not admitted through this object")
+        n = self.n_of[sim]
+        kw = dict(dtype=torch.float64, device=self.device)
+        pos, Q, w = torch.empty(n, 3, **kw), torch.empty(n, 5, **kw), torch.empty(n, 3, **kw)
+        self._check(self.lib.mm_batch_read(self.b, int(sim), _ptr(pos), _ptr(Q), _ptr(w)))
+        return pos, Q, w
+
+    def evict(self, sim: int):
+        self._check(self.lib.mm_batch_evict(self.b, int(sim)))
+        self.n_of.pop(sim, None)
+
+    def usage(self) -> dict:
+        cells, cap, sims = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        self._check(self.lib.mm_batch_usage(self.b, ctypes.byref(cells), ctypes.byref(cap), ctypes.byref(sims)))
+        return dict(cells=cells.value, cell_capacity=cap.value, sims=sims.value)
+
+    def serve(self, requests: list):
+        """Runs the serving loop over requests, each a dict with arrival (s),
+        params, pos and prim (CUDA float64), steps, and optional dt_max,
+        pos_out and Q_out tensors.  Returns (results, stats) as dicts."""
+        torch = self._torch
+        n_req = len(requests)
+        arr = (Request * max(n_req, 1))()
+        for k, r in enumerate(requests):
+            n = int(r["pos"].shape[0])
+            q = arr[k]
+            q.arrival = float(r["arrival"])
+            q.n = n
+            q.pos = _ptr(r["pos"], torch.float64, (n, 3), "pos")
+            q.prim = _ptr(r["prim"], torch.float64, (n, 5), "prim")
+            q.params = r["params"]
+            q.dt_max = float(r.get("dt_max", math.inf))
+            q.steps = int(r["steps"])
+            q.pos_out = _ptr(r.get("pos_out"), torch.float64, (n, 3), "pos_out")
+            q.Q_out = _ptr(r.get("Q_out"), torch.float64, (n, 5), "Q_out")
+        res = (RequestResult * max(n_req, 1))()
+        stats = ServeStats()
+        self._check(self.lib.mm_serve(self.b, arr, n_req, res, ctypes.byref(stats)))
+        results = [dict(admitted=res[k].admitted, finished=res[k].finished, status=res[k].status,
+                        steps=res[k].steps, t=res[k].t) for k in range(n_req)]
+        return results, stats.as_dict()
 
 
 def version() -> str:

@@ -16,26 +16,6 @@ constexpr int kThreads = 256;
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-__device__ inline double dt_of(const DevStatus* src, double dt_fixed) {
-  if (!src) return dt_fixed;
-  const double d = __longlong_as_double((long long)src->dt_bits);
-  return fmin(d, dt_fixed);
-}
-
-// Sum of one integer per thread over the block, added to *dst by thread 0.
-__device__ void block_add(unsigned long long v, unsigned long long* dst) {
-  __shared__ unsigned long long red[kThreads / 64];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += red[k];
-    if (t) atomicAdd(dst, t);
-  }
-}
-
 // Floors of Sec. 4.1 on conserved densities: a density below the floor is
 // raised keeping velocity and pressure; a pressure below the floor is raised
 // keeping density and velocity.  Returns 1 if any floor fired.
@@ -177,16 +157,63 @@ __device__ inline T dm_factor(T theta, T dU, T D) {
 
 // ---------------------------------------------------------------------------
 
+// Merges a per-cell timestep into its segment's minimum.  A block whose
+// cells all belong to one segment (the usual case) reduces in LDS and issues
+// one atomic; otherwise each wavefront does, or each cell of a wavefront
+// that straddles segments.  Positive doubles order as their bit patterns.
+__device__ void seg_min_dt(double v, int seg, bool active, SegStatus* segst) {
+  __shared__ double red[kThreads / 64];
+  __shared__ int sseg0[kThreads / 64 + 1];
+  const int lane = __lane_id(), wid = threadIdx.x >> 6;
+  const unsigned long long act = __ballot(active);
+  const int first = act ? __ffsll((long long)act) - 1 : 0;
+  const int seg0 = __shfl(seg, first, 64);
+  const bool uniform = __ballot(active && seg != seg0) == 0ull;
+  double m = active ? v : 1e300;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+  if (lane == 0) {
+    red[wid] = m;
+    sseg0[wid] = !act ? -1 : (uniform ? seg0 : -2);   // -1: no cell, -2: mixed
+  }
+  __syncthreads();
+  int bseg = -1;
+  bool block_uniform = true;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+    const int q = sseg0[k];
+    if (q == -1) continue;
+    if (q == -2 || (bseg >= 0 && q != bseg)) block_uniform = false;
+    bseg = q;
+  }
+  if (block_uniform) {
+    if (threadIdx.x == 0 && bseg >= 0) {
+      double t = red[0];
+      for (int k = 1; k < (int)(blockDim.x >> 6); ++k) t = fmin(t, red[k]);
+      if (t < 1e300) atomicMin(&segst[bseg].dt_bits, (unsigned long long)__double_as_longlong(t));
+    }
+  } else if (uniform) {
+    if (lane == first && act && m < 1e300)
+      atomicMin(&segst[seg0].dt_bits, (unsigned long long)__double_as_longlong(m));
+  } else if (active && v < 1e300) {
+    atomicMin(&segst[seg].dt_bits, (unsigned long long)__double_as_longlong(v));
+  }
+}
+
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_cell_state(HydroParams hp, int64_t n, const double* __restrict__ Qc,
+__global__ __launch_bounds__(kThreads) void k_cell_state(const SegDesc* __restrict__ segs,
+                                                         const int32_t* __restrict__ sseg, int64_t n,
+                                                         const double* __restrict__ Qc,
                                                          const int32_t* __restrict__ perm,
                                                          const double* __restrict__ geo, double* __restrict__ Qs,
-                                                         R* __restrict__ U, double* __restrict__ w, DevStatus* st) {
-  __shared__ double red[kThreads / 64];
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                         R* __restrict__ U, double* __restrict__ w, DevStatus* st,
+                                                         SegStatus* segst) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  const bool active = s < n;
   double dti = 1e300;
-  int hit = 0, bad = 0;
-  if (s < n) {
+  int seg = 0;
+  if (active) {
+    seg = sseg[s];
+    const HydroParams& hp = segs[seg].hp;
     const int64_t q = perm[s];
     double Q[5], u[5];
 #pragma unroll
@@ -199,26 +226,29 @@ __global__ __launch_bounds__(kThreads) void k_cell_state(HydroParams hp, int64_t
     const double crx = geo[4 * s + 1], cry = geo[4 * s + 2], crz = geo[4 * s + 3];
 #pragma unroll
     for (int k = 0; k < 5; ++k) u[k] = Q[k] / V;
-    const double g1 = hp.gamma - 1.0;
-    hit = apply_floors(u, g1, hp.rho_floor, hp.p_floor);
+    const double gamma = hp.gamma, g1 = gamma - 1.0;
+    if (apply_floors(u, g1, hp.rho_floor, hp.p_floor)) atomicAdd(&segst[seg].floor_hits[0], 1ull);
     // Mesh velocity and timestep (Sec. 4.2).
     const double rho = u[0];
     const double vx = u[1] / rho, vy = u[2] / rho, vz = u[3] / rho;
     const double P = g1 * (u[4] - 0.5 * (u[1] * vx + u[2] * vy + u[3] * vz));
-    const double cs = sqrt(hp.gamma * P / rho);
+    const double cs = sqrt(gamma * P / rho);
     const double Rr = cbrt(3.0 * V / (4.0 * kPi));
     const double dn = sqrt(crx * crx + cry * cry + crz * crz);
+    const double zeta = hp.zeta;
     double ramp;
-    if (dn < 0.9 * hp.zeta * Rr) ramp = 0.0;
-    else if (dn <= 1.1 * hp.zeta * Rr) ramp = (dn - 0.9 * hp.zeta * Rr) / (0.2 * hp.zeta * Rr);
+    if (dn < 0.9 * zeta * Rr) ramp = 0.0;
+    else if (dn <= 1.1 * zeta * Rr) ramp = (dn - 0.9 * zeta * Rr) / (0.2 * zeta * Rr);
     else ramp = 1.0;
     double dwx = 0.0, dwy = 0.0, dwz = 0.0;
     if (dn > 0.0 && ramp > 0.0) {
-      dwx = hp.chi * cs * ramp * crx / dn;
-      dwy = hp.chi * cs * ramp * cry / dn;
-      dwz = hp.chi * cs * ramp * crz / dn;
+      const double chi = hp.chi;
+      dwx = chi * cs * ramp * crx / dn;
+      dwy = chi * cs * ramp * cry / dn;
+      dwz = chi * cs * ramp * crz / dn;
     }
-    const double wx = hp.eta * vx + dwx, wy = hp.eta * vy + dwy, wz = hp.eta * vz + dwz;
+    const double eta = hp.eta;
+    const double wx = eta * vx + dwx, wy = eta * vy + dwy, wz = eta * vz + dwz;
     const double rx = vx - wx, ry = vy - wy, rz = vz - wz;
     dti = hp.cfl * Rr / (cs + sqrt(rx * rx + ry * ry + rz * rz));
     w[3 * s] = wx;
@@ -227,156 +257,153 @@ __global__ __launch_bounds__(kThreads) void k_cell_state(HydroParams hp, int64_t
 #pragma unroll
     for (int k = 0; k < 5; ++k) U[5 * s + k] = (R)u[k];
     if (!(dti > 0.0 && dti < 1e300)) {
-      bad = 1;
+      seg_fail(st, segst, seg, F_NONFINITE, (int)s);
       dti = 1e300;
     }
   }
-  double m = dti;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = red[0];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) t = fmin(t, red[k]);
-    if (t < 1e300) atomicMin(&st->dt_bits, (unsigned long long)__double_as_longlong(t));
-  }
-  block_add((unsigned long long)hit, &st->floor_hits[0]);
-  if (bad) {
-    atomicOr(&st->flags, F_NONFINITE);
-    atomicMin(&st->bad_cell, (int)s);
-  }
+  seg_min_dt(dti, seg, active, segst);
 }
 
 // Least-squares gradient about the centroids with the S10 limiter (Sec. 4.1);
 // with U_half set, the half-step predictor is applied in the same pass.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_gradient(HydroParams hp, int64_t n, const R* __restrict__ U,
+__global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict__ segs,
+                                                       const int32_t* __restrict__ sseg, int64_t n,
+                                                       const R* __restrict__ U,
                                                        const unsigned long long* __restrict__ off,
                                                        const NbrEntry* __restrict__ nbr,
                                                        const double* __restrict__ minv, int limit, R* __restrict__ G,
-                                                       const double* __restrict__ w, const DevStatus* dt_src,
-                                                       double dt_fixed, R* __restrict__ Uh, DevStatus* st) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int hit = 0;
-  if (s < n) {
-    const int64_t e0 = (int64_t)(off[s] >> 32), e1 = (int64_t)(off[s + 1] >> 32);
-    R ui[5], umax[5], umin[5], b[15];
+                                                       const double* __restrict__ w, const SegStatus* dt_src,
+                                                       double dt_fixed, R* __restrict__ Uh, SegStatus* segst) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t e0 = (int64_t)(off[s] >> 32), e1 = (int64_t)(off[s + 1] >> 32);
+  R ui[5], umax[5], umin[5], b[15];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    ui[q] = U[5 * s + q];
+    umax[q] = ui[q];
+    umin[q] = ui[q];
+  }
+#pragma unroll
+  for (int k = 0; k < 15; ++k) b[k] = R(0);
+  for (int64_t e = e0; e < e1; ++e) {
+    const NbrEntry E = nbr[e];
+    const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2], wg = (R)E.wgt;
+    const R* uo = U + 5 * (int64_t)E.o;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      ui[q] = U[5 * s + q];
-      umax[q] = ui[q];
-      umin[q] = ui[q];
-    }
-#pragma unroll
-    for (int k = 0; k < 15; ++k) b[k] = R(0);
-    for (int64_t e = e0; e < e1; ++e) {
-      const NbrEntry E = nbr[e];
-      const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2], wg = (R)E.wgt;
-      const R* uo = U + 5 * (int64_t)E.o;
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        const R v = uo[q];
-        const R t = wg * (v - ui[q]);
-        b[3 * q] += t * dx;
-        b[3 * q + 1] += t * dy;
-        b[3 * q + 2] += t * dz;
-        umax[q] = v > umax[q] ? v : umax[q];
-        umin[q] = v < umin[q] ? v : umin[q];
-      }
-    }
-    const double* mi = minv + 6 * s;
-    const R m00 = (R)mi[0], m01 = (R)mi[1], m02 = (R)mi[2], m11 = (R)mi[3], m12 = (R)mi[4], m22 = (R)mi[5];
-    R g[15];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const R bx = b[3 * q], by = b[3 * q + 1], bz = b[3 * q + 2];
-      g[3 * q] = m00 * bx + m01 * by + m02 * bz;
-      g[3 * q + 1] = m01 * bx + m11 * by + m12 * bz;
-      g[3 * q + 2] = m02 * bx + m12 * by + m22 * bz;
-    }
-    if (limit) {
-      R alpha[5] = {R(1), R(1), R(1), R(1), R(1)};
-      for (int64_t e = e0; e < e1; ++e) {
-        const NbrEntry E = nbr[e];
-        const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          const R D = g[3 * q] * dx + g[3 * q + 1] * dy + g[3 * q + 2] * dz;
-          R psi = R(1);
-          if (D > R(0)) psi = (umax[q] - ui[q]) / D;
-          else if (D < R(0)) psi = (umin[q] - ui[q]) / D;
-          alpha[q] = psi < alpha[q] ? psi : alpha[q];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        g[3 * q] *= alpha[q];
-        g[3 * q + 1] *= alpha[q];
-        g[3 * q + 2] *= alpha[q];
-      }
-    }
-    if (G) {
-#pragma unroll
-      for (int k = 0; k < 15; ++k) G[15 * s + k] = g[k];
-    }
-    if (Uh) {
-      const double dt = dt_of(dt_src, dt_fixed);
-      const R wv[3] = {(R)w[3 * s], (R)w[3 * s + 1], (R)w[3 * s + 2]};
-      R rt[5], uh[5];
-      state_rate(ui, g, wv, (R)(hp.gamma - 1.0), hp.predictor_frame == 0, rt);
-      const R hdt = (R)(0.5 * dt);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) uh[q] = ui[q] + hdt * rt[q];
-      hit = apply_floors(uh, (R)(hp.gamma - 1.0), (R)hp.rho_floor, (R)hp.p_floor);
-#pragma unroll
-      for (int q = 0; q < 5; ++q) Uh[5 * s + q] = uh[q];
+      const R v = uo[q];
+      const R t = wg * (v - ui[q]);
+      b[3 * q] += t * dx;
+      b[3 * q + 1] += t * dy;
+      b[3 * q + 2] += t * dz;
+      umax[q] = v > umax[q] ? v : umax[q];
+      umin[q] = v < umin[q] ? v : umin[q];
     }
   }
-  if (Uh) block_add((unsigned long long)hit, &st->floor_hits[1]);
-}
-
-template <typename R>
-__global__ __launch_bounds__(kThreads) void k_predict(HydroParams hp, int64_t n, const R* __restrict__ U,
-                                                      const R* __restrict__ G, const double* __restrict__ w,
-                                                      const DevStatus* dt_src, double dt_fixed, R* __restrict__ Uh,
-                                                      DevStatus* st) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int hit = 0;
-  if (s < n) {
-    R ui[5], g[15], rt[5], uh[5];
+  const double* mi = minv + 6 * s;
+  const R m00 = (R)mi[0], m01 = (R)mi[1], m02 = (R)mi[2], m11 = (R)mi[3], m12 = (R)mi[4], m22 = (R)mi[5];
+  R g[15];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) ui[q] = U[5 * s + q];
+  for (int q = 0; q < 5; ++q) {
+    const R bx = b[3 * q], by = b[3 * q + 1], bz = b[3 * q + 2];
+    g[3 * q] = m00 * bx + m01 * by + m02 * bz;
+    g[3 * q + 1] = m01 * bx + m11 * by + m12 * bz;
+    g[3 * q + 2] = m02 * bx + m12 * by + m22 * bz;
+  }
+  const int seg = sseg[s];
+  const bool lim = limit < kLimitMaskBit0 ? limit != kLimitOff
+                                          : ((segs[seg].hp.limit_mask >> (limit - kLimitMaskBit0)) & 1) != 0;
+  if (lim) {
+    R alpha[5] = {R(1), R(1), R(1), R(1), R(1)};
+    for (int64_t e = e0; e < e1; ++e) {
+      const NbrEntry E = nbr[e];
+      const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2];
 #pragma unroll
-    for (int k = 0; k < 15; ++k) g[k] = G[15 * s + k];
+      for (int q = 0; q < 5; ++q) {
+        const R D = g[3 * q] * dx + g[3 * q + 1] * dy + g[3 * q + 2] * dz;
+        R psi = R(1);
+        if (D > R(0)) psi = (umax[q] - ui[q]) / D;
+        else if (D < R(0)) psi = (umin[q] - ui[q]) / D;
+        alpha[q] = psi < alpha[q] ? psi : alpha[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      g[3 * q] *= alpha[q];
+      g[3 * q + 1] *= alpha[q];
+      g[3 * q + 2] *= alpha[q];
+    }
+  }
+  if (G) {
+#pragma unroll
+    for (int k = 0; k < 15; ++k) G[15 * s + k] = g[k];
+  }
+  if (Uh) {
+    const HydroParams& hp = segs[seg].hp;
+    const double dt = seg_dt(segs, dt_src, seg, dt_fixed);
     const R wv[3] = {(R)w[3 * s], (R)w[3 * s + 1], (R)w[3 * s + 2]};
-    const double dt = dt_of(dt_src, dt_fixed);
+    R rt[5], uh[5];
     state_rate(ui, g, wv, (R)(hp.gamma - 1.0), hp.predictor_frame == 0, rt);
     const R hdt = (R)(0.5 * dt);
 #pragma unroll
     for (int q = 0; q < 5; ++q) uh[q] = ui[q] + hdt * rt[q];
-    hit = apply_floors(uh, (R)(hp.gamma - 1.0), (R)hp.rho_floor, (R)hp.p_floor);
+    if (apply_floors(uh, (R)(hp.gamma - 1.0), (R)hp.rho_floor, (R)hp.p_floor))
+      atomicAdd(&segst[seg].floor_hits[1], 1ull);
 #pragma unroll
     for (int q = 0; q < 5; ++q) Uh[5 * s + q] = uh[q];
   }
-  block_add((unsigned long long)hit, &st->floor_hits[1]);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_predict(const SegDesc* __restrict__ segs,
+                                                      const int32_t* __restrict__ sseg, int64_t n,
+                                                      const R* __restrict__ U, const R* __restrict__ G,
+                                                      const double* __restrict__ w, const SegStatus* dt_src,
+                                                      double dt_fixed, R* __restrict__ Uh, SegStatus* segst) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int seg = sseg[s];
+  const HydroParams& hp = segs[seg].hp;
+  R ui[5], g[15], rt[5], uh[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) ui[q] = U[5 * s + q];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) g[k] = G[15 * s + k];
+  const R wv[3] = {(R)w[3 * s], (R)w[3 * s + 1], (R)w[3 * s + 2]};
+  const double dt = seg_dt(segs, dt_src, seg, dt_fixed);
+  state_rate(ui, g, wv, (R)(hp.gamma - 1.0), hp.predictor_frame == 0, rt);
+  const R hdt = (R)(0.5 * dt);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) uh[q] = ui[q] + hdt * rt[q];
+  if (apply_floors(uh, (R)(hp.gamma - 1.0), (R)hp.rho_floor, (R)hp.p_floor))
+    atomicAdd(&segst[seg].floor_hits[1], 1ull);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) Uh[5 * s + q] = uh[q];
 }
 
 // One thread per unique face (Sec. 4 items 1-5, Sec. 4.1 reconstruction):
-// phi = dt A F, F the lab-frame flux from the owner i toward j.
+// phi = dt A F, F the lab-frame flux from the owner i toward j.  Each XCD
+// takes one contiguous eighth of the face list (faces are in owner order, so
+// the cells it gathers stay in its L2) and its blocks stride through it.
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_flux(HydroParams hp, int64_t nf_host,
+__global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ segs, int64_t nf_host,
                                                    const unsigned long long* __restrict__ nf_dev,
                                                    const Face* __restrict__ faces,
                                                    const double* __restrict__ spos, const double* __restrict__ geo,
                                                    const R* __restrict__ Uh, const R* __restrict__ Gh,
-                                                   const double* __restrict__ w, const DevStatus* dt_src,
-                                                   double dt_fixed, R* __restrict__ phi, DevStatus* st) {
+                                                   const double* __restrict__ w, const SegStatus* dt_src,
+                                                   double dt_fixed, R* __restrict__ phi, SegStatus* segst) {
   const int64_t nf = nf_dev ? std::min<int64_t>((int64_t)*nf_dev, nf_host) : nf_host;
-  int hit = 0;
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t xcd = blockIdx.x % kXcds, kb = blockIdx.x / kXcds;
+  const int64_t nbx = ((int64_t)gridDim.x - xcd + kXcds - 1) / kXcds;
+  const int64_t lo = nf * xcd / kXcds, hi = nf * (xcd + 1) / kXcds;
+  for (int64_t f = lo + kb * blockDim.x + threadIdx.x; f < hi; f += nbx * blockDim.x) {
     const Face F = faces[f];
     const int64_t i = F.i, j = F.j;
+    const int seg = F.seg;
+    const HydroParams& hp = segs[seg].hp;
     int kx, ky, kz;
     decode(F.code, kx, ky, kz);
     // Geometry in double: r_j + s - r_i, face centre and centroid offsets.
@@ -411,20 +438,20 @@ __global__ __launch_bounds__(kThreads) void k_flux(HydroParams hp, int64_t nf_ho
       UR[q] = uj + dm_factor(theta, ui - uj, Dj) * Dj;
     }
     const R g1 = (R)(hp.gamma - 1.0);
-    hit += apply_floors(UL, g1, (R)hp.rho_floor, (R)hp.p_floor);
+    int hit = apply_floors(UL, g1, (R)hp.rho_floor, (R)hp.p_floor);
     hit += apply_floors(UR, g1, (R)hp.rho_floor, (R)hp.p_floor);
+    if (hit) atomicAdd(&segst[seg].floor_hits[2], (unsigned long long)hit);
     R Fx[5];
     moving_hllc(UL, UR, nrm, wt, (R)hp.gamma, Fx);
-    const R scale = (R)(dt_of(dt_src, dt_fixed) * F.A);
+    const R scale = (R)(seg_dt(segs, dt_src, seg, dt_fixed) * F.A);
 #pragma unroll
     for (int q = 0; q < 5; ++q) phi[5 * f + q] = scale * Fx[q];
   }
-  block_add((unsigned long long)hit, &st->floor_hits[2]);
 }
 
 // Per-cell sum of the face fluxes through the CSR list in a fixed order:
-// the owner side loses phi, the neighbour side gains it (Sec. 4, eq. "time
-// evolution").  Accumulation in double.
+// the owner side loses phi, the neighbour side gains it (Sec. 4, update of
+// the charges).  Accumulation in double.
 template <typename R>
 __device__ inline void cell_flux_sum(int64_t s, const unsigned long long* off, const int32_t* csr, const R* phi,
                                      double acc[5]) {
@@ -441,60 +468,59 @@ __device__ inline void cell_flux_sum(int64_t s, const unsigned long long* off, c
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_update(HydroParams hp, int64_t n, const unsigned long long* __restrict__ off,
+__global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__ segs,
+                                                     const int32_t* __restrict__ sseg, int64_t n,
+                                                     const unsigned long long* __restrict__ off,
                                                      const int32_t* __restrict__ csr, const R* __restrict__ phi,
                                                      const double* __restrict__ geo, const int32_t* __restrict__ perm,
                                                      const double* __restrict__ Qs, double* __restrict__ Qc,
                                                      const double* __restrict__ spos, const double* __restrict__ w,
                                                      double* __restrict__ posc, double* __restrict__ wc,
-                                                     const DevStatus* dt_src, double dt_max, DevStatus* st) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int hit = 0, bad = 0;
-  if (s < n) {
-    double acc[5], Q[5];
-    cell_flux_sum(s, off, csr, phi, acc);
+                                                     const SegStatus* dt_src, DevStatus* st, SegStatus* segst) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int seg = sseg[s];
+  const HydroParams& hp = segs[seg].hp;
+  double acc[5], Q[5];
+  cell_flux_sum(s, off, csr, phi, acc);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) Q[q] = Qs[5 * s + q] + acc[q];
-    // Floors at the cell centre after the step, with the time-n volume.
-    const double V = geo[4 * s];
-    double u[5];
+  for (int q = 0; q < 5; ++q) Q[q] = Qs[5 * s + q] + acc[q];
+  // Floors at the cell centre after the step, with the time-n volume.
+  const double V = geo[4 * s];
+  double u[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) u[q] = Q[q] / V;
-    if (apply_floors(u, hp.gamma - 1.0, hp.rho_floor, hp.p_floor)) {
-      hit = 1;
+  for (int q = 0; q < 5; ++q) u[q] = Q[q] / V;
+  if (apply_floors(u, hp.gamma - 1.0, hp.rho_floor, hp.p_floor)) {
+    atomicAdd(&segst[seg].floor_hits[3], 1ull);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) Q[q] = u[q] * V;
-    }
-    const int64_t c = perm[s];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      Qc[5 * c + q] = Q[q];
-      if (!isfinite(Q[q])) bad = 1;
-    }
-    // Drift by the full step with periodic wrap.
-    const double dt = dt_of(dt_src, dt_max);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double wa = w[3 * s + a];
-      double x = spos[3 * s + a] + wa * dt;
-      if (x < 0.0) x += hp.L[a];
-      if (x >= hp.L[a]) x -= hp.L[a];
-      posc[3 * c + a] = x;
-      wc[3 * c + a] = wa;
-    }
+    for (int q = 0; q < 5; ++q) Q[q] = u[q] * V;
   }
-  block_add((unsigned long long)hit, &st->floor_hits[3]);
-  if (bad) {
-    atomicOr(&st->flags, F_NONFINITE);
-    atomicMin(&st->bad_cell, (int)s);
+  const int64_t c = perm[s];
+  int bad = 0;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    Qc[5 * c + q] = Q[q];
+    if (!isfinite(Q[q])) bad = 1;
   }
+  // Drift by the full step with periodic wrap.
+  const double dt = seg_dt(segs, dt_src, seg, 0.0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double wa = w[3 * s + a];
+    double x = spos[3 * s + a] + wa * dt;
+    if (x < 0.0) x += hp.L[a];
+    if (x >= hp.L[a]) x -= hp.L[a];
+    posc[3 * c + a] = x;
+    wc[3 * c + a] = wa;
+  }
+  if (bad) seg_fail(st, segst, seg, F_NONFINITE, (int)s);
 }
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_accumulate(int64_t n, const unsigned long long* __restrict__ off,
                                                          const int32_t* __restrict__ csr, const R* __restrict__ phi,
                                                          const int32_t* __restrict__ perm, double* __restrict__ dQc) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
   double acc[5];
   cell_flux_sum(s, off, csr, phi, acc);
@@ -521,12 +547,21 @@ __global__ void k_scatter_rows(const R* __restrict__ src, const int32_t* __restr
   dst[(int64_t)perm[s] * width + k] = src[t];
 }
 
+__global__ void k_copy_rows(const double* __restrict__ src, double* __restrict__ dst, int64_t count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) dst[t] = src[t];
+}
+
 // Charges from primitives (Sec. 4.3): Q = (rho, rho v, P/(gamma-1) + rho v^2/2) V.
-__global__ void k_init_charges(HydroParams hp, int64_t n, const double* __restrict__ prim,
-                               const int32_t* __restrict__ perm, const double* __restrict__ geo,
-                               double* __restrict__ Q) {
+// prim and Q may be the same array (each thread reads its row before writing it).
+__global__ void k_init_charges(const SegDesc* __restrict__ segs, const int32_t* __restrict__ sseg, int64_t n,
+                               const double* prim, const int32_t* __restrict__ perm,
+                               const double* __restrict__ geo, double* Q, int only_fresh) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
+  const int seg = sseg[s];
+  if (only_fresh && !segs[seg].fresh) return;
+  const double gamma = segs[seg].hp.gamma;
   const int64_t c = perm[s];
   const double V = geo[4 * s];
   const double rho = prim[5 * c], vx = prim[5 * c + 1], vy = prim[5 * c + 2], vz = prim[5 * c + 3],
@@ -536,96 +571,110 @@ __global__ void k_init_charges(HydroParams hp, int64_t n, const double* __restri
   Q[5 * c + 1] = rho * vx * V;
   Q[5 * c + 2] = rho * vy * V;
   Q[5 * c + 3] = rho * vz * V;
-  Q[5 * c + 4] = (P / (hp.gamma - 1.0) + ke) * V;
+  Q[5 * c + 4] = (P / (gamma - 1.0) + ke) * V;
 }
 
 }  // namespace
 
 template <typename R>
-void launch_cell_state(const HydroParams& hp, int64_t n, const double* Q_caller, const int32_t* perm,
-                       const double* geo, double* Qs, R* U, double* w, DevStatus* st_dev, hipStream_t st) {
-  hipLaunchKernelGGL(k_cell_state<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, Q_caller, perm,
-                     geo, Qs, U, w, st_dev);
+void launch_cell_state(const SegDesc* segs, const int32_t* sseg, int64_t n, const double* Q_slots,
+                       const int32_t* perm, const double* geo, double* Qs, R* U, double* w, DevStatus* st_dev,
+                       SegStatus* segst, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_cell_state<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, Q_slots,
+                     perm, geo, Qs, U, w, st_dev, segst);
 }
 
 template <typename R>
-void launch_gradient(const HydroParams& hp, int64_t n, const R* U, const unsigned long long* csr_off,
-                     const NbrEntry* nbr, const double* minv, int limit, R* G, const double* w,
-                     const DevStatus* dt_src, double dt_fixed, R* U_half, DevStatus* st_dev, hipStream_t st) {
-  hipLaunchKernelGGL(k_gradient<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, U, csr_off, nbr,
-                     minv, limit, G, w, dt_src, dt_fixed, U_half, st_dev);
+void launch_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U,
+                     const unsigned long long* csr_off, const NbrEntry* nbr, const double* minv, int limit, R* G,
+                     const double* w, const SegStatus* dt_src, double dt_fixed, R* U_half, SegStatus* segst,
+                     hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gradient<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, U, csr_off,
+                     nbr, minv, limit, G, w, dt_src, dt_fixed, U_half, segst);
 }
 
 template <typename R>
-void launch_predict(const HydroParams& hp, int64_t n, const R* U, const R* G, const double* w,
-                    const DevStatus* dt_src, double dt_fixed, R* U_half, DevStatus* st_dev, hipStream_t st) {
-  hipLaunchKernelGGL(k_predict<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, U, G, w, dt_src,
-                     dt_fixed, U_half, st_dev);
+void launch_predict(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U, const R* G, const double* w,
+                    const SegStatus* dt_src, double dt_fixed, R* U_half, SegStatus* segst, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_predict<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, U, G, w,
+                     dt_src, dt_fixed, U_half, segst);
 }
 
 template <typename R>
-void launch_flux(const HydroParams& hp, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
+void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
                  const double* spos, const double* geo, const R* Uh, const R* Gh, const double* w,
-                 const DevStatus* dt_src, double dt_fixed, R* phi, DevStatus* st_dev, hipStream_t st) {
+                 const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst, hipStream_t st) {
   if (nf_host <= 0) return;
-  // Grid-stride: with a device count the grid only needs to cover the bound.
-  const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(nf_host, kThreads), 1 << 16);
-  hipLaunchKernelGGL(k_flux<R>, dim3(blocks), dim3(kThreads), 0, st, hp, nf_host, nf_dev, faces, spos, geo, Uh, Gh,
-                     w, dt_src, dt_fixed, phi, st_dev);
+  // Enough resident blocks to fill the chip; each strides through its XCD's
+  // part of the (device-counted) face list.
+  const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(nf_host, kThreads), 4096);
+  hipLaunchKernelGGL(k_flux<R>, dim3(blocks), dim3(kThreads), 0, st, segs, nf_host, nf_dev, faces, spos, geo, Uh, Gh,
+                     w, dt_src, dt_fixed, phi, segst);
 }
 
 template <typename R>
-void launch_update(const HydroParams& hp, int64_t n, const unsigned long long* csr_off, const int32_t* csr,
-                   const R* phi, const double* geo, const int32_t* perm, const double* Qs, double* Q_caller,
-                   const double* spos, const double* w, double* pos_caller, double* w_caller,
-                   const DevStatus* dt_src, double dt_max, DevStatus* st_dev, hipStream_t st) {
-  hipLaunchKernelGGL(k_update<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, csr_off, csr, phi, geo,
-                     perm, Qs, Q_caller, spos, w, pos_caller, w_caller, dt_src, dt_max, st_dev);
+void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* csr_off,
+                   const int32_t* csr, const R* phi, const double* geo, const int32_t* perm, const double* Qs,
+                   double* Q_slots, const double* spos, const double* w, double* pos_slots, double* w_slots,
+                   const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_update<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, csr_off, csr,
+                     phi, geo, perm, Qs, Q_slots, spos, w, pos_slots, w_slots, dt_src, st_dev, segst);
 }
 
 template <typename R>
 void launch_accumulate(int64_t n, const unsigned long long* csr_off, const int32_t* csr, const R* phi,
-                       const int32_t* perm, double* dQ_caller, hipStream_t st) {
+                       const int32_t* perm, double* dQ_slots, hipStream_t st) {
+  if (n <= 0) return;
   hipLaunchKernelGGL(k_accumulate<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, csr_off, csr, phi,
-                     perm, dQ_caller);
+                     perm, dQ_slots);
 }
 
 template <typename R>
-void launch_gather_rows(const R* src_caller, const int32_t* perm, int64_t n, int width, R* dst, hipStream_t st) {
+void launch_gather_rows(const R* src_slots, const int32_t* perm, int64_t n, int width, R* dst, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gather_rows<R>, dim3(blocks_for(n * width, kThreads)), dim3(kThreads), 0, st, src_caller, perm,
+  hipLaunchKernelGGL(k_gather_rows<R>, dim3(blocks_for(n * width, kThreads)), dim3(kThreads), 0, st, src_slots, perm,
                      n, width, dst);
 }
 
 template <typename R>
-void launch_scatter_rows(const R* src, const int32_t* perm, int64_t n, int width, R* dst_caller, hipStream_t st) {
+void launch_scatter_rows(const R* src, const int32_t* perm, int64_t n, int width, R* dst_slots, hipStream_t st) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_scatter_rows<R>, dim3(blocks_for(n * width, kThreads)), dim3(kThreads), 0, st, src, perm, n,
-                     width, dst_caller);
+                     width, dst_slots);
 }
 
-void launch_init_charges(const HydroParams& hp, int64_t n, const double* prim_caller, const int32_t* perm,
-                         const double* geo, double* Q_caller, hipStream_t st) {
+void launch_init_charges(const SegDesc* segs, const int32_t* sseg, int64_t n, const double* prim_slots,
+                         const int32_t* perm, const double* geo, double* Q_slots, int only_fresh, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_init_charges, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, hp, n, prim_caller, perm,
-                     geo, Q_caller);
+  hipLaunchKernelGGL(k_init_charges, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, prim_slots,
+                     perm, geo, Q_slots, only_fresh);
+}
+
+void launch_copy_rows(const double* src, double* dst, int64_t n, int width, hipStream_t st) {
+  const int64_t count = n * width;
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_copy_rows, dim3(blocks_for(count, kThreads)), dim3(kThreads), 0, st, src, dst, count);
 }
 
 #define MM_INSTANTIATE(R)                                                                                          \
-  template void launch_cell_state<R>(const HydroParams&, int64_t, const double*, const int32_t*, const double*,   \
-                                     double*, R*, double*, DevStatus*, hipStream_t);                              \
-  template void launch_gradient<R>(const HydroParams&, int64_t, const R*, const unsigned long long*,              \
-                                   const NbrEntry*, const double*, int, R*, const double*, const DevStatus*,      \
-                                   double, R*, DevStatus*, hipStream_t);                                          \
-  template void launch_predict<R>(const HydroParams&, int64_t, const R*, const R*, const double*,                 \
-                                  const DevStatus*, double, R*, DevStatus*, hipStream_t);                         \
-  template void launch_flux<R>(const HydroParams&, int64_t, const unsigned long long*, const Face*, const double*, \
-                               const double*, const R*, const R*, const double*, const DevStatus*, double, R*,   \
-                               DevStatus*, hipStream_t);                                                          \
-  template void launch_update<R>(const HydroParams&, int64_t, const unsigned long long*, const int32_t*,          \
-                                 const R*, const double*, const int32_t*, const double*, double*, const double*,  \
-                                 const double*, double*, double*, const DevStatus*, double, DevStatus*,           \
-                                 hipStream_t);                                                                    \
+  template void launch_cell_state<R>(const SegDesc*, const int32_t*, int64_t, const double*, const int32_t*,      \
+                                     const double*, double*, R*, double*, DevStatus*, SegStatus*, hipStream_t);   \
+  template void launch_gradient<R>(const SegDesc*, const int32_t*, int64_t, const R*, const unsigned long long*,  \
+                                   const NbrEntry*, const double*, int, R*, const double*, const SegStatus*,      \
+                                   double, R*, SegStatus*, hipStream_t);                                          \
+  template void launch_predict<R>(const SegDesc*, const int32_t*, int64_t, const R*, const R*, const double*,     \
+                                  const SegStatus*, double, R*, SegStatus*, hipStream_t);                         \
+  template void launch_flux<R>(const SegDesc*, int64_t, const unsigned long long*, const Face*, const double*,    \
+                               const double*, const R*, const R*, const double*, const SegStatus*, double, R*,   \
+                               SegStatus*, hipStream_t);                                                          \
+  template void launch_update<R>(const SegDesc*, const int32_t*, int64_t, const unsigned long long*,              \
+                                 const int32_t*, const R*, const double*, const int32_t*, const double*, double*, \
+                                 const double*, const double*, double*, double*, const SegStatus*, DevStatus*,    \
+                                 SegStatus*, hipStream_t);                                                        \
   template void launch_accumulate<R>(int64_t, const unsigned long long*, const int32_t*, const R*, const int32_t*, \
                                      double*, hipStream_t);                                                       \
   template void launch_gather_rows<R>(const R*, const int32_t*, int64_t, int, R*, hipStream_t);                   \

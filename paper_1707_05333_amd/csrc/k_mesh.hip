@@ -17,17 +17,21 @@ inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t
 // index of its first unique face in the low 32 bits and of its first CSR
 // entry in the high 32 bits.
 __global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ spos, const double* __restrict__ geo,
-                                                    int64_t n, GridParams g, const StageNbr* __restrict__ stage_nb,
+                                                    int64_t n, const SegDesc* __restrict__ segs,
+                                                    const int32_t* __restrict__ sseg,
+                                                    const StageNbr* __restrict__ stage_nb,
                                                     const StageGeo* __restrict__ stage_geo,
                                                     const unsigned long long* __restrict__ counts,
                                                     const unsigned long long* __restrict__ off, int64_t face_cap,
                                                     Face* __restrict__ faces, int32_t* __restrict__ csr,
                                                     NbrEntry* __restrict__ nbr, double* __restrict__ minv,
-                                                    DevStatus* st) {
+                                                    DevStatus* st, SegStatus* segst) {
   __shared__ int smax[256];
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   int nf = 0;
   if (s < n) {
+    const int seg = sseg[s];
+    const double L[3] = {segs[seg].g.L[0], segs[seg].g.L[1], segs[seg].g.L[2]};
     const unsigned long long cnt = counts[s];
     nf = (int)(cnt >> 32);
     const unsigned long long o = off[s];
@@ -51,9 +55,9 @@ __global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ s
       int kx, ky, kz;
       decode(code, kx, ky, kz);
       // centroid displacement d = (c_j + s) - c_i = (r_j + s - r_i) + (c_j - r_j) - (c_i - r_i)
-      const double drx = (spos[3 * (int64_t)j] + kx * g.L[0]) - rx;
-      const double dry = (spos[3 * (int64_t)j + 1] + ky * g.L[1]) - ry;
-      const double drz = (spos[3 * (int64_t)j + 2] + kz * g.L[2]) - rz;
+      const double drx = (spos[3 * (int64_t)j] + kx * L[0]) - rx;
+      const double dry = (spos[3 * (int64_t)j + 1] + ky * L[1]) - ry;
+      const double drz = (spos[3 * (int64_t)j + 2] + kz * L[2]) - rz;
       const double dx = drx + geo[4 * (int64_t)j + 1] - cix;
       const double dy = dry + geo[4 * (int64_t)j + 2] - ciy;
       const double dz = drz + geo[4 * (int64_t)j + 3] - ciz;
@@ -80,7 +84,7 @@ __global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ s
           out.i = (int32_t)s;
           out.j = j;
           out.code = code;
-          out.pad = 0;
+          out.seg = seg;
           out.A = F.A;
           out.f[0] = F.f[0];
           out.f[1] = F.f[1];
@@ -133,10 +137,7 @@ __global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ s
     } else {
       for (int k = 0; k < 6; ++k) mi[k] = 0.0;
     }
-    if (bad) {
-      atomicOr(&st->flags, bad);
-      atomicMin(&st->bad_cell, (int)s);
-    }
+    if (bad) seg_fail(st, segst, seg, bad, (int)s);
   }
   smax[threadIdx.x] = nf;
   __syncthreads();
@@ -182,13 +183,13 @@ __global__ void k_export_faces(int64_t nf, const int32_t* __restrict__ perm, con
 
 }  // namespace
 
-void launch_build_mesh(const double* spos, const double* geo, int64_t n, const GridParams& g,
+void launch_build_mesh(const double* spos, const double* geo, int64_t n, const SegDesc* segs, const int32_t* sseg,
                        const StageNbr* stage_nb, const StageGeo* stage_geo, const unsigned long long* counts,
-                       const unsigned long long* off,
-                       int64_t face_cap, Face* faces, int32_t* csr, NbrEntry* nbr, double* minv,
-                       DevStatus* st_dev, hipStream_t st) {
-  hipLaunchKernelGGL(k_build_mesh, dim3(blocks_for(n, 256)), dim3(256), 0, st, spos, geo, n, g, stage_nb, stage_geo, counts, off,
-                     face_cap, faces, csr, nbr, minv, st_dev);
+                       const unsigned long long* off, int64_t face_cap, Face* faces, int32_t* csr, NbrEntry* nbr,
+                       double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_build_mesh, dim3(blocks_for(n, 256)), dim3(256), 0, st, spos, geo, n, segs, sseg, stage_nb,
+                       stage_geo, counts, off, face_cap, faces, csr, nbr, minv, st_dev, segst);
   hipLaunchKernelGGL(k_copy_totals, dim3(1), dim3(64), 0, st, off, n, st_dev);
 }
 

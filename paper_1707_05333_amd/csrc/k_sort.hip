@@ -124,51 +124,71 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
   if (i < n) p[i] = v;
 }
 
-__global__ void k_status_reset(DevStatus* s) {
-  if (threadIdx.x == 0) {
-    s->dt_bits = 0x7ff0000000000000ull;   // +inf
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_status_reset(DevStatus* s, SegStatus* segst, int nseg) {
+  const int t = threadIdx.x;
+  if (t == 0) {
     s->flags = 0;
     s->n_deferred = 0;
     s->max_faces = 0;
     s->bad_cell = 0x7fffffff;
-    for (int k = 0; k < 4; ++k) s->floor_hits[k] = 0;
     s->n_faces = 0;
     s->n_csr = 0;
     s->asym_cell = -1;
     s->asym_nbr = -1;
   }
+  for (int k = t; k < nseg; k += blockDim.x) {
+    SegStatus& g = segst[k];
+    g.dt_bits = 0x7ff0000000000000ull;   // +inf
+    g.flags = 0;
+    g.bad_cell = 0x7fffffff;
+    for (int q = 0; q < 4; ++q) g.floor_hits[q] = 0;
+  }
 }
 
-__global__ void k_hash(const double* __restrict__ pos, int64_t n, GridParams g, int32_t* __restrict__ key,
-                       unsigned long long* bcount, DevStatus* st) {
+// Bucket key of every used slot: the segment's first bucket plus the bucket
+// of the point in that segment's grid.  Unused slots get key -1.
+__global__ void k_hash(const double* __restrict__ pos, int64_t n_slots, const int32_t* __restrict__ slot_seg,
+                       const SegDesc* __restrict__ segs, int32_t* __restrict__ key, unsigned long long* bcount,
+                       DevStatus* st, SegStatus* segst) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n_slots) return;
+  const int seg = slot_seg ? slot_seg[i] : 0;
+  if (seg < 0) {
+    key[i] = -1;
+    return;
+  }
+  const GridParams& g = segs[seg].g;
   const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
   const bool ok = (x >= 0.0) && (x < g.L[0]) && (y >= 0.0) && (y < g.L[1]) && (z >= 0.0) && (z < g.L[2]);
-  int k = 0;
+  int64_t k = g.base;
   if (ok) {
     const int bx = bucket_coord(x, g.inv_hb[0], g.nb[0]);
     const int by = bucket_coord(y, g.inv_hb[1], g.nb[1]);
     const int bz = bucket_coord(z, g.inv_hb[2], g.nb[2]);
-    k = bx + g.nb[0] * (by + g.nb[1] * bz);
+    k += bx + g.nb[0] * (by + g.nb[1] * bz);
   } else {
-    atomicOr(&st->flags, F_BADPOS);
-    atomicMin(&st->bad_cell, (int)i);
+    seg_fail(st, segst, seg, F_BADPOS, (int)i);
   }
-  key[i] = k;
+  key[i] = (int32_t)k;
   atomicAdd(&bcount[k], 1ull);
 }
 
-__global__ void k_scatter(const int32_t* __restrict__ key, int64_t n, const unsigned long long* __restrict__ boff,
+__global__ void k_scatter(const int32_t* __restrict__ key, int64_t n_slots, const unsigned long long* __restrict__ boff,
                           unsigned long long* cursor, int32_t* __restrict__ perm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n_slots) return;
   const int k = key[i];
+  if (k < 0) return;
   const unsigned long long slot = boff[k] + atomicAdd(&cursor[k], 1ull);
   perm[slot] = (int32_t)i;
 }
 
-// Restores caller order inside each bucket (buckets hold a handful of points).
+// Restores slot order inside each bucket (buckets hold a handful of points).
 __global__ void k_bucket_order(const unsigned long long* __restrict__ boff, int64_t nbt, int32_t* perm) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbt) return;
@@ -184,14 +204,16 @@ __global__ void k_bucket_order(const unsigned long long* __restrict__ boff, int6
   }
 }
 
-__global__ void k_gather_pos(const double* __restrict__ pos, const int32_t* __restrict__ perm, int64_t n,
-                             double* __restrict__ spos) {
+__global__ void k_gather_pos(const double* __restrict__ pos, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ slot_seg, int64_t n, double* __restrict__ spos,
+                             int32_t* __restrict__ sseg) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int64_t q = perm[s];
   spos[3 * s] = pos[3 * q];
   spos[3 * s + 1] = pos[3 * q + 1];
   spos[3 * s + 2] = pos[3 * q + 2];
+  sseg[s] = slot_seg ? slot_seg[q] : 0;
 }
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -217,20 +239,27 @@ void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hip
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
 }
 
-void launch_status_reset(DevStatus* s, hipStream_t st) {
-  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, st, s);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
 }
 
-void launch_sort(const double* pos, int64_t n, const GridParams& g, unsigned long long* bcount,
-                 unsigned long long* boff, unsigned long long* scan_tmp, int32_t* key, int32_t* perm,
-                 double* spos, DevStatus* st_dev, hipStream_t st) {
-  launch_fill_u64(bcount, 0ull, g.nbt, st);
-  hipLaunchKernelGGL(k_hash, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, n, g, key, bcount, st_dev);
-  scan_u64(bcount, boff, g.nbt, scan_tmp, st);
-  launch_fill_u64(bcount, 0ull, g.nbt, st);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, key, n, boff, bcount, perm);
-  hipLaunchKernelGGL(k_bucket_order, dim3(blocks_for(g.nbt, 256)), dim3(256), 0, st, boff, (int64_t)g.nbt, perm);
-  hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, perm, n, spos);
+void launch_status_reset(DevStatus* s, SegStatus* segst, int nseg, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(256), 0, st, s, segst, nseg);
+}
+
+void launch_sort(const double* pos, int64_t n_slots, const int32_t* slot_seg, int64_t n, const SegDesc* segs,
+                 int64_t nbt, unsigned long long* bcount, unsigned long long* boff, unsigned long long* scan_tmp,
+                 int32_t* key, int32_t* perm, int32_t* sseg, double* spos, DevStatus* st_dev, SegStatus* segst,
+                 hipStream_t st) {
+  launch_fill_u64(bcount, 0ull, nbt, st);
+  hipLaunchKernelGGL(k_hash, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, pos, n_slots, slot_seg, segs, key,
+                     bcount, st_dev, segst);
+  scan_u64(bcount, boff, nbt, scan_tmp, st);
+  launch_fill_u64(bcount, 0ull, nbt, st);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, key, n_slots, boff, bcount, perm);
+  hipLaunchKernelGGL(k_bucket_order, dim3(blocks_for(nbt, 256)), dim3(256), 0, st, boff, nbt, perm);
+  hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, perm, slot_seg, n, spos, sseg);
 }
 
 }  // namespace mm

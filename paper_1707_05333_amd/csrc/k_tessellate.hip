@@ -54,7 +54,8 @@ struct __align__(16) TessLds {
 struct TessArgs {
   const double* spos;
   int64_t n;
-  GridParams g;
+  const SegDesc* segs;
+  const int32_t* sseg;
   const unsigned long long* boff;
   StageNbr* stage_nb;
   StageGeo* stage_geo;
@@ -63,6 +64,7 @@ struct TessArgs {
   double* rmax2;
   int32_t* deferred;
   DevStatus* st;
+  SegStatus* segst;
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -147,10 +149,9 @@ __device__ __forceinline__ void intersect3(const double4 a, const double4 b, con
   z = (a.w * bcz + b.w * caz + c.w * abz) * inv;
 }
 
-__device__ void fail_cell(const TessArgs& A, int s, int bit) {
+__device__ void fail_cell(const TessArgs& A, int s, int seg, int bit) {
   if (__lane_id() == 0) {
-    atomicOr(&A.st->flags, bit);
-    atomicMin(&A.st->bad_cell, s);
+    seg_fail(A.st, A.segst, seg, bit, s);
     A.counts[s] = 0ull;
     A.geo[4 * (int64_t)s] = 0.0;
   }
@@ -217,9 +218,8 @@ __device__ int ring_for(const GridParams& g, const double edge[3], double r2) {
 // half-width `ring` into LDS (at most kCands of them); returns their number.
 // Lanes take one bucket each and step through its points together.  The
 // generator's own images are not gathered: the box planes stand for them.
-__device__ int gather(TessLds& S, const TessArgs& A, const int s, const double r[3], const int b[3], const int ring,
-                      const double lo2, const double hi2) {
-  const GridParams& g = A.g;
+__device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const int s, const double r[3],
+                      const int b[3], const int ring, const double lo2, const double hi2) {
   const int W = 2 * ring + 1, W3 = W * W * W;
   int nc = 0;
   for (int chunk = 0; chunk < W3; chunk += 64) {
@@ -236,7 +236,7 @@ __device__ int gather(TessLds& S, const TessArgs& A, const int s, const double r
         kk[a] = t < 0 ? -1 : (t >= g.nb[a] ? 1 : 0);
         bb[a] = t - kk[a] * g.nb[a];
       }
-      const int key = bb[0] + g.nb[0] * (bb[1] + g.nb[1] * bb[2]);
+      const int64_t key = g.base + bb[0] + g.nb[0] * (bb[1] + g.nb[1] * bb[2]);
       const unsigned long long b0 = A.boff[key];
       bst = (int)b0;
       cnt = (int)(A.boff[key + 1] - b0);
@@ -272,14 +272,16 @@ __device__ int gather(TessLds& S, const TessArgs& A, const int s, const double r
   return nc;
 }
 
-// Orders the gathered candidates by distance (ties: gather order).
+// Orders the gathered candidates by distance; ties by neighbour and image,
+// so the order does not depend on how the stencil was walked.
 __device__ void sort_candidates(TessLds& S, const int nc) {
   for (int c = __lane_id(); c < nc; c += 64) {
     const double key = S.cd[c].w;
+    const int id = S.cjk[c];
     int rank = 0;
     for (int m = 0; m < nc; ++m) {
       const double km = S.cd[m].w;
-      rank += (km < key) || (km == key && m < c);
+      rank += (km < key) || (km == key && (S.cjk[m] < id || (S.cjk[m] == id && m < c)));
     }
     S.order[rank] = (uint8_t)c;
   }
@@ -523,7 +525,8 @@ __device__ void defer_cell(const TessArgs& A, int s, double rmax2) {
 //   first shell ends at twice the pass-1 farthest vertex, which bounds the
 //   true one (the pass-1 cell contains the true cell).
 __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int pass) {
-  const GridParams& g = A.g;
+  const int seg = A.sseg[s];
+  const GridParams& g = A.segs[seg].g;   // read in place (wave-uniform loads), never copied
   const double r[3] = {A.spos[3 * (int64_t)s], A.spos[3 * (int64_t)s + 1], A.spos[3 * (int64_t)s + 2]};
   int b[3];
   double edge[3];   // distance from the generator to its bucket's nearer wall, per axis
@@ -541,14 +544,14 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
 #pragma unroll
     for (int a = 0; a < 3; ++a) reach = fmin(reach, g.ring * g.hb[a] + edge[a]);
     const double hi2 = fmin(reach * reach, g.r_filter * g.r_filter);
-    const int nc = gather(S, A, s, r, b, g.ring, 0.0, hi2);
+    const int nc = gather(S, A, g, s, r, b, g.ring, 0.0, hi2);
     if (nc > kCands) {
       defer_cell(A, s, -1.0);
       return;
     }
     sort_candidates(S, nc);
     if (int bad = clip_candidates(S, nc, C)) {
-      fail_cell(A, s, bad);
+      fail_cell(A, s, seg, bad);
       return;
     }
     if (!(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12))) {
@@ -568,21 +571,21 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
     for (int shell = 0; shell < 32 && !done; ++shell) {
       const int ring = ring_for(g, edge, hi2);
       if (ring > g.nb[0] || ring > g.nb[1] || ring > g.nb[2]) {
-        fail_cell(A, s, F_BOX);
+        fail_cell(A, s, seg, F_BOX);
         return;
       }
-      int nc = gather(S, A, s, r, b, ring, lo2, hi2);
+      int nc = gather(S, A, g, s, r, b, ring, lo2, hi2);
       for (int tries = 0; nc > kCands && tries < 40; ++tries) {
         hi2 = lo2 + 0.5 * (hi2 - lo2);
-        nc = gather(S, A, s, r, b, ring, lo2, hi2);
+        nc = gather(S, A, g, s, r, b, ring, lo2, hi2);
       }
       if (nc > kCands) {
-        fail_cell(A, s, F_CANDS);
+        fail_cell(A, s, seg, F_CANDS);
         return;
       }
       sort_candidates(S, nc);
       if (int bad = clip_candidates(S, nc, C)) {
-        fail_cell(A, s, bad);
+        fail_cell(A, s, seg, bad);
         return;
       }
       if (4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)) {
@@ -594,17 +597,17 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
       }
     }
     if (!done) {
-      fail_cell(A, s, F_INCOMPLETE);
+      fail_cell(A, s, seg, F_INCOMPLETE);
       return;
     }
   }
-  if (int bad = finish_cell(S, A, s, C)) fail_cell(A, s, bad);
+  if (int bad = finish_cell(S, A, s, C)) fail_cell(A, s, seg, bad);
 }
 
 __global__ __launch_bounds__(64 * kWaves) void k_tess_pass1(TessArgs A) {
   __shared__ TessLds lds[kWaves];
   const int w = threadIdx.x >> 6;
-  const int64_t s = (int64_t)blockIdx.x * kWaves + w;
+  const int64_t s = xcd_block() * kWaves + w;
   if (s >= A.n) return;
   tess_cell(lds[w], A, (int)s, 1);
 }
@@ -619,11 +622,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_tess_pass2(TessArgs A) {
 
 }  // namespace
 
-void launch_tessellate(const double* spos, int64_t n, const GridParams& g, const unsigned long long* boff,
-                       StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
-                       double* rmax2,
-                       int32_t* deferred, DevStatus* st_dev, hipStream_t st) {
-  TessArgs A{spos, n, g, boff, stage_nb, stage_geo, counts, geo, rmax2, deferred, st_dev};
+void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
+                       const unsigned long long* boff, StageNbr* stage_nb, StageGeo* stage_geo,
+                       unsigned long long* counts, double* geo, double* rmax2, int32_t* deferred, DevStatus* st_dev,
+                       SegStatus* segst, hipStream_t st) {
+  if (n <= 0) return;
+  TessArgs A{spos, n, segs, sseg, boff, stage_nb, stage_geo, counts, geo, rmax2, deferred, st_dev, segst};
   const unsigned blocks = (unsigned)((n + kWaves - 1) / kWaves);
   hipLaunchKernelGGL(k_tess_pass1, dim3(blocks), dim3(64 * kWaves), 0, st, A);
   const unsigned blocks2 = (unsigned)std::min<int64_t>(blocks, 1024);

@@ -1,0 +1,101 @@
+// The engine behind both public front ends (one simulation per mm_ctx, many
+// per mm_batch): the device memory of the internal (bucket-sorted) cell
+// space, the segment table, the enqueue order of a tessellation and of a
+// whole step, and the single status readback.  Host code only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/mm.h"
+#include "mm_internal.h"
+
+namespace mm {
+
+// Bytes of device memory the engine reserves per unit of capacity: per
+// internal cell (faces at kFacesPerCell unique faces per cell included) and
+// per slot of a caller-order pool.
+constexpr int64_t kFacesPerCell = 12;
+int64_t engine_bytes_per_cell(int precision);
+
+// Bucket grid of a segment of n points in box p.box whose buckets start at
+// `base` in the shared table.  Buckets are about one mean spacing wide
+// whatever rfac, so the cell order (bucket, then slot) and with it every
+// result do not depend on the candidate radius.
+GridParams make_grid(const mm_params& p, int64_t n, double rfac, int64_t base);
+HydroParams hydro_params(const mm_params& p);
+bool params_ok(const mm_params* p, std::string& why);
+
+struct Engine {
+  int precision = MM_FP64;
+  int64_t ncap = 0, slot_cap = 0, fcap = 0, nbcap = 0;
+  int segcap = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // Sort and tessellation.
+  int32_t *key = nullptr, *perm = nullptr, *sseg = nullptr, *deferred = nullptr;
+  double *spos = nullptr, *geo = nullptr, *rmax2 = nullptr, *minv = nullptr;
+  unsigned long long *bcount = nullptr, *boff = nullptr, *scan_tmp = nullptr, *counts = nullptr, *off = nullptr;
+  StageNbr* stage_nb = nullptr;
+  StageGeo* stage_geo = nullptr;
+  Face* faces = nullptr;
+  int32_t* csr = nullptr;
+  NbrEntry* nbr = nullptr;
+  // State in internal order.
+  void *U = nullptr, *G = nullptr, *Uh = nullptr, *Gh = nullptr, *phi = nullptr;
+  double *w = nullptr, *Qs = nullptr;
+  // Segment table and status.
+  SegDesc* segs = nullptr;
+  SegStatus* segst = nullptr;
+  DevStatus* st = nullptr;
+  SegDesc* segs_host = nullptr;       // pinned staging of the table
+  SegStatus* segst_host = nullptr;    // pinned mirror
+  DevStatus* st_host = nullptr;       // pinned mirror
+  hipEvent_t upload_done = nullptr;
+  int nseg = 0;
+  // Mesh currently held.
+  int64_t n = 0, n_faces = 0, nbt = 0;
+  double rfac = 2.0;   // first-pass candidate radius in mean spacings (adapted per call)
+  // Stage timing.
+  bool timing = false;
+  hipEvent_t ev[9] = {};
+  double stage_ms[8] = {};
+  std::string err;
+
+  // Reserves everything; returns MM_OK or MM_ENOMEM / MM_EHIP with err set.
+  mm_status init(int precision, int64_t ncap, int64_t slot_cap, int64_t fcap, int segcap, hipStream_t stream);
+  void release();
+
+  // Host staging of the segment table, safe to write once returned; then
+  // upload(nseg) copies the first nseg descriptors (stream-ordered).
+  SegDesc* staging();
+  mm_status upload(int nseg);
+  void reset_status();
+  // Sort, cell construction and mesh assembly of n cells living in n_slots
+  // caller-order slots (slot_seg: segment per slot, NULL for one segment).
+  void enqueue_tessellation(const double* pos, int64_t n_slots, const int32_t* slot_seg, int64_t n, int64_t nbt);
+  // One whole step: tessellation, charges of fresh segments, states, two
+  // gradients with the predictor, fluxes, update and drift.  Q, pos and w
+  // are slot-order arrays, updated in place.
+  void enqueue_step(double* pos, double* w, double* Q, int64_t n_slots, const int32_t* slot_seg, int64_t n,
+                    int64_t nbt, bool any_fresh);
+  // Waits for the stream and copies the status of the launch set and of
+  // the first nseg segments to the host mirrors.
+  mm_status readback();
+  void finish_timing();
+  void adapt_filter();
+  // Status code and message for failure bits (of the whole set or a segment).
+  mm_status check_flags(int flags, int bad_cell, std::string& msg) const;
+  mm_status fail(mm_status code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  void mark(int k) {
+    if (timing) (void)hipEventRecord(ev[k], stream);
+  }
+};
+
+double dt_from_bits(unsigned long long bits);
+
+}  // namespace mm

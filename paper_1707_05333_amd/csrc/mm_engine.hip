@@ -1,0 +1,299 @@
+// Engine: device memory of the internal cell space, segment table, enqueue
+// order of a tessellation and of a step, status readback.
+#include "mm_engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace mm {
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+}  // namespace
+
+int64_t engine_bytes_per_cell(int precision) {
+  const int64_t r = precision == MM_MIXED ? 4 : 8;
+  const int64_t per_cell = 4 * 4                                       // key, perm, sseg, deferred
+                           + 8 * (3 + 4 + 1 + 6 + 1 + 1)               // spos, geo, rmax2, minv, counts, off
+                           + 16                                        // bucket count and offset
+                           + (int64_t)kMaxFaces * (sizeof(StageNbr) + sizeof(StageGeo))
+                           + r * (5 + 15 + 5 + 15) + 8 * (3 + 5);      // U, G, Uh, Gh, w, Qs
+  const int64_t per_face = sizeof(Face) + 2 * (4 + sizeof(NbrEntry)) + 5 * r;   // face, CSR, nbr, phi
+  return per_cell + kFacesPerCell * per_face;
+}
+
+GridParams make_grid(const mm_params& p, int64_t n, double rfac, int64_t base) {
+  GridParams g{};
+  const double vol = p.box[0] * p.box[1] * p.box[2];
+  const double spacing = std::cbrt(vol / (double)n);
+  g.r_filter = rfac * spacing;
+  // At most n + 8 buckets per segment (the shared table is sized for it).
+  double h = spacing;
+  for (;;) {
+    int64_t nbt = 1;
+    for (int a = 0; a < 3; ++a) {
+      g.nb[a] = std::max(1, (int)std::floor(p.box[a] / h));
+      nbt *= g.nb[a];
+    }
+    if (nbt <= n + 8) {
+      g.nbt = (int)nbt;
+      break;
+    }
+    h *= 1.1;
+  }
+  for (int a = 0; a < 3; ++a) {
+    g.hb[a] = p.box[a] / g.nb[a];
+    g.inv_hb[a] = 1.0 / g.hb[a];
+    g.L[a] = p.box[a];
+  }
+  const double hmin = std::min(g.hb[0], std::min(g.hb[1], g.hb[2]));
+  g.ring = std::max(1, (int)std::ceil(g.r_filter / hmin * (1.0 - 1e-12)));
+  // Few buckets along an axis: the stencil may not exceed the axis' buckets
+  // (images beyond one box length are outside the scheme's premise).
+  g.ring = std::min(g.ring, std::min(g.nb[0], std::min(g.nb[1], g.nb[2])));
+  g.pad = 0;
+  g.base = base;
+  return g;
+}
+
+HydroParams hydro_params(const mm_params& p) {
+  HydroParams h;
+  for (int a = 0; a < 3; ++a) h.L[a] = p.box[a];
+  h.gamma = p.gamma;
+  h.cfl = p.cfl;
+  h.eta = p.eta;
+  h.chi = p.chi;
+  h.zeta = p.zeta;
+  h.theta = p.theta;
+  h.rho_floor = p.rho_floor;
+  h.p_floor = p.p_floor;
+  h.limit_mask = p.limit_mask;
+  h.predictor_frame = p.predictor_frame;
+  return h;
+}
+
+bool params_ok(const mm_params* p, std::string& why) {
+  for (int a = 0; a < 3; ++a)
+    if (!(std::isfinite(p->box[a]) && p->box[a] > 0)) { why = "box lengths must be finite and positive"; return false; }
+  if (!(p->gamma > 1.0 && std::isfinite(p->gamma))) { why = "gamma must exceed 1"; return false; }
+  if (!(p->cfl > 0.0)) { why = "cfl must be positive"; return false; }
+  if (!(p->zeta > 0.0)) { why = "zeta must be positive"; return false; }
+  if (!(p->rho_floor > 0.0 && p->p_floor > 0.0)) { why = "floors must be positive"; return false; }
+  if (p->precision != MM_FP64 && p->precision != MM_MIXED) { why = "precision must be MM_FP64 or MM_MIXED"; return false; }
+  if (p->riemann != MM_HLLC) { why = "riemann must be MM_HLLC"; return false; }
+  if (p->limit_mask < 0 || p->limit_mask > 3) { why = "limit_mask must be in 0..3"; return false; }
+  if (p->predictor_frame != 0 && p->predictor_frame != 1) { why = "predictor_frame must be 0 or 1"; return false; }
+  return true;
+}
+
+double dt_from_bits(unsigned long long bits) {
+  if (bits == 0x7ff0000000000000ull) return INFINITY;
+  double d;
+  std::memcpy(&d, &bits, sizeof d);
+  return d;
+}
+
+mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, int seg_cap, hipStream_t s) {
+  precision = prec;
+  ncap = n_cap;
+  slot_cap = s_cap;
+  fcap = std::min<int64_t>(f_cap, 0x7fffffffll);
+  segcap = seg_cap;
+  nbcap = ncap + 8ll * segcap;
+  stream = s;
+  if (hipGetDevice(&device) != hipSuccess) return fail(MM_EHIP, "hipGetDevice failed");
+  const int64_t N = ncap, F = fcap;
+  const size_t rs = precision == MM_MIXED ? sizeof(float) : sizeof(double);
+  bool ok = true;
+  ok &= dalloc(&key, slot_cap) == hipSuccess;
+  ok &= dalloc(&perm, N) == hipSuccess;
+  ok &= dalloc(&sseg, N) == hipSuccess;
+  ok &= dalloc(&deferred, N) == hipSuccess;
+  ok &= dalloc(&spos, 3 * N) == hipSuccess;
+  ok &= dalloc(&geo, 4 * N) == hipSuccess;
+  ok &= dalloc(&rmax2, N) == hipSuccess;
+  ok &= dalloc(&minv, 6 * N) == hipSuccess;
+  ok &= dalloc(&bcount, nbcap) == hipSuccess;
+  ok &= dalloc(&boff, nbcap + 1) == hipSuccess;
+  ok &= dalloc(&scan_tmp, scan_tmp_elems(std::max(N, nbcap))) == hipSuccess;
+  ok &= dalloc(&counts, N) == hipSuccess;
+  ok &= dalloc(&off, N + 1) == hipSuccess;
+  ok &= dalloc(&stage_nb, (size_t)N * kMaxFaces) == hipSuccess;
+  ok &= dalloc(&stage_geo, (size_t)N * kMaxFaces) == hipSuccess;
+  ok &= dalloc(&faces, F) == hipSuccess;
+  ok &= dalloc(&csr, 2 * F) == hipSuccess;
+  ok &= dalloc(&nbr, 2 * F) == hipSuccess;
+  ok &= hipMalloc(&U, std::max<size_t>(5 * N * rs, 1)) == hipSuccess;
+  ok &= hipMalloc(&G, std::max<size_t>(15 * N * rs, 1)) == hipSuccess;
+  ok &= hipMalloc(&Uh, std::max<size_t>(5 * N * rs, 1)) == hipSuccess;
+  ok &= hipMalloc(&Gh, std::max<size_t>(15 * N * rs, 1)) == hipSuccess;
+  ok &= hipMalloc(&phi, std::max<size_t>(5 * F * rs, 1)) == hipSuccess;
+  ok &= dalloc(&w, 3 * N) == hipSuccess;
+  ok &= dalloc(&Qs, 5 * N) == hipSuccess;
+  ok &= dalloc(&segs, segcap) == hipSuccess;
+  ok &= dalloc(&segst, segcap) == hipSuccess;
+  ok &= dalloc(&st, 1) == hipSuccess;
+  ok &= hipHostMalloc((void**)&segs_host, sizeof(SegDesc) * segcap, hipHostMallocDefault) == hipSuccess;
+  ok &= hipHostMalloc((void**)&segst_host, sizeof(SegStatus) * segcap, hipHostMallocDefault) == hipSuccess;
+  ok &= hipHostMalloc((void**)&st_host, sizeof(DevStatus), hipHostMallocDefault) == hipSuccess;
+  ok &= hipEventCreateWithFlags(&upload_done, hipEventDisableTiming) == hipSuccess;
+  for (hipEvent_t& e : ev) ok &= hipEventCreate(&e) == hipSuccess;
+  if (!ok) {
+    const hipError_t e = hipGetLastError();
+    release();
+    return fail(MM_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+  }
+  std::memset(segs_host, 0, sizeof(SegDesc) * segcap);
+  std::memset(segst_host, 0, sizeof(SegStatus) * segcap);
+  std::memset(st_host, 0, sizeof(DevStatus));
+  return MM_OK;
+}
+
+void Engine::release() {
+  void* ptrs[] = {key, perm, sseg, deferred, spos, geo, rmax2, minv, bcount, boff, scan_tmp, counts, off,
+                  stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, Gh, phi, w, Qs, segs, segst, st};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  void* hptrs[] = {segs_host, segst_host, st_host};
+  for (void* q : hptrs)
+    if (q) (void)hipHostFree(q);
+  if (upload_done) (void)hipEventDestroy(upload_done);
+  for (hipEvent_t& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  *this = Engine();
+}
+
+mm_status Engine::upload(int k) {
+  if (k < 0 || k > segcap) return fail(MM_EINVAL, "segment count beyond capacity");
+  nseg = k;
+  if (k == 0) return MM_OK;
+  const hipError_t e = hipMemcpyAsync(segs, segs_host, sizeof(SegDesc) * k, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return fail(MM_EHIP, std::string("segment upload: ") + hipGetErrorString(e));
+  (void)hipEventRecord(upload_done, stream);
+  return MM_OK;
+}
+
+SegDesc* Engine::staging() {
+  // The staging buffer may be rewritten only once the last upload has run.
+  (void)hipEventSynchronize(upload_done);
+  return segs_host;
+}
+
+void Engine::reset_status() { launch_status_reset(st, segst, nseg, stream); }
+
+void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int32_t* slot_seg, int64_t n_cells,
+                                  int64_t n_buckets) {
+  nbt = n_buckets;
+  mark(0);
+  launch_sort(pos, n_slots, slot_seg, n_cells, segs, n_buckets, bcount, boff, scan_tmp, key, perm, sseg, spos, st,
+              segst, stream);
+  mark(1);
+  launch_tessellate(spos, n_cells, segs, sseg, boff, stage_nb, stage_geo, counts, geo, rmax2, deferred, st, segst,
+                    stream);
+  mark(2);
+  scan_u64(counts, off, n_cells, scan_tmp, stream);
+  launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, fcap, faces, csr, nbr, minv, st,
+                    segst, stream);
+}
+
+namespace {
+
+template <typename R>
+void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n, bool any_fresh) {
+  const unsigned long long* nf_dev = &E.st->n_faces;
+  R *U = (R*)E.U, *Uh = (R*)E.Uh, *Gh = (R*)E.Gh, *phi = (R*)E.phi;
+  if (any_fresh) launch_init_charges(E.segs, E.sseg, n, Q, E.perm, E.geo, Q, 1, E.stream);
+  launch_cell_state<R>(E.segs, E.sseg, n, Q, E.perm, E.geo, E.Qs, U, E.w, E.st, E.segst, E.stream);
+  E.mark(4);
+  launch_gradient<R>(E.segs, E.sseg, n, U, E.off, E.nbr, E.minv, kLimitMaskBit0, nullptr, E.w,
+                     E.segst, 0.0, Uh, E.segst, E.stream);
+  E.mark(5);
+  launch_gradient<R>(E.segs, E.sseg, n, Uh, E.off, E.nbr, E.minv, kLimitMaskBit1, Gh,
+                     nullptr, nullptr, 0.0, nullptr, E.segst, E.stream);
+  E.mark(6);
+  launch_flux<R>(E.segs, E.fcap, nf_dev, E.faces, E.spos, E.geo, Uh, Gh, E.w, E.segst, 0.0, phi, E.segst, E.stream);
+  E.mark(7);
+  launch_update<R>(E.segs, E.sseg, n, E.off, E.csr, phi, E.geo, E.perm, E.Qs, Q, E.spos, E.w, pos, w_slots, E.segst,
+                   E.st, E.segst, E.stream);
+}
+
+}  // namespace
+
+void Engine::enqueue_step(double* pos, double* w_slots, double* Q, int64_t n_slots, const int32_t* slot_seg,
+                          int64_t n_cells, int64_t n_buckets, bool any_fresh) {
+  reset_status();
+  enqueue_tessellation(pos, n_slots, slot_seg, n_cells, n_buckets);
+  mark(3);
+  if (precision == MM_MIXED) enqueue_hydro<float>(*this, pos, w_slots, Q, n_cells, any_fresh);
+  else enqueue_hydro<double>(*this, pos, w_slots, Q, n_cells, any_fresh);
+  mark(8);
+}
+
+mm_status Engine::readback() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(MM_EHIP, std::string("launch: ") + hipGetErrorString(e));
+  e = hipMemcpyAsync(st_host, st, sizeof(DevStatus), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess && nseg > 0)
+    e = hipMemcpyAsync(segst_host, segst, sizeof(SegStatus) * nseg, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(MM_EHIP, std::string("status readback: ") + hipGetErrorString(e));
+  return MM_OK;
+}
+
+void Engine::finish_timing() {
+  if (!timing) return;
+  for (int k = 0; k < 8; ++k) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+    stage_ms[k] = ms;
+  }
+}
+
+// The first-pass radius only changes how much work goes to the shell pass,
+// never the cells (clipping is always in order of distance, ties broken by
+// neighbour and image): widen it when many cells were deferred, narrow it
+// slowly when none were.
+void Engine::adapt_filter() {
+  const double d = st_host->n_deferred, nn = (double)n;
+  if (d > 0.02 * nn) rfac = std::min(rfac * 1.15, 3.0);
+  else if (d < 0.002 * nn) rfac = std::max(rfac * 0.98, 1.9);
+}
+
+mm_status Engine::check_flags(int flags, int bad_cell, std::string& msg) const {
+  if (!flags) return MM_OK;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "device flags 0x%x (first internal cell %d)", flags, bad_cell);
+  const std::string at(buf);
+  if (flags & F_BADPOS) { msg = "a position is not finite or lies outside [0, L): " + at; return MM_EINVAL; }
+  if (flags & F_PLANES) { msg = "a cell has more than 64 live faces: " + at; return MM_ECAPACITY; }
+  if (flags & F_VERTS) { msg = "a cell has more than 128 vertices: " + at; return MM_ECAPACITY; }
+  if (flags & F_CANDS) { msg = "more than 128 neighbour candidates in a cell's stencil: " + at; return MM_ECAPACITY; }
+  if (flags & F_FACECAP) { msg = "more unique faces than the face capacity: " + at; return MM_ECAPACITY; }
+  if (flags & F_BOX) { msg = "a cell is too large for the periodic box (needs 2 R_max < L): " + at; return MM_EDEGENERATE; }
+  if (flags & F_INCOMPLETE) { msg = "a cell could not be completed: " + at; return MM_EDEGENERATE; }
+  if (flags & F_ASYM) {
+    // Name the two points of one unmatched face in the slot numbering.
+    int32_t pi = -1, pj = -1;
+    if (st_host->asym_cell >= 0 && st_host->asym_nbr >= 0) {
+      (void)hipMemcpy(&pi, perm + st_host->asym_cell, sizeof pi, hipMemcpyDeviceToHost);
+      (void)hipMemcpy(&pj, perm + st_host->asym_nbr, sizeof pj, hipMemcpyDeviceToHost);
+    }
+    char pair[96];
+    std::snprintf(pair, sizeof pair, "; points %d and %d", pi, pj);
+    msg = "asymmetric face topology (degenerate input?): " + at + pair;
+    return MM_EDEGENERATE;
+  }
+  if (flags & (F_WALK | F_VOLUME)) { msg = "corrupted or empty cell: " + at; return MM_EDEGENERATE; }
+  if (flags & F_NONFINITE) { msg = "a state became NaN or infinite: " + at; return MM_ENONFINITE; }
+  msg = at;
+  return MM_EDEGENERATE;
+}
+
+}  // namespace mm

@@ -1,5 +1,13 @@
 // Internal declarations shared by the HIP kernels and the host runtime of the
 // MI355X moving-mesh step.  Not part of the public interface (include/mm.h).
+//
+// Every launch works on a set of segments: independent simulations (each
+// with its own periodic box, point count, scheme parameters and timestep)
+// whose cells share one internal index space.  A single simulation is the
+// one-segment case.  Cells of a segment are contiguous in the internal
+// (bucket-sorted) order, and nothing a kernel computes for a cell reads
+// another segment's data, so a simulation's results do not depend on what
+// else shares its launches.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,7 +25,7 @@ constexpr int kVerts = 128;
 constexpr int kCands = 128;
 constexpr int kMaxFaces = kPlanes;   // staging slots per cell
 
-// Failure bits collected in DevStatus::flags.
+// Failure bits collected in DevStatus::flags and SegStatus::flags.
 enum : int {
   F_BADPOS = 1 << 0,      // position not finite or outside [0, L)
   F_PLANES = 1 << 1,      // more than kPlanes live faces
@@ -32,20 +40,26 @@ enum : int {
   F_BOX = 1 << 10,        // stencil wider than the periodic box allows
 };
 
-// Status block written by the kernels and read back once per step.
+// Status of the whole launch set, read back once per call.
 struct DevStatus {
-  unsigned long long dt_bits;    // min over cells of dt_i as IEEE bits (dt_i > 0)
-  int flags;
+  int flags;                     // OR of every segment's flags
   int n_deferred;                // cells handed to the wide-stencil pass
   int max_faces;
   int bad_cell;                  // lowest internal cell index with a failure
-  unsigned long long floor_hits[4];
   unsigned long long n_faces;    // unique faces (copy of the scan total)
   unsigned long long n_csr;      // directed faces (copy of the scan total)
   int asym_cell, asym_nbr;       // one face without a partner (internal cells), for diagnostics
 };
 
-// Periodic bucket grid for the neighbour search.
+// Status of one segment.
+struct SegStatus {
+  unsigned long long dt_bits;    // min over the segment's cells of dt_i as IEEE bits (dt_i > 0)
+  int flags;
+  int bad_cell;                  // lowest internal cell index with a failure
+  unsigned long long floor_hits[4];
+};
+
+// Periodic bucket grid of one segment for the neighbour search.
 struct GridParams {
   int nb[3];        // buckets per axis
   int nbt;          // total buckets
@@ -53,7 +67,26 @@ struct GridParams {
   double inv_hb[3];
   double L[3];      // box
   int ring;         // stencil half-width (in buckets) of the first pass
+  int pad;
   double r_filter;  // first-pass candidate radius
+  int64_t base;     // first bucket of this grid in the shared bucket table
+};
+
+// Scheme parameters as the kernels need them.
+struct HydroParams {
+  double L[3];
+  double gamma, cfl, eta, chi, zeta, theta, rho_floor, p_floor;
+  int limit_mask;
+  int predictor_frame;
+};
+
+// One segment as the kernels see it.
+struct SegDesc {
+  GridParams g;
+  HydroParams hp;
+  double dt_max;    // cap of the segment's timestep
+  int32_t fresh;    // 1: the charges still hold primitives (first step after admission)
+  int32_t pad;
 };
 
 // One face of a cell as written by the tessellation kernel (cell-local list),
@@ -71,7 +104,7 @@ struct StageGeo {
 struct Face {
   int32_t i, j;     // owner and neighbour (internal)
   int32_t code;     // periodic image of j seen from i
-  int32_t pad;
+  int32_t seg;      // segment of both cells
   double A;
   double f[3];      // area centroid minus r_i
 };
@@ -83,14 +116,6 @@ struct NbrEntry {
   int32_t pad;
   double d[3];
   double wgt;
-};
-
-// Scheme parameters as the kernels need them.
-struct HydroParams {
-  double L[3];
-  double gamma, cfl, eta, chi, zeta, theta, rho_floor, p_floor;
-  int limit_mask;
-  int predictor_frame;
 };
 
 // Bucket of one coordinate; the sort and the tessellation must agree on it.
@@ -108,6 +133,30 @@ inline __host__ __device__ void decode(int code, int& kx, int& ky, int& kz) {
   kz = code / 9 - 1;
 }
 
+// Workgroups are handed to the eight XCDs in turn (workgroup b runs on XCD
+// b mod 8).  This renumbering gives each XCD one contiguous run of logical
+// blocks, so the neighbour reuse inside a run stays in that XCD's L2.
+constexpr int kXcds = 8;
+inline __device__ int64_t xcd_block() {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  const int64_t x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// Timestep of segment `seg`: the device CFL minimum capped by the segment's
+// dt_max, or dt_fixed when no status is given (component calls).
+inline __device__ double seg_dt(const SegDesc* segs, const SegStatus* dt_src, int seg, double dt_fixed) {
+  if (!dt_src) return dt_fixed;
+  return fmin(__longlong_as_double((long long)dt_src[seg].dt_bits), segs[seg].dt_max);
+}
+
+inline __device__ void seg_fail(DevStatus* st, SegStatus* segst, int seg, int bits, int cell) {
+  atomicOr(&st->flags, bits);
+  atomicMin(&st->bad_cell, cell);
+  atomicOr(&segst[seg].flags, bits);
+  atomicMin(&segst[seg].bad_cell, cell);
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers (each enqueues on `st`).
 // ---------------------------------------------------------------------------
@@ -119,62 +168,77 @@ void scan_u64(const unsigned long long* in, unsigned long long* out, int64_t n, 
               hipStream_t st);
 
 void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t st);
-void launch_status_reset(DevStatus* s, hipStream_t st);
+void launch_status_reset(DevStatus* s, SegStatus* segst, int nseg, hipStream_t st);
 
-// Bucket sort of the generators (grid hash, counting sort, index order inside
-// a bucket).  Writes perm (internal -> caller), spos, bucket offsets boff.
-void launch_sort(const double* pos, int64_t n, const GridParams& g, unsigned long long* bcount,
-                 unsigned long long* boff, unsigned long long* scan_tmp, int32_t* key, int32_t* perm,
-                 double* spos, DevStatus* st_dev, hipStream_t st);
+// Bucket sort of the generators of every segment (grid hash, counting sort,
+// caller order inside a bucket).  pos covers n_slots slots; slot_seg[q] is
+// the segment of slot q (-1: unused slot), or NULL for one segment covering
+// every slot.  Writes perm (internal -> slot), the segment of each internal
+// cell, the sorted positions and the bucket offsets of all nbt buckets.
+void launch_sort(const double* pos, int64_t n_slots, const int32_t* slot_seg, int64_t n, const SegDesc* segs,
+                 int64_t nbt, unsigned long long* bcount, unsigned long long* boff, unsigned long long* scan_tmp,
+                 int32_t* key, int32_t* perm, int32_t* sseg, double* spos, DevStatus* st_dev, SegStatus* segst,
+                 hipStream_t st);
 
 // Tessellation: pass 1 over every cell, then the deferred cells.
-void launch_tessellate(const double* spos, int64_t n, const GridParams& g, const unsigned long long* boff,
-                       StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
-                       double* rmax2,
-                       int32_t* deferred, DevStatus* st_dev, hipStream_t st);
+void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
+                       const unsigned long long* boff, StageNbr* stage_nb, StageGeo* stage_geo,
+                       unsigned long long* counts, double* geo, double* rmax2, int32_t* deferred, DevStatus* st_dev,
+                       SegStatus* segst, hipStream_t st);
 
 // Faces, CSR, neighbour entries and inverse LSQ matrices from the staged lists.
-void launch_build_mesh(const double* spos, const double* geo, int64_t n, const GridParams& g,
+void launch_build_mesh(const double* spos, const double* geo, int64_t n, const SegDesc* segs, const int32_t* sseg,
                        const StageNbr* stage_nb, const StageGeo* stage_geo, const unsigned long long* counts,
-                       const unsigned long long* off,
-                       int64_t face_cap, Face* faces, int32_t* csr, NbrEntry* nbr, double* minv,
-                       DevStatus* st_dev, hipStream_t st);
+                       const unsigned long long* off, int64_t face_cap, Face* faces, int32_t* csr, NbrEntry* nbr,
+                       double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
 // Hydro kernels, instantiated for double (MM_FP64) and float (MM_MIXED).
+// Slot-space arrays (Q, pos, w, prim) are indexed through perm.  dt_src
+// (may be NULL, then dt_fixed applies) holds each segment's CFL minimum.
 template <typename R>
-void launch_cell_state(const HydroParams& hp, int64_t n, const double* Q_caller, const int32_t* perm,
-                       const double* geo, double* Qs, R* U, double* w, DevStatus* st_dev, hipStream_t st);
+void launch_cell_state(const SegDesc* segs, const int32_t* sseg, int64_t n, const double* Q_slots,
+                       const int32_t* perm, const double* geo, double* Qs, R* U, double* w, DevStatus* st_dev,
+                       SegStatus* segst, hipStream_t st);
+// Limiter selection of the gradient kernel: off, on, or the segment's own
+// limit_mask bit 0 (first gradient) / bit 1 (second gradient).
+enum : int { kLimitOff = 0, kLimitOn = 1, kLimitMaskBit0 = 2, kLimitMaskBit1 = 3 };
 template <typename R>
-void launch_gradient(const HydroParams& hp, int64_t n, const R* U, const unsigned long long* csr_off,
-                     const NbrEntry* nbr, const double* minv, int limit, R* G, const double* w,
-                     const DevStatus* dt_src, double dt_fixed, R* U_half, DevStatus* st_dev, hipStream_t st);
+void launch_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U,
+                     const unsigned long long* csr_off, const NbrEntry* nbr, const double* minv, int limit, R* G,
+                     const double* w, const SegStatus* dt_src, double dt_fixed, R* U_half, SegStatus* segst,
+                     hipStream_t st);
 template <typename R>
-void launch_predict(const HydroParams& hp, int64_t n, const R* U, const R* G, const double* w,
-                    const DevStatus* dt_src, double dt_fixed, R* U_half, DevStatus* st_dev, hipStream_t st);
+void launch_predict(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U, const R* G, const double* w,
+                    const SegStatus* dt_src, double dt_fixed, R* U_half, SegStatus* segst, hipStream_t st);
 // nf_dev (device count, may be NULL) overrides nf_host, which then only
 // bounds the launch.
 template <typename R>
-void launch_flux(const HydroParams& hp, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
+void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
                  const double* spos, const double* geo, const R* Uh, const R* Gh, const double* w,
-                 const DevStatus* dt_src, double dt_fixed, R* phi, DevStatus* st_dev, hipStream_t st);
+                 const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst, hipStream_t st);
 template <typename R>
-void launch_update(const HydroParams& hp, int64_t n, const unsigned long long* csr_off, const int32_t* csr,
-                   const R* phi, const double* geo, const int32_t* perm, const double* Qs, double* Q_caller,
-                   const double* spos, const double* w, double* pos_caller, double* w_caller,
-                   const DevStatus* dt_src, double dt_max, DevStatus* st_dev, hipStream_t st);
+void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* csr_off,
+                   const int32_t* csr, const R* phi, const double* geo, const int32_t* perm, const double* Qs,
+                   double* Q_slots, const double* spos, const double* w, double* pos_slots, double* w_slots,
+                   const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 template <typename R>
 void launch_accumulate(int64_t n, const unsigned long long* csr_off, const int32_t* csr, const R* phi,
-                       const int32_t* perm, double* dQ_caller, hipStream_t st);
+                       const int32_t* perm, double* dQ_slots, hipStream_t st);
 
-// Layout conversions between caller order and internal order.
+// Layout conversions between slot order and internal order.
 template <typename R>
-void launch_gather_rows(const R* src_caller, const int32_t* perm, int64_t n, int width, R* dst, hipStream_t st);
+void launch_gather_rows(const R* src_slots, const int32_t* perm, int64_t n, int width, R* dst, hipStream_t st);
 template <typename R>
-void launch_scatter_rows(const R* src, const int32_t* perm, int64_t n, int width, R* dst_caller, hipStream_t st);
-void launch_init_charges(const HydroParams& hp, int64_t n, const double* prim_caller, const int32_t* perm,
-                         const double* geo, double* Q_caller, hipStream_t st);
+void launch_scatter_rows(const R* src, const int32_t* perm, int64_t n, int width, R* dst_slots, hipStream_t st);
+// Charges from primitives, Q = U(prim) V; with only_fresh set, only for
+// segments flagged fresh, reading and writing the same slot array.
+void launch_init_charges(const SegDesc* segs, const int32_t* sseg, int64_t n, const double* prim_slots,
+                         const int32_t* perm, const double* geo, double* Q_slots, int only_fresh, hipStream_t st);
 void launch_export_mesh(int64_t n, int64_t nf, const int32_t* perm, const double* spos, const double* geo,
                         const Face* faces, double* V, double* centroid, int32_t* fi, int32_t* fj, int32_t* fc,
                         double* fA, double* ff, hipStream_t st);
+// Copies n rows of `width` doubles (device to device, may not overlap).
+void launch_copy_rows(const double* src, double* dst, int64_t n, int width, hipStream_t st);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 
 }  // namespace mm

@@ -44,6 +44,13 @@ int main(void) {
   printf("mm_step_info %zu %zu %zu\n", sizeof(mm_step_info), offsetof(mm_step_info, floor_hits),
          offsetof(mm_step_info, flags));
   printf("mm_mesh_view %zu %zu\n", sizeof(mm_mesh_view), offsetof(mm_mesh_view, faces));
+  printf("mm_sim_info %zu %zu %zu\n", sizeof(mm_sim_info), offsetof(mm_sim_info, floor_hits),
+         offsetof(mm_sim_info, flags));
+  printf("mm_request %zu %zu %zu %zu\n", sizeof(mm_request), offsetof(mm_request, params),
+         offsetof(mm_request, steps), offsetof(mm_request, Q_out));
+  printf("mm_request_result %zu %zu\n", sizeof(mm_request_result), offsetof(mm_request_result, t));
+  printf("mm_serve_stats %zu %zu %zu\n", sizeof(mm_serve_stats), offsetof(mm_serve_stats, step_p99),
+         offsetof(mm_serve_stats, max_resident));
   return 0;
 }
 ''')
@@ -55,6 +62,11 @@ int main(void) {
     assert out["mm_params"] == [ctypes.sizeof(P), P.gamma.offset, P.precision.offset, P.predictor_frame.offset]
     assert out["mm_step_info"] == [ctypes.sizeof(S), S.floor_hits.offset, S.flags.offset]
     assert out["mm_mesh_view"] == [ctypes.sizeof(V), V.faces.offset]
+    I, R, RR, SS = M.SimInfo, M.Request, M.RequestResult, M.ServeStats
+    assert out["mm_sim_info"] == [ctypes.sizeof(I), I.floor_hits.offset, I.flags.offset]
+    assert out["mm_request"] == [ctypes.sizeof(R), R.params.offset, R.steps.offset, R.Q_out.offset]
+    assert out["mm_request_result"] == [ctypes.sizeof(RR), RR.t.offset]
+    assert out["mm_serve_stats"] == [ctypes.sizeof(SS), SS.step_p99.offset, SS.max_resident.offset]
 
 
 def test_defaults_and_version():
@@ -97,6 +109,23 @@ def test_calls_on_null_context_fail_cleanly():
     assert lib.mm_step(None, 10, None, None, None, 1.0, None) == -1
     assert lib.mm_destroy(None) == -1
     assert lib.mm_last_error(None) is not None
+
+
+def test_batch_footprint_and_host_validation():
+    import paper_1707_05333_amd as M
+    lib = M.load_library()
+    f64, mix = M.batch_footprint(1000, "fp64"), M.batch_footprint(1000, "mixed")
+    assert f64 > mix > 0
+    assert M.batch_footprint(2000, "mixed") - mix == mix - M.batch_footprint(0, "mixed")
+    b = ctypes.c_void_p()
+    assert lib.mm_batch_create(ctypes.byref(b), 7, 1 << 30, 8, None) == -1 and not b.value
+    assert lib.mm_batch_create(ctypes.byref(b), M.MM_MIXED, 1 << 30, 0, None) == -1
+    assert lib.mm_batch_create(ctypes.byref(b), M.MM_MIXED, 100, 8, None) == -1
+    assert lib.mm_batch_last_error(None)
+    for fn, args in [("mm_batch_step", (None, None, 0, None)), ("mm_batch_evict", (None, 0)),
+                     ("mm_batch_read", (None, 0, None, None, None)), ("mm_batch_destroy", (None,)),
+                     ("mm_serve", (None, None, 0, None, None))]:
+        assert getattr(lib, fn)(*args) == -1
 
 
 def test_make_params_validates_names():

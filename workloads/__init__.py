@@ -182,6 +182,15 @@ def c4_kelvin_helmholtz(k, n_min=1000, n_max=200000, base_seed=4000) -> Workload
                     steps=20, meta=dict(shape=(side,) * 3, request=int(k)))
 
 
+def poisson_arrivals(n, rate, seed=4) -> np.ndarray:
+    """Arrival times (seconds, non-decreasing, first at 0) of n requests of a
+    Poisson stream with the given rate (requests per second)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / float(rate), size=int(n))
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
+
+
 def uniform_state(pos, box, rho=1.0, vel=(0.0, 0.0, 0.0), P=1.0, gamma=5.0 / 3.0,
                   name="uniform", **over) -> Workload:
     """Uniform density, velocity and pressure on a given point set."""
