@@ -16,6 +16,17 @@ constexpr int kThreads = 256;
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// a / b: correctly rounded in double; in float (the mixed-precision state
+// arithmetic) through the hardware reciprocal, within about one ulp.
+template <typename T>
+__device__ inline T quot(T a, T b) {
+  return a / b;
+}
+template <>
+__device__ inline float quot<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+
 // Floors of Sec. 4.1 on conserved densities: a density below the floor is
 // raised keeping velocity and pressure; a pressure below the floor is raised
 // keeping density and velocity.  Returns 1 if any floor fired.
@@ -26,9 +37,10 @@ __device__ inline int apply_floors(T U[5], T g1, T rho_floor, T p_floor) {
   if (rho < rho_floor) {
     T vx = 0, vy = 0, vz = 0, P = p_floor;
     if (rho > T(0)) {
-      vx = U[1] / rho;
-      vy = U[2] / rho;
-      vz = U[3] / rho;
+      const T ir = quot(T(1), rho);
+      vx = U[1] * ir;
+      vy = U[2] * ir;
+      vz = U[3] * ir;
       P = g1 * (U[4] - T(0.5) * (U[1] * vx + U[2] * vy + U[3] * vz));
     }
     P = P > p_floor ? P : p_floor;
@@ -36,13 +48,13 @@ __device__ inline int apply_floors(T U[5], T g1, T rho_floor, T p_floor) {
     U[1] = rho_floor * vx;
     U[2] = rho_floor * vy;
     U[3] = rho_floor * vz;
-    U[4] = P / g1 + T(0.5) * rho_floor * (vx * vx + vy * vy + vz * vz);
+    U[4] = quot(P, g1) + T(0.5) * rho_floor * (vx * vx + vy * vy + vz * vz);
     hit = 1;
   }
-  const T ke = T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / U[0];
+  const T ke = quot(T(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]), U[0]);
   const T P = g1 * (U[4] - ke);
   if (P < p_floor) {
-    U[4] = p_floor / g1 + ke;
+    U[4] = quot(p_floor, g1) + ke;
     hit = 1;
   }
   return hit;
@@ -54,14 +66,15 @@ __device__ inline int apply_floors(T U[5], T g1, T rho_floor, T p_floor) {
 template <typename T>
 __device__ inline void state_rate(const T U[5], const T g[15], const T wv[3], T g1, bool moving, T out[5]) {
   const T rho = U[0];
-  const T v[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+  const T ir = quot(T(1), rho);
+  const T v[3] = {U[1] * ir, U[2] * ir, U[3] * ir};
   const T vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
   const T P = g1 * (U[4] - T(0.5) * rho * vv);
   T dP[3], divv = 0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     dP[d] = g1 * (g[12 + d] - (v[0] * g[3 + d] + v[1] * g[6 + d] + v[2] * g[9 + d]) + T(0.5) * vv * g[d]);
-    divv += (g[3 * (1 + d) + d] - v[d] * g[d]) / rho;
+    divv += (g[3 * (1 + d) + d] - v[d] * g[d]) * ir;
   }
   T div[5];
   div[0] = g[3 + 0] + g[6 + 1] + g[9 + 2];
@@ -79,10 +92,11 @@ __device__ inline void state_rate(const T U[5], const T g[15], const T wv[3], T 
 }
 
 // Euler flux along unit normal n of a face-frame state (rho, v, P).
+// ig1 = 1 / (gamma - 1).
 template <typename T>
-__device__ inline void euler_flux(T rho, const T v[3], T P, const T n[3], T g1, T F[5]) {
+__device__ inline void euler_flux(T rho, const T v[3], T P, const T n[3], T ig1, T F[5]) {
   const T u = v[0] * n[0] + v[1] * n[1] + v[2] * n[2];
-  const T E = P / g1 + T(0.5) * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  const T E = P * ig1 + T(0.5) * rho * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
   F[0] = rho * u;
   F[1] = rho * u * v[0] + P * n[0];
   F[2] = rho * u * v[1] + P * n[1];
@@ -94,15 +108,18 @@ __device__ inline void euler_flux(T rho, const T v[3], T P, const T n[3], T g1, 
 // items 3-5): both lab-frame states are boosted to the face frame, HLLC with
 // Davis wave-speed bounds gives the face-frame flux, and the flux is boosted
 // back (mass flux unchanged; momentum + wt F_rho; energy + wt.F_m +
-// |wt|^2/2 F_rho).
+// |wt|^2/2 F_rho).  The reciprocal densities are formed once per side.
 template <typename T>
 __device__ inline void moving_hllc(const T UL[5], const T UR[5], const T n[3], const T wt[3], T gamma, T F[5]) {
   const T g1 = gamma - T(1);
+  const T ig1 = quot(T(1), g1);
+  const T rL = UL[0], rR = UR[0];
+  const T irL = quot(T(1), rL), irR = quot(T(1), rR);
   T vL[3], vR[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    vL[a] = UL[1 + a] / UL[0];
-    vR[a] = UR[1 + a] / UR[0];
+    vL[a] = UL[1 + a] * irL;
+    vR[a] = UR[1 + a] * irR;
   }
   const T PL = g1 * (UL[4] - T(0.5) * (UL[1] * vL[0] + UL[2] * vL[1] + UL[3] * vL[2]));
   const T PR = g1 * (UR[4] - T(0.5) * (UR[1] * vR[0] + UR[2] * vR[1] + UR[3] * vR[2]));
@@ -111,31 +128,32 @@ __device__ inline void moving_hllc(const T UL[5], const T UR[5], const T n[3], c
     vL[a] -= wt[a];
     vR[a] -= wt[a];
   }
-  const T rL = UL[0], rR = UR[0];
   const T uL = vL[0] * n[0] + vL[1] * n[1] + vL[2] * n[2];
   const T uR = vR[0] * n[0] + vR[1] * n[1] + vR[2] * n[2];
-  const T cL = sqrt(gamma * PL / rL), cR = sqrt(gamma * PR / rR);
+  const T cL = sqrt(gamma * PL * irL), cR = sqrt(gamma * PR * irR);
   const T SL = fmin(uL - cL, uR - cR);
   const T SR = fmax(uL + cL, uR + cR);
   T Ff[5];
   if (SL >= T(0)) {
-    euler_flux(rL, vL, PL, n, g1, Ff);
+    euler_flux(rL, vL, PL, n, ig1, Ff);
   } else if (SR < T(0)) {
-    euler_flux(rR, vR, PR, n, g1, Ff);
+    euler_flux(rR, vR, PR, n, ig1, Ff);
   } else {
-    const T Ss = (PR - PL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
+    const T Ss = quot(PR - PL + rL * uL * (SL - uL) - rR * uR * (SR - uR), rL * (SL - uL) - rR * (SR - uR));
     const bool left = Ss >= T(0);
     const T rK = left ? rL : rR, uK = left ? uL : uR, PK = left ? PL : PR, SK = left ? SL : SR;
+    const T irK = left ? irL : irR;
     const T* vK = left ? vL : vR;
     T FK[5];
-    euler_flux(rK, vK, PK, n, g1, FK);
-    const T EK = PK / g1 + T(0.5) * rK * (vK[0] * vK[0] + vK[1] * vK[1] + vK[2] * vK[2]);
-    const T fac = rK * (SK - uK) / (SK - Ss);
+    euler_flux(rK, vK, PK, n, ig1, FK);
+    const T EK = PK * ig1 + T(0.5) * rK * (vK[0] * vK[0] + vK[1] * vK[1] + vK[2] * vK[2]);
+    const T a = SK - uK;
+    const T fac = quot(rK * a, SK - Ss);
     const T du = Ss - uK;
     Ff[0] = FK[0] + SK * (fac - rK);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) Ff[1 + a] = FK[1 + a] + SK * (fac * (vK[a] + du * n[a]) - rK * vK[a]);
-    Ff[4] = FK[4] + SK * (fac * (EK / rK + du * (Ss + PK / (rK * (SK - uK)))) - EK);
+    for (int q = 0; q < 3; ++q) Ff[1 + q] = FK[1 + q] + SK * (fac * (vK[q] + du * n[q]) - rK * vK[q]);
+    Ff[4] = FK[4] + SK * (fac * (EK * irK + du * (Ss + quot(PK * irK, a))) - EK);
   }
   const T w2 = wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2];
   F[0] = Ff[0];
@@ -144,15 +162,17 @@ __device__ inline void moving_hllc(const T UL[5], const T UR[5], const T n[3], c
   F[4] = Ff[4] + wt[0] * Ff[1] + wt[1] * Ff[2] + wt[2] * Ff[3] + T(0.5) * w2 * Ff[0];
 }
 
-// Duffell-MacFadyen factor on one face (Sec. 4.1): the extrapolation D from
+// Duffell-MacFadyen limit on one face (Sec. 4.1): the extrapolation D from
 // the centroid to the face may not exceed theta times the jump dU to the
-// neighbour, nor oppose its sign.
+// neighbour, nor oppose its sign.  Returns beta D with
+// beta = min(1, max(0, theta dU / D)), which is D, 0 or theta dU, so no
+// division is needed; theta <= 0 switches the limit off (beta = 1).
 template <typename T>
-__device__ inline T dm_factor(T theta, T dU, T D) {
-  if (theta <= T(0) || D == T(0)) return T(1);
-  T b = theta * dU / D;
-  b = b > T(0) ? b : T(0);
-  return b < T(1) ? b : T(1);
+__device__ inline T dm_limited(T theta, T dU, T D) {
+  if (theta <= T(0)) return D;
+  const T t = theta * dU;
+  if (!(t * D > T(0))) return T(0);   // opposite signs, or a zero jump or extrapolation
+  return fabs(t) < fabs(D) ? t : D;
 }
 
 // ---------------------------------------------------------------------------
@@ -270,14 +290,18 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict__ segs,
                                                        const int32_t* __restrict__ sseg, int64_t n,
                                                        const R* __restrict__ U,
-                                                       const unsigned long long* __restrict__ off,
+                                                       const unsigned long long* __restrict__ counts,
+                                                       const unsigned long long* __restrict__ soff,
                                                        const NbrEntry* __restrict__ nbr,
                                                        const double* __restrict__ minv, int limit, R* __restrict__ G,
                                                        const double* __restrict__ w, const SegStatus* dt_src,
-                                                       double dt_fixed, R* __restrict__ Uh, SegStatus* segst) {
+                                                       double dt_fixed, R* __restrict__ Uh,
+                                                       FluxCell<R>* __restrict__ rec, const double* __restrict__ geo,
+                                                       const double* __restrict__ spos, SegStatus* segst) {
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  const int64_t e0 = (int64_t)(off[s] >> 32), e1 = (int64_t)(off[s + 1] >> 32);
+  const int nf = (int)(counts[s] >> 32);
+  const NbrEntry* list = nbr + sell_slot(soff, s, 0);   // entry e at list[64 e]
   R ui[5], umax[5], umin[5], b[15];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
@@ -287,8 +311,8 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
   }
 #pragma unroll
   for (int k = 0; k < 15; ++k) b[k] = R(0);
-  for (int64_t e = e0; e < e1; ++e) {
-    const NbrEntry E = nbr[e];
+  for (int e = 0; e < nf; ++e) {
+    const NbrEntry E = list[64 * e];
     const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2], wg = (R)E.wgt;
     const R* uo = U + 5 * (int64_t)E.o;
 #pragma unroll
@@ -316,29 +340,58 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
   const bool lim = limit < kLimitMaskBit0 ? limit != kLimitOff
                                           : ((segs[seg].hp.limit_mask >> (limit - kLimitMaskBit0)) & 1) != 0;
   if (lim) {
-    R alpha[5] = {R(1), R(1), R(1), R(1), R(1)};
-    for (int64_t e = e0; e < e1; ++e) {
-      const NbrEntry E = nbr[e];
+    // alpha = min(1, min_j psi_j) with psi_j = (U^max - U_i) / D_j for
+    // D_j > 0 and (U^min - U_i) / D_j for D_j < 0.  Over the neighbours with
+    // D_j > 0 the smallest quotient is the one with the largest D_j
+    // (correctly rounded division is monotone), and likewise for D_j < 0,
+    // so two divisions per component give the same value as one per
+    // neighbour.
+    R dpos[5], dneg[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) dpos[q] = dneg[q] = R(0);
+    for (int e = 0; e < nf; ++e) {
+      const NbrEntry E = list[64 * e];
       const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
         const R D = g[3 * q] * dx + g[3 * q + 1] * dy + g[3 * q + 2] * dz;
-        R psi = R(1);
-        if (D > R(0)) psi = (umax[q] - ui[q]) / D;
-        else if (D < R(0)) psi = (umin[q] - ui[q]) / D;
-        alpha[q] = psi < alpha[q] ? psi : alpha[q];
+        dpos[q] = D > dpos[q] ? D : dpos[q];
+        dneg[q] = D < dneg[q] ? D : dneg[q];
       }
     }
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      g[3 * q] *= alpha[q];
-      g[3 * q + 1] *= alpha[q];
-      g[3 * q + 2] *= alpha[q];
+      R alpha = R(1);
+      if (dpos[q] > R(0)) {
+        const R psi = quot(umax[q] - ui[q], dpos[q]);
+        alpha = psi < alpha ? psi : alpha;
+      }
+      if (dneg[q] < R(0)) {
+        const R psi = quot(umin[q] - ui[q], dneg[q]);
+        alpha = psi < alpha ? psi : alpha;
+      }
+      g[3 * q] *= alpha;
+      g[3 * q + 1] *= alpha;
+      g[3 * q + 2] *= alpha;
     }
   }
   if (G) {
 #pragma unroll
     for (int k = 0; k < 15; ++k) G[15 * s + k] = g[k];
+  }
+  if (rec) {
+    FluxCell<R> C;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) C.U[q] = ui[q];
+#pragma unroll
+    for (int k = 0; k < 15; ++k) C.G[k] = g[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      C.w[a] = w[3 * s + a];
+      C.c[a] = geo[4 * s + 1 + a];
+      C.r[a] = spos[3 * s + a];
+    }
+    rec[s] = C;
   }
   if (Uh) {
     const HydroParams& hp = segs[seg].hp;
@@ -391,9 +444,7 @@ template <typename R>
 __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ segs, int64_t nf_host,
                                                    const unsigned long long* __restrict__ nf_dev,
                                                    const Face* __restrict__ faces,
-                                                   const double* __restrict__ spos, const double* __restrict__ geo,
-                                                   const R* __restrict__ Uh, const R* __restrict__ Gh,
-                                                   const double* __restrict__ w, const SegStatus* dt_src,
+                                                   const FluxCell<R>* __restrict__ rec, const SegStatus* dt_src,
                                                    double dt_fixed, R* __restrict__ phi, SegStatus* segst) {
   const int64_t nf = nf_dev ? std::min<int64_t>((int64_t)*nf_dev, nf_host) : nf_host;
   const int64_t xcd = blockIdx.x % kXcds, kb = blockIdx.x / kXcds;
@@ -401,41 +452,38 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
   const int64_t lo = nf * xcd / kXcds, hi = nf * (xcd + 1) / kXcds;
   for (int64_t f = lo + kb * blockDim.x + threadIdx.x; f < hi; f += nbx * blockDim.x) {
     const Face F = faces[f];
-    const int64_t i = F.i, j = F.j;
+    const FluxCell<R> A = rec[F.i];
+    const FluxCell<R> B = rec[F.j];
     const int seg = F.seg;
     const HydroParams& hp = segs[seg].hp;
     int kx, ky, kz;
     decode(F.code, kx, ky, kz);
     // Geometry in double: r_j + s - r_i, face centre and centroid offsets.
-    const double drx = (spos[3 * j] + kx * hp.L[0]) - spos[3 * i];
-    const double dry = (spos[3 * j + 1] + ky * hp.L[1]) - spos[3 * i + 1];
-    const double drz = (spos[3 * j + 2] + kz * hp.L[2]) - spos[3 * i + 2];
+    const double drx = (B.r[0] + kx * hp.L[0]) - A.r[0];
+    const double dry = (B.r[1] + ky * hp.L[1]) - A.r[1];
+    const double drz = (B.r[2] + kz * hp.L[2]) - A.r[2];
     const double len = sqrt(drx * drx + dry * dry + drz * drz);
-    const double nx = drx / len, ny = dry / len, nz = drz / len;
-    const double wix = w[3 * i], wiy = w[3 * i + 1], wiz = w[3 * i + 2];
-    const double wjx = w[3 * j], wjy = w[3 * j + 1], wjz = w[3 * j + 2];
+    const double ilen = 1.0 / len;
+    const double nx = drx * ilen, ny = dry * ilen, nz = drz * ilen;
     // Face velocity (Sec. 4 item 1): bisector's normal speed at the face
     // centre plus the mean generator velocity.
-    const double sn = ((wix - wjx) * (F.f[0] - 0.5 * drx) + (wiy - wjy) * (F.f[1] - 0.5 * dry) +
-                       (wiz - wjz) * (F.f[2] - 0.5 * drz)) / len;
-    const R wt[3] = {(R)(sn * nx + 0.5 * (wix + wjx)), (R)(sn * ny + 0.5 * (wiy + wjy)),
-                     (R)(sn * nz + 0.5 * (wiz + wjz))};
+    const double sn = ((A.w[0] - B.w[0]) * (F.f[0] - 0.5 * drx) + (A.w[1] - B.w[1]) * (F.f[1] - 0.5 * dry) +
+                       (A.w[2] - B.w[2]) * (F.f[2] - 0.5 * drz)) * ilen;
+    const R wt[3] = {(R)(sn * nx + 0.5 * (A.w[0] + B.w[0])), (R)(sn * ny + 0.5 * (A.w[1] + B.w[1])),
+                     (R)(sn * nz + 0.5 * (A.w[2] + B.w[2]))};
     const R nrm[3] = {(R)nx, (R)ny, (R)nz};
     // f - c_i and f - (c_j + s), with f and c relative to the generators.
-    const R fi[3] = {(R)(F.f[0] - geo[4 * i + 1]), (R)(F.f[1] - geo[4 * i + 2]), (R)(F.f[2] - geo[4 * i + 3])};
-    const R fj[3] = {(R)(F.f[0] - drx - geo[4 * j + 1]), (R)(F.f[1] - dry - geo[4 * j + 2]),
-                     (R)(F.f[2] - drz - geo[4 * j + 3])};
+    const R fi[3] = {(R)(F.f[0] - A.c[0]), (R)(F.f[1] - A.c[1]), (R)(F.f[2] - A.c[2])};
+    const R fj[3] = {(R)(F.f[0] - drx - B.c[0]), (R)(F.f[1] - dry - B.c[1]), (R)(F.f[2] - drz - B.c[2])};
     const R theta = (R)hp.theta;
     R UL[5], UR[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      const R ui = Uh[5 * i + q], uj = Uh[5 * j + q];
-      const R* gi = Gh + 15 * i + 3 * q;
-      const R* gj = Gh + 15 * j + 3 * q;
-      const R Di = gi[0] * fi[0] + gi[1] * fi[1] + gi[2] * fi[2];
-      const R Dj = gj[0] * fj[0] + gj[1] * fj[1] + gj[2] * fj[2];
-      UL[q] = ui + dm_factor(theta, uj - ui, Di) * Di;
-      UR[q] = uj + dm_factor(theta, ui - uj, Dj) * Dj;
+      const R ui = A.U[q], uj = B.U[q];
+      const R Di = A.G[3 * q] * fi[0] + A.G[3 * q + 1] * fi[1] + A.G[3 * q + 2] * fi[2];
+      const R Dj = B.G[3 * q] * fj[0] + B.G[3 * q + 1] * fj[1] + B.G[3 * q + 2] * fj[2];
+      UL[q] = ui + dm_limited(theta, uj - ui, Di);
+      UR[q] = uj + dm_limited(theta, ui - uj, Dj);
     }
     const R g1 = (R)(hp.gamma - 1.0);
     int hit = apply_floors(UL, g1, (R)hp.rho_floor, (R)hp.p_floor);
@@ -449,17 +497,38 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
   }
 }
 
+template <typename R>
+__global__ void k_pack_flux_cells(int64_t n, const R* __restrict__ U, const R* __restrict__ G,
+                                  const double* __restrict__ w, const double* __restrict__ geo,
+                                  const double* __restrict__ spos, FluxCell<R>* __restrict__ rec) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  FluxCell<R> C;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) C.U[q] = U[5 * s + q];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) C.G[k] = G[15 * s + k];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    C.w[a] = w[3 * s + a];
+    C.c[a] = geo[4 * s + 1 + a];
+    C.r[a] = spos[3 * s + a];
+  }
+  rec[s] = C;
+}
+
 // Per-cell sum of the face fluxes through the CSR list in a fixed order:
 // the owner side loses phi, the neighbour side gains it (Sec. 4, update of
 // the charges).  Accumulation in double.
 template <typename R>
-__device__ inline void cell_flux_sum(int64_t s, const unsigned long long* off, const int32_t* csr, const R* phi,
-                                     double acc[5]) {
-  const int64_t e0 = (int64_t)(off[s] >> 32), e1 = (int64_t)(off[s + 1] >> 32);
+__device__ inline void cell_flux_sum(int64_t s, const unsigned long long* counts, const unsigned long long* soff,
+                                     const int32_t* csr, const R* phi, double acc[5]) {
+  const int nf = (int)(counts[s] >> 32);
+  const int32_t* list = csr + sell_slot(soff, s, 0);   // entry e at list[64 e]
 #pragma unroll
   for (int q = 0; q < 5; ++q) acc[q] = 0.0;
-  for (int64_t e = e0; e < e1; ++e) {
-    const int32_t cf = csr[e];
+  for (int e = 0; e < nf; ++e) {
+    const int32_t cf = list[64 * e];
     const int64_t fid = cf & 0x7fffffff;
     const double sg = cf < 0 ? 1.0 : -1.0;
 #pragma unroll
@@ -470,7 +539,8 @@ __device__ inline void cell_flux_sum(int64_t s, const unsigned long long* off, c
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__ segs,
                                                      const int32_t* __restrict__ sseg, int64_t n,
-                                                     const unsigned long long* __restrict__ off,
+                                                     const unsigned long long* __restrict__ counts,
+                                                     const unsigned long long* __restrict__ soff,
                                                      const int32_t* __restrict__ csr, const R* __restrict__ phi,
                                                      const double* __restrict__ geo, const int32_t* __restrict__ perm,
                                                      const double* __restrict__ Qs, double* __restrict__ Qc,
@@ -482,7 +552,7 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
   const int seg = sseg[s];
   const HydroParams& hp = segs[seg].hp;
   double acc[5], Q[5];
-  cell_flux_sum(s, off, csr, phi, acc);
+  cell_flux_sum(s, counts, soff, csr, phi, acc);
 #pragma unroll
   for (int q = 0; q < 5; ++q) Q[q] = Qs[5 * s + q] + acc[q];
   // Floors at the cell centre after the step, with the time-n volume.
@@ -517,13 +587,14 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_accumulate(int64_t n, const unsigned long long* __restrict__ off,
+__global__ __launch_bounds__(kThreads) void k_accumulate(int64_t n, const unsigned long long* __restrict__ counts,
+                                                         const unsigned long long* __restrict__ soff,
                                                          const int32_t* __restrict__ csr, const R* __restrict__ phi,
                                                          const int32_t* __restrict__ perm, double* __restrict__ dQc) {
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
   double acc[5];
-  cell_flux_sum(s, off, csr, phi, acc);
+  cell_flux_sum(s, counts, soff, csr, phi, acc);
   const int64_t c = perm[s];
 #pragma unroll
   for (int q = 0; q < 5; ++q) dQc[5 * c + q] = acc[q];
@@ -587,12 +658,21 @@ void launch_cell_state(const SegDesc* segs, const int32_t* sseg, int64_t n, cons
 
 template <typename R>
 void launch_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U,
-                     const unsigned long long* csr_off, const NbrEntry* nbr, const double* minv, int limit, R* G,
-                     const double* w, const SegStatus* dt_src, double dt_fixed, R* U_half, SegStatus* segst,
+                     const unsigned long long* counts, const unsigned long long* soff, const NbrEntry* nbr,
+                     const double* minv, int limit, R* G, const double* w, const SegStatus* dt_src, double dt_fixed,
+                     R* U_half, FluxCell<R>* rec, const double* geo, const double* spos, SegStatus* segst,
                      hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gradient<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, U, csr_off,
-                     nbr, minv, limit, G, w, dt_src, dt_fixed, U_half, segst);
+  hipLaunchKernelGGL(k_gradient<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, U, counts,
+                     soff, nbr, minv, limit, G, w, dt_src, dt_fixed, U_half, rec, geo, spos, segst);
+}
+
+template <typename R>
+void launch_pack_flux_cells(int64_t n, const R* U, const R* G, const double* w, const double* geo,
+                            const double* spos, FluxCell<R>* rec, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pack_flux_cells<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, U, G, w, geo,
+                     spos, rec);
 }
 
 template <typename R>
@@ -605,32 +685,33 @@ void launch_predict(const SegDesc* segs, const int32_t* sseg, int64_t n, const R
 
 template <typename R>
 void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
-                 const double* spos, const double* geo, const R* Uh, const R* Gh, const double* w,
-                 const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst, hipStream_t st) {
+                 const FluxCell<R>* rec, const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst,
+                 hipStream_t st) {
   if (nf_host <= 0) return;
   // Enough resident blocks to fill the chip; each strides through its XCD's
   // part of the (device-counted) face list.
   const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(nf_host, kThreads), 4096);
-  hipLaunchKernelGGL(k_flux<R>, dim3(blocks), dim3(kThreads), 0, st, segs, nf_host, nf_dev, faces, spos, geo, Uh, Gh,
-                     w, dt_src, dt_fixed, phi, segst);
+  hipLaunchKernelGGL(k_flux<R>, dim3(blocks), dim3(kThreads), 0, st, segs, nf_host, nf_dev, faces, rec, dt_src,
+                     dt_fixed, phi, segst);
 }
 
 template <typename R>
-void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* csr_off,
-                   const int32_t* csr, const R* phi, const double* geo, const int32_t* perm, const double* Qs,
-                   double* Q_slots, const double* spos, const double* w, double* pos_slots, double* w_slots,
-                   const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
+void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* counts,
+                   const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo,
+                   const int32_t* perm, const double* Qs, double* Q_slots, const double* spos, const double* w,
+                   double* pos_slots, double* w_slots, const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst,
+                   hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_update<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, csr_off, csr,
-                     phi, geo, perm, Qs, Q_slots, spos, w, pos_slots, w_slots, dt_src, st_dev, segst);
+  hipLaunchKernelGGL(k_update<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, counts, soff,
+                     csr, phi, geo, perm, Qs, Q_slots, spos, w, pos_slots, w_slots, dt_src, st_dev, segst);
 }
 
 template <typename R>
-void launch_accumulate(int64_t n, const unsigned long long* csr_off, const int32_t* csr, const R* phi,
-                       const int32_t* perm, double* dQ_slots, hipStream_t st) {
+void launch_accumulate(int64_t n, const unsigned long long* counts, const unsigned long long* soff, const int32_t* csr,
+                       const R* phi, const int32_t* perm, double* dQ_slots, hipStream_t st) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_accumulate<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, csr_off, csr, phi,
-                     perm, dQ_slots);
+  hipLaunchKernelGGL(k_accumulate<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, counts, soff, csr,
+                     phi, perm, dQ_slots);
 }
 
 template <typename R>
@@ -664,19 +745,21 @@ void launch_copy_rows(const double* src, double* dst, int64_t n, int width, hipS
   template void launch_cell_state<R>(const SegDesc*, const int32_t*, int64_t, const double*, const int32_t*,      \
                                      const double*, double*, R*, double*, DevStatus*, SegStatus*, hipStream_t);   \
   template void launch_gradient<R>(const SegDesc*, const int32_t*, int64_t, const R*, const unsigned long long*,  \
-                                   const NbrEntry*, const double*, int, R*, const double*, const SegStatus*,      \
-                                   double, R*, SegStatus*, hipStream_t);                                          \
+                                   const unsigned long long*, const NbrEntry*, const double*, int, R*,            \
+                                   const double*, const SegStatus*, double, R*, FluxCell<R>*, const double*,      \
+                                   const double*, SegStatus*, hipStream_t);                                       \
+  template void launch_pack_flux_cells<R>(int64_t, const R*, const R*, const double*, const double*,              \
+                                          const double*, FluxCell<R>*, hipStream_t);                              \
   template void launch_predict<R>(const SegDesc*, const int32_t*, int64_t, const R*, const R*, const double*,     \
                                   const SegStatus*, double, R*, SegStatus*, hipStream_t);                         \
-  template void launch_flux<R>(const SegDesc*, int64_t, const unsigned long long*, const Face*, const double*,    \
-                               const double*, const R*, const R*, const double*, const SegStatus*, double, R*,   \
-                               SegStatus*, hipStream_t);                                                          \
+  template void launch_flux<R>(const SegDesc*, int64_t, const unsigned long long*, const Face*,                    \
+                               const FluxCell<R>*, const SegStatus*, double, R*, SegStatus*, hipStream_t);        \
   template void launch_update<R>(const SegDesc*, const int32_t*, int64_t, const unsigned long long*,              \
-                                 const int32_t*, const R*, const double*, const int32_t*, const double*, double*, \
-                                 const double*, const double*, double*, double*, const SegStatus*, DevStatus*,    \
-                                 SegStatus*, hipStream_t);                                                        \
-  template void launch_accumulate<R>(int64_t, const unsigned long long*, const int32_t*, const R*, const int32_t*, \
-                                     double*, hipStream_t);                                                       \
+                                 const unsigned long long*, const int32_t*, const R*, const double*,              \
+                                 const int32_t*, const double*, double*, const double*, const double*, double*,   \
+                                 double*, const SegStatus*, DevStatus*, SegStatus*, hipStream_t);                 \
+  template void launch_accumulate<R>(int64_t, const unsigned long long*, const unsigned long long*,               \
+                                     const int32_t*, const R*, const int32_t*, double*, hipStream_t);             \
   template void launch_gather_rows<R>(const R*, const int32_t*, int64_t, int, R*, hipStream_t);                   \
   template void launch_scatter_rows<R>(const R*, const int32_t*, int64_t, int, R*, hipStream_t);
 

@@ -1,10 +1,16 @@
 // Mesh assembly after the tessellation: unique faces (each stored once, by
-// the cell with the lower internal index), the per-cell face lists (CSR) used
-// to apply every face flux to both of its cells with opposite signs (Sec. 4,
-// eq. "time evolution"), the per-cell neighbour entries of the least-squares
-// gradient (centroid displacements and weights, Sec. 4.1) and the inverse of
-// each cell's 3x3 least-squares matrix.  Also the exports of the mesh to the
-// caller's point order.
+// the cell with the lower internal index), the per-cell face lists used to
+// apply every face flux to both of its cells with opposite signs (Sec. 4,
+// update of the charges), the per-cell neighbour entries of the
+// least-squares gradient (centroid displacements and weights, Sec. 4.1) and
+// the inverse of each cell's 3x3 least-squares matrix.  Also the exports of
+// the mesh to the caller's point order.
+//
+// Per-cell lists use a sliced ELL layout: cells are taken in slices of 64
+// consecutive internal cells, a slice is as wide as its longest list, and
+// entry e of cell s sits at soff[s / 64] + 64 e + s % 64.  A wavefront
+// that walks the lists of 64 consecutive cells in step then reads one
+// contiguous row per step.
 #include "mm_internal.h"
 
 namespace mm {
@@ -13,39 +19,52 @@ namespace {
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// One thread per cell.  The packed prefix sum off[] holds, for cell s, the
-// index of its first unique face in the low 32 bits and of its first CSR
-// entry in the high 32 bits.
-__global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ spos, const double* __restrict__ geo,
-                                                    int64_t n, const SegDesc* __restrict__ segs,
-                                                    const int32_t* __restrict__ sseg,
-                                                    const StageNbr* __restrict__ stage_nb,
-                                                    const StageGeo* __restrict__ stage_geo,
-                                                    const unsigned long long* __restrict__ counts,
-                                                    const unsigned long long* __restrict__ off, int64_t face_cap,
-                                                    Face* __restrict__ faces, int32_t* __restrict__ csr,
-                                                    NbrEntry* __restrict__ nbr, double* __restrict__ minv,
-                                                    DevStatus* st, SegStatus* segst) {
-  __shared__ int smax[256];
-  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
-  int nf = 0;
-  if (s < n) {
-    const int seg = sseg[s];
+constexpr int kGroup = 16;                       // lanes per cell in the assembly
+constexpr int kMeshThreads = 256;
+constexpr int kCellsPerBlock = kMeshThreads / kGroup;
+
+// 64 times the longest list of each slice of 64 cells (one wavefront per slice).
+__global__ __launch_bounds__(256) void k_slice_width(const unsigned long long* __restrict__ counts, int64_t n,
+                                                     unsigned long long* __restrict__ sw) {
+  const int64_t k = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t s = 64 * k + __lane_id();
+  const int64_t nslices = (n + 63) / 64;
+  int w = s < n ? (int)(counts[s] >> 32) : 0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o, 64));
+  if (k < nslices && __lane_id() == 0) sw[k] = 64ull * (unsigned long long)w;
+}
+
+// Sixteen lanes per cell; lane l takes the cell's faces l, l + 16, ...
+// The packed prefix sum off[] holds, for cell s, the index of its first
+// unique face in its low 32 bits.
+__global__ __launch_bounds__(kMeshThreads) void k_build_mesh(
+    const double* __restrict__ spos, const double* __restrict__ geo, int64_t n, const SegDesc* __restrict__ segs,
+    const int32_t* __restrict__ sseg, const StageNbr* __restrict__ stage_nb, const StageGeo* __restrict__ stage_geo,
+    const unsigned long long* __restrict__ counts, const unsigned long long* __restrict__ off,
+    const unsigned long long* __restrict__ soff, int64_t face_cap, int64_t sell_cap, Face* __restrict__ faces,
+    int32_t* __restrict__ csr, NbrEntry* __restrict__ nbr, double* __restrict__ minv, DevStatus* st,
+    SegStatus* segst) {
+  __shared__ int smax[kMeshThreads / 64];
+  const int l = threadIdx.x & (kGroup - 1);
+  const int64_t s = xcd_block() * kCellsPerBlock + (threadIdx.x / kGroup);
+  const bool active = s < n;
+  double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
+  int nf = 0, bad = 0, seg = 0;
+  if (active) {
+    seg = sseg[s];
     const double L[3] = {segs[seg].g.L[0], segs[seg].g.L[1], segs[seg].g.L[2]};
-    const unsigned long long cnt = counts[s];
-    nf = (int)(cnt >> 32);
-    const unsigned long long o = off[s];
-    const int64_t face_base = (int64_t)(o & 0xffffffffull);
-    const int64_t csr_base = (int64_t)(o >> 32);
-    const double rx = spos[3 * s], ry = spos[3 * s + 1], rz = spos[3 * s + 2];
-    const double cix = geo[4 * s + 1], ciy = geo[4 * s + 2], ciz = geo[4 * s + 3];
-    double m00 = 0, m01 = 0, m02 = 0, m11 = 0, m12 = 0, m22 = 0;
-    int bad = 0;
-    if (csr_base + nf > 2 * face_cap) {   // directed faces beyond the CSR capacity
+    nf = (int)(counts[s] >> 32);
+    const int64_t face_base = (int64_t)(off[s] & 0xffffffffull);
+    const int64_t slice = s >> 6;
+    const int64_t sbase = (int64_t)soff[slice] + (s & 63);
+    if ((int64_t)soff[slice + 1] > sell_cap) {   // lists beyond the list capacity
       nf = 0;
       bad |= F_FACECAP;
     }
-    for (int e = 0; e < nf; ++e) {
+    const double rx = spos[3 * s], ry = spos[3 * s + 1], rz = spos[3 * s + 2];
+    const double cix = geo[4 * s + 1], ciy = geo[4 * s + 2], ciz = geo[4 * s + 3];
+    for (int e = l; e < nf; e += kGroup) {
       const StageNbr Nb = stage_nb[s * kMaxFaces + e];
       const StageGeo F = stage_geo[s * kMaxFaces + e];
       const int j = Nb.j;
@@ -69,7 +88,8 @@ __global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ s
       E.d[1] = dy;
       E.d[2] = dz;
       E.wgt = wgt;
-      nbr[csr_base + e] = E;
+      const int64_t slot = sbase + 64ll * e;
+      nbr[slot] = E;
       m00 += wgt * dx * dx;
       m01 += wgt * dx * dy;
       m02 += wgt * dx * dz;
@@ -116,8 +136,21 @@ __global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ s
           else bad |= F_FACECAP;
         }
       }
-      csr[csr_base + e] = entry;
+      csr[slot] = entry;
     }
+  }
+  // Least-squares matrix summed over the group's lanes, and its failures.
+#pragma unroll
+  for (int o = kGroup / 2; o > 0; o >>= 1) {
+    m00 += __shfl_xor(m00, o, kGroup);
+    m01 += __shfl_xor(m01, o, kGroup);
+    m02 += __shfl_xor(m02, o, kGroup);
+    m11 += __shfl_xor(m11, o, kGroup);
+    m12 += __shfl_xor(m12, o, kGroup);
+    m22 += __shfl_xor(m22, o, kGroup);
+    bad |= __shfl_xor(bad, o, kGroup);
+  }
+  if (active && l == 0) {
     // Inverse of the symmetric least-squares matrix by its adjugate.
     const double a00 = m11 * m22 - m12 * m12;
     const double a01 = m02 * m12 - m01 * m22;
@@ -139,13 +172,17 @@ __global__ __launch_bounds__(256) void k_build_mesh(const double* __restrict__ s
     }
     if (bad) seg_fail(st, segst, seg, bad, (int)s);
   }
-  smax[threadIdx.x] = nf;
+  // Largest face count of the block.
+  int mx = nf;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+  if (__lane_id() == 0) smax[threadIdx.x >> 6] = mx;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + w]);
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = smax[0];
+    for (int k = 1; k < kMeshThreads / 64; ++k) t = max(t, smax[k]);
+    if (t > 0) atomicMax(&st->max_faces, t);
   }
-  if (threadIdx.x == 0 && smax[0] > 0) atomicMax(&st->max_faces, smax[0]);
 }
 
 __global__ void k_copy_totals(const unsigned long long* off, int64_t n, DevStatus* st) {
@@ -185,11 +222,17 @@ __global__ void k_export_faces(int64_t nf, const int32_t* __restrict__ perm, con
 
 void launch_build_mesh(const double* spos, const double* geo, int64_t n, const SegDesc* segs, const int32_t* sseg,
                        const StageNbr* stage_nb, const StageGeo* stage_geo, const unsigned long long* counts,
-                       const unsigned long long* off, int64_t face_cap, Face* faces, int32_t* csr, NbrEntry* nbr,
-                       double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_build_mesh, dim3(blocks_for(n, 256)), dim3(256), 0, st, spos, geo, n, segs, sseg, stage_nb,
-                       stage_geo, counts, off, face_cap, faces, csr, nbr, minv, st_dev, segst);
+                       const unsigned long long* off, unsigned long long* sw, unsigned long long* soff,
+                       unsigned long long* scan_tmp, int64_t face_cap, int64_t sell_cap, Face* faces, int32_t* csr,
+                       NbrEntry* nbr, double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
+  if (n > 0) {
+    const int64_t nslices = (n + 63) / 64;
+    hipLaunchKernelGGL(k_slice_width, dim3(blocks_for(nslices, 4)), dim3(256), 0, st, counts, n, sw);
+    scan_u64(sw, soff, nslices, scan_tmp, st);
+    hipLaunchKernelGGL(k_build_mesh, dim3(blocks_for(n, kCellsPerBlock)), dim3(kMeshThreads), 0, st, spos, geo, n,
+                       segs, sseg, stage_nb, stage_geo, counts, off, soff, face_cap, sell_cap, faces, csr, nbr, minv,
+                       st_dev, segst);
+  }
   hipLaunchKernelGGL(k_copy_totals, dim3(1), dim3(64), 0, st, off, n, st_dev);
 }
 

@@ -273,8 +273,26 @@ __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const 
 }
 
 // Orders the gathered candidates by distance; ties by neighbour and image,
-// so the order does not depend on how the stencil was walked.
+// so the order does not depend on how the stencil was walked.  Exact ties
+// are rare (lattice symmetries), so the ranks are first taken by distance
+// alone and redone with the identities only when some distance repeats.
 __device__ void sort_candidates(TessLds& S, const int nc) {
+  bool tie = false;
+  for (int c = __lane_id(); c < nc; c += 64) {
+    const double key = S.cd[c].w;
+    int lt = 0, eq = 0;
+    for (int m = 0; m < nc; ++m) {
+      const double km = S.cd[m].w;
+      lt += km < key;
+      eq += km == key;
+    }
+    tie |= eq > 1;
+    if (eq == 1) S.order[lt] = (uint8_t)c;
+  }
+  if (__ballot(tie) == 0ull) {
+    wave_sync();
+    return;
+  }
   for (int c = __lane_id(); c < nc; c += 64) {
     const double key = S.cd[c].w;
     const int id = S.cjk[c];

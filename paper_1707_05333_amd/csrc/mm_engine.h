@@ -17,6 +17,9 @@ namespace mm {
 // internal cell (faces at kFacesPerCell unique faces per cell included) and
 // per slot of a caller-order pool.
 constexpr int64_t kFacesPerCell = 12;
+// Sliced-ELL list entries reserved per cell (a slice is as wide as its
+// longest list: about 20 for jittered lattices, 30 for Poisson points).
+constexpr int64_t kListPerCell = 40;
 int64_t engine_bytes_per_cell(int precision);
 
 // Bucket grid of a segment of n points in box p.box whose buckets start at
@@ -29,7 +32,7 @@ bool params_ok(const mm_params* p, std::string& why);
 
 struct Engine {
   int precision = MM_FP64;
-  int64_t ncap = 0, slot_cap = 0, fcap = 0, nbcap = 0;
+  int64_t ncap = 0, slot_cap = 0, fcap = 0, nbcap = 0, sell_cap = 0;
   int segcap = 0;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -37,13 +40,14 @@ struct Engine {
   int32_t *key = nullptr, *perm = nullptr, *sseg = nullptr, *deferred = nullptr;
   double *spos = nullptr, *geo = nullptr, *rmax2 = nullptr, *minv = nullptr;
   unsigned long long *bcount = nullptr, *boff = nullptr, *scan_tmp = nullptr, *counts = nullptr, *off = nullptr;
+  unsigned long long *sw = nullptr, *soff = nullptr;   // slice widths and offsets of the per-cell lists
   StageNbr* stage_nb = nullptr;
   StageGeo* stage_geo = nullptr;
   Face* faces = nullptr;
   int32_t* csr = nullptr;
   NbrEntry* nbr = nullptr;
   // State in internal order.
-  void *U = nullptr, *G = nullptr, *Uh = nullptr, *Gh = nullptr, *phi = nullptr;
+  void *U = nullptr, *G = nullptr, *Uh = nullptr, *rec = nullptr, *phi = nullptr;   // rec: FluxCell<R>[n]
   double *w = nullptr, *Qs = nullptr;
   // Segment table and status.
   SegDesc* segs = nullptr;

@@ -24,8 +24,10 @@ int64_t engine_bytes_per_cell(int precision) {
                            + 8 * (3 + 4 + 1 + 6 + 1 + 1)               // spos, geo, rmax2, minv, counts, off
                            + 16                                        // bucket count and offset
                            + (int64_t)kMaxFaces * (sizeof(StageNbr) + sizeof(StageGeo))
-                           + r * (5 + 15 + 5 + 15) + 8 * (3 + 5);      // U, G, Uh, Gh, w, Qs
-  const int64_t per_face = sizeof(Face) + 2 * (4 + sizeof(NbrEntry)) + 5 * r;   // face, CSR, nbr, phi
+                           + kListPerCell * (4 + sizeof(NbrEntry))     // per-cell lists
+                           + r * (5 + 15 + 5) + 8 * (3 + 5)            // U, G, Uh, w, Qs
+                           + (r == 4 ? sizeof(FluxCell<float>) : sizeof(FluxCell<double>));
+  const int64_t per_face = sizeof(Face) + 5 * r;                       // face, phi
   return per_cell + kFacesPerCell * per_face;
 }
 
@@ -107,6 +109,7 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
   fcap = std::min<int64_t>(f_cap, 0x7fffffffll);
   segcap = seg_cap;
   nbcap = ncap + 8ll * segcap;
+  sell_cap = kListPerCell * ((ncap + 63) / 64) * 64;   // whole slices of 64 cells
   stream = s;
   if (hipGetDevice(&device) != hipSuccess) return fail(MM_EHIP, "hipGetDevice failed");
   const int64_t N = ncap, F = fcap;
@@ -125,15 +128,18 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
   ok &= dalloc(&scan_tmp, scan_tmp_elems(std::max(N, nbcap))) == hipSuccess;
   ok &= dalloc(&counts, N) == hipSuccess;
   ok &= dalloc(&off, N + 1) == hipSuccess;
+  ok &= dalloc(&sw, (N + 63) / 64 + 1) == hipSuccess;
+  ok &= dalloc(&soff, (N + 63) / 64 + 2) == hipSuccess;
   ok &= dalloc(&stage_nb, (size_t)N * kMaxFaces) == hipSuccess;
   ok &= dalloc(&stage_geo, (size_t)N * kMaxFaces) == hipSuccess;
   ok &= dalloc(&faces, F) == hipSuccess;
-  ok &= dalloc(&csr, 2 * F) == hipSuccess;
-  ok &= dalloc(&nbr, 2 * F) == hipSuccess;
+  ok &= dalloc(&csr, sell_cap) == hipSuccess;
+  ok &= dalloc(&nbr, sell_cap) == hipSuccess;
   ok &= hipMalloc(&U, std::max<size_t>(5 * N * rs, 1)) == hipSuccess;
   ok &= hipMalloc(&G, std::max<size_t>(15 * N * rs, 1)) == hipSuccess;
   ok &= hipMalloc(&Uh, std::max<size_t>(5 * N * rs, 1)) == hipSuccess;
-  ok &= hipMalloc(&Gh, std::max<size_t>(15 * N * rs, 1)) == hipSuccess;
+  ok &= hipMalloc(&rec, std::max<size_t>(N * (precision == MM_MIXED ? sizeof(FluxCell<float>)
+                                                                       : sizeof(FluxCell<double>)), 1)) == hipSuccess;
   ok &= hipMalloc(&phi, std::max<size_t>(5 * F * rs, 1)) == hipSuccess;
   ok &= dalloc(&w, 3 * N) == hipSuccess;
   ok &= dalloc(&Qs, 5 * N) == hipSuccess;
@@ -157,8 +163,8 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
 }
 
 void Engine::release() {
-  void* ptrs[] = {key, perm, sseg, deferred, spos, geo, rmax2, minv, bcount, boff, scan_tmp, counts, off,
-                  stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, Gh, phi, w, Qs, segs, segst, st};
+  void* ptrs[] = {key, perm, sseg, deferred, spos, geo, rmax2, minv, bcount, boff, scan_tmp, counts, off, sw, soff,
+                  stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, segs, segst, st};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   void* hptrs[] = {segs_host, segst_host, st_host};
@@ -199,8 +205,8 @@ void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int3
                     stream);
   mark(2);
   scan_u64(counts, off, n_cells, scan_tmp, stream);
-  launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, fcap, faces, csr, nbr, minv, st,
-                    segst, stream);
+  launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, sw, soff, scan_tmp, fcap,
+                    sell_cap, faces, csr, nbr, minv, st, segst, stream);
 }
 
 namespace {
@@ -208,19 +214,20 @@ namespace {
 template <typename R>
 void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n, bool any_fresh) {
   const unsigned long long* nf_dev = &E.st->n_faces;
-  R *U = (R*)E.U, *Uh = (R*)E.Uh, *Gh = (R*)E.Gh, *phi = (R*)E.phi;
+  R *U = (R*)E.U, *Uh = (R*)E.Uh, *phi = (R*)E.phi;
+  FluxCell<R>* rec = (FluxCell<R>*)E.rec;
   if (any_fresh) launch_init_charges(E.segs, E.sseg, n, Q, E.perm, E.geo, Q, 1, E.stream);
   launch_cell_state<R>(E.segs, E.sseg, n, Q, E.perm, E.geo, E.Qs, U, E.w, E.st, E.segst, E.stream);
   E.mark(4);
-  launch_gradient<R>(E.segs, E.sseg, n, U, E.off, E.nbr, E.minv, kLimitMaskBit0, nullptr, E.w,
-                     E.segst, 0.0, Uh, E.segst, E.stream);
+  launch_gradient<R>(E.segs, E.sseg, n, U, E.counts, E.soff, E.nbr, E.minv, kLimitMaskBit0, nullptr, E.w, E.segst,
+                     0.0, Uh, nullptr, nullptr, nullptr, E.segst, E.stream);
   E.mark(5);
-  launch_gradient<R>(E.segs, E.sseg, n, Uh, E.off, E.nbr, E.minv, kLimitMaskBit1, Gh,
-                     nullptr, nullptr, 0.0, nullptr, E.segst, E.stream);
+  launch_gradient<R>(E.segs, E.sseg, n, Uh, E.counts, E.soff, E.nbr, E.minv, kLimitMaskBit1, nullptr, E.w, nullptr,
+                     0.0, nullptr, rec, E.geo, E.spos, E.segst, E.stream);
   E.mark(6);
-  launch_flux<R>(E.segs, E.fcap, nf_dev, E.faces, E.spos, E.geo, Uh, Gh, E.w, E.segst, 0.0, phi, E.segst, E.stream);
+  launch_flux<R>(E.segs, E.fcap, nf_dev, E.faces, rec, E.segst, 0.0, phi, E.segst, E.stream);
   E.mark(7);
-  launch_update<R>(E.segs, E.sseg, n, E.off, E.csr, phi, E.geo, E.perm, E.Qs, Q, E.spos, E.w, pos, w_slots, E.segst,
+  launch_update<R>(E.segs, E.sseg, n, E.counts, E.soff, E.csr, phi, E.geo, E.perm, E.Qs, Q, E.spos, E.w, pos, w_slots, E.segst,
                    E.st, E.segst, E.stream);
 }
 

@@ -109,6 +109,19 @@ struct Face {
   double f[3];      // area centroid minus r_i
 };
 
+// Everything the face kernel reads of one cell, in one aligned record so a
+// gather of a neighbour touches two or three cache lines: the half-step
+// state and its gradient (precision type), the mesh velocity, the centroid
+// minus the generator, and the generator.
+template <typename R>
+struct __align__(16) FluxCell {
+  R U[5];
+  R G[15];
+  double w[3];
+  double c[3];
+  double r[3];
+};
+
 // Per-cell neighbour entry used by the gradient kernel: neighbour index,
 // centroid displacement d = c_j + s - c_i and LSQ weight A / |d|^2.
 struct NbrEntry {
@@ -186,11 +199,20 @@ void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const
                        unsigned long long* counts, double* geo, double* rmax2, int32_t* deferred, DevStatus* st_dev,
                        SegStatus* segst, hipStream_t st);
 
-// Faces, CSR, neighbour entries and inverse LSQ matrices from the staged lists.
+// Per-cell lists (face ids with sign, neighbour entries) use a sliced ELL
+// layout: slices of 64 consecutive internal cells, each as wide as its
+// longest list; entry e of cell s sits at soff[s / 64] + 64 e + s % 64.
+inline __host__ __device__ int64_t sell_slot(const unsigned long long* soff, int64_t s, int e) {
+  return (int64_t)soff[s >> 6] + 64ll * e + (s & 63);
+}
+
+// Unique faces, per-cell lists (slice offsets soff, from the slice widths sw),
+// neighbour entries and inverse LSQ matrices from the staged lists.
 void launch_build_mesh(const double* spos, const double* geo, int64_t n, const SegDesc* segs, const int32_t* sseg,
                        const StageNbr* stage_nb, const StageGeo* stage_geo, const unsigned long long* counts,
-                       const unsigned long long* off, int64_t face_cap, Face* faces, int32_t* csr, NbrEntry* nbr,
-                       double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
+                       const unsigned long long* off, unsigned long long* sw, unsigned long long* soff,
+                       unsigned long long* scan_tmp, int64_t face_cap, int64_t sell_cap, Face* faces, int32_t* csr,
+                       NbrEntry* nbr, double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
 // Hydro kernels, instantiated for double (MM_FP64) and float (MM_MIXED).
 // Slot-space arrays (Q, pos, w, prim) are indexed through perm.  dt_src
@@ -202,11 +224,18 @@ void launch_cell_state(const SegDesc* segs, const int32_t* sseg, int64_t n, cons
 // Limiter selection of the gradient kernel: off, on, or the segment's own
 // limit_mask bit 0 (first gradient) / bit 1 (second gradient).
 enum : int { kLimitOff = 0, kLimitOn = 1, kLimitMaskBit0 = 2, kLimitMaskBit1 = 3 };
+// Gradients of U (to G when set); with U_half set, the half-step predictor
+// (needs w); with rec set, the face kernel's cell records (needs w, geo and
+// spos).
 template <typename R>
 void launch_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U,
-                     const unsigned long long* csr_off, const NbrEntry* nbr, const double* minv, int limit, R* G,
-                     const double* w, const SegStatus* dt_src, double dt_fixed, R* U_half, SegStatus* segst,
+                     const unsigned long long* counts, const unsigned long long* soff, const NbrEntry* nbr,
+                     const double* minv, int limit, R* G, const double* w, const SegStatus* dt_src, double dt_fixed,
+                     R* U_half, FluxCell<R>* rec, const double* geo, const double* spos, SegStatus* segst,
                      hipStream_t st);
+template <typename R>
+void launch_pack_flux_cells(int64_t n, const R* U, const R* G, const double* w, const double* geo,
+                            const double* spos, FluxCell<R>* rec, hipStream_t st);
 template <typename R>
 void launch_predict(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U, const R* G, const double* w,
                     const SegStatus* dt_src, double dt_fixed, R* U_half, SegStatus* segst, hipStream_t st);
@@ -214,15 +243,16 @@ void launch_predict(const SegDesc* segs, const int32_t* sseg, int64_t n, const R
 // bounds the launch.
 template <typename R>
 void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
-                 const double* spos, const double* geo, const R* Uh, const R* Gh, const double* w,
-                 const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst, hipStream_t st);
+                 const FluxCell<R>* rec, const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst,
+                 hipStream_t st);
 template <typename R>
-void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* csr_off,
-                   const int32_t* csr, const R* phi, const double* geo, const int32_t* perm, const double* Qs,
+void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* counts,
+                   const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo, const int32_t* perm, const double* Qs,
                    double* Q_slots, const double* spos, const double* w, double* pos_slots, double* w_slots,
                    const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 template <typename R>
-void launch_accumulate(int64_t n, const unsigned long long* csr_off, const int32_t* csr, const R* phi,
+void launch_accumulate(int64_t n, const unsigned long long* counts, const unsigned long long* soff, const int32_t* csr,
+                       const R* phi,
                        const int32_t* perm, double* dQ_slots, hipStream_t st);
 
 // Layout conversions between slot order and internal order.

@@ -263,13 +263,13 @@ mm_status mm_gradients(mm_ctx* c, const void* U, void* grad, int32_t limit) {
   const int lim = limit ? kLimitOn : kLimitOff;
   if (c->p.precision == MM_MIXED) {
     launch_gather_rows<float>((const float*)U, E.perm, n, 5, (float*)E.U, E.stream);
-    launch_gradient<float>(E.segs, E.sseg, n, (const float*)E.U, E.off, E.nbr, E.minv, lim, (float*)E.G, nullptr,
-                           nullptr, 0.0, nullptr, E.segst, E.stream);
+    launch_gradient<float>(E.segs, E.sseg, n, (const float*)E.U, E.counts, E.soff, E.nbr, E.minv, lim, (float*)E.G, nullptr,
+                           nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, E.segst, E.stream);
     launch_scatter_rows<float>((const float*)E.G, E.perm, n, 15, (float*)grad, E.stream);
   } else {
     launch_gather_rows<double>((const double*)U, E.perm, n, 5, (double*)E.U, E.stream);
-    launch_gradient<double>(E.segs, E.sseg, n, (const double*)E.U, E.off, E.nbr, E.minv, lim, (double*)E.G,
-                            nullptr, nullptr, 0.0, nullptr, E.segst, E.stream);
+    launch_gradient<double>(E.segs, E.sseg, n, (const double*)E.U, E.counts, E.soff, E.nbr, E.minv, lim, (double*)E.G,
+                            nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, E.segst, E.stream);
     launch_scatter_rows<double>((const double*)E.G, E.perm, n, 15, (double*)grad, E.stream);
   }
   HIPCHECK(c, hipGetLastError());
@@ -311,16 +311,20 @@ mm_status mm_fluxes(mm_ctx* c, const void* U_half, const void* grad_half, const 
   launch_gather_rows<double>(w, E.perm, n, 3, E.w, E.stream);
   if (c->p.precision == MM_MIXED) {
     launch_gather_rows<float>((const float*)U_half, E.perm, n, 5, (float*)E.Uh, E.stream);
-    launch_gather_rows<float>((const float*)grad_half, E.perm, n, 15, (float*)E.Gh, E.stream);
-    launch_flux<float>(E.segs, E.n_faces, nullptr, E.faces, E.spos, E.geo, (const float*)E.Uh, (const float*)E.Gh,
-                       E.w, nullptr, dt, (float*)E.phi, E.segst, E.stream);
-    launch_accumulate<float>(n, E.off, E.csr, (const float*)E.phi, E.perm, dQ, E.stream);
+    launch_gather_rows<float>((const float*)grad_half, E.perm, n, 15, (float*)E.G, E.stream);
+    launch_pack_flux_cells<float>(n, (const float*)E.Uh, (const float*)E.G, E.w, E.geo, E.spos,
+                                  (FluxCell<float>*)E.rec, E.stream);
+    launch_flux<float>(E.segs, E.n_faces, nullptr, E.faces, (const FluxCell<float>*)E.rec, nullptr, dt,
+                       (float*)E.phi, E.segst, E.stream);
+    launch_accumulate<float>(n, E.counts, E.soff, E.csr, (const float*)E.phi, E.perm, dQ, E.stream);
   } else {
     launch_gather_rows<double>((const double*)U_half, E.perm, n, 5, (double*)E.Uh, E.stream);
-    launch_gather_rows<double>((const double*)grad_half, E.perm, n, 15, (double*)E.Gh, E.stream);
-    launch_flux<double>(E.segs, E.n_faces, nullptr, E.faces, E.spos, E.geo, (const double*)E.Uh,
-                        (const double*)E.Gh, E.w, nullptr, dt, (double*)E.phi, E.segst, E.stream);
-    launch_accumulate<double>(n, E.off, E.csr, (const double*)E.phi, E.perm, dQ, E.stream);
+    launch_gather_rows<double>((const double*)grad_half, E.perm, n, 15, (double*)E.G, E.stream);
+    launch_pack_flux_cells<double>(n, (const double*)E.Uh, (const double*)E.G, E.w, E.geo, E.spos,
+                                   (FluxCell<double>*)E.rec, E.stream);
+    launch_flux<double>(E.segs, E.n_faces, nullptr, E.faces, (const FluxCell<double>*)E.rec, nullptr, dt,
+                        (double*)E.phi, E.segst, E.stream);
+    launch_accumulate<double>(n, E.counts, E.soff, E.csr, (const double*)E.phi, E.perm, dQ, E.stream);
   }
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
