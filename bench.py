@@ -1,21 +1,35 @@
 """Benchmark of the moving-mesh step on one MI355X.
 
-Default workload: the FP64 Sod shock tube, a 256 x 64 x 64 jittered lattice
-(1,048,576 cells) in a periodic 4 x 1 x 1 box, gamma = 1.4, Lagrangian mesh,
-CFL 0.3.  One step is the whole path: sort, cell construction, mesh assembly,
-cell states and timestep, gradient + predictor, half-step gradient, face
-fluxes, update + drift.  Inputs are resident in HBM before the timed region.
+Main line (the JSON "value"): the plain FP64 Sod shock tube, a 256 x 64 x 64
+jittered lattice (1,048,576 cells) in a periodic 4 x 1 x 1 box, gamma = 1.4,
+Lagrangian mesh, CFL 0.3.  One step is the whole path: sort, cell
+construction, mesh assembly, cell states and timestep, gradient +
+predictor, half-step gradient, face fluxes, update + drift.  Inputs are
+resident in HBM before the timed region.
 
-Prints one JSON line (metric, value in cell-updates/s, roofline of the
-dominant kernel measured with HIP events inside the timed region, per-stage
-times, and the CPU oracle's rate on a bounded slab of the same workload).
+Also reported on the same line:
+  roofline     the dominant kernel (cell construction) against the FP64 ALU
+               peak, its duration from HIP events on the context stream over
+               the timed region, and the HBM traffic of the committed counter
+               summary when it was taken on the current kernel source;
+  flux_kernel  the face kernel against the HBM peak (algorithmic bytes);
+  mixed        the point blast (128^3, 100 steps) in mixed precision against
+               the FP64 path: cell-updates/s of both, relative L1 density
+               error, conservation drift;
+  serving      a Poisson stream of Kelvin-Helmholtz simulations (1e3..2e5
+               points each, 20 steps, mixed) through the batch serving loop
+               under an explicit device budget: throughput, p50/p99 step
+               latency, turnaround;
+  cpu_baseline the CPU oracle on a bounded sample of the Sod workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -26,10 +40,12 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
-# Algorithmic cost model ("Measurement"):
+# Algorithmic cost model:
 TESS_FLOP_PER_CELL = 1.0e4          # FP64 flops to construct one cell
 FLUX_FACE_BYTES = {"fp64": 48 + 40, "mixed": 48 + 20}      # face record + stored flux
 FLUX_CELL_BYTES = {"fp64": 232, "mixed": 152}              # U_half, grad_half, c-r, w, r once per cell
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tess_pass1_sod_256x64x64_traffic.md")
+TESS_SOURCE = os.path.join(ROOT, "paper_1707_05333_amd", "csrc", "k_tessellate.hip")
 
 
 def parse():
@@ -40,11 +56,20 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--workload", choices=["sod", "blast"], default="sod")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-depth", type=int, default=64,
-                    help="z layers of the lattice in the oracle's timing slab")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision blast object")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving object")
+    ap.add_argument("--mixed-steps", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-budget-gib", type=float, default=8.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum CPU time of the oracle sample (whole steps)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB device copy (for counter calibration under rocprofv3)")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def make_workload(name):
@@ -55,31 +80,151 @@ def make_workload(name):
 
 
 def cpu_baseline(args):
-    """The oracle, as it is, on a slab of the workload: same spacing and
-    states, fewer z layers (periodic), one step."""
+    """The oracle, as it is, on the workload itself: whole steps until at
+    least --cpu-seconds of wall time."""
     import oracle
     import workloads as W
-    if args.workload == "sod":
-        depth = args.cpu_sample_depth
-        wl = W.c2_sod(shape=(256, 64, depth), box=(4.0, 1.0, depth / 64.0))
-        sample = f"one oracle step of the Sod tube slab 256x64x{depth} (box 4 x 1 x {depth / 64:g})"
-    else:
-        depth = args.cpu_sample_depth
-        wl = W.c3_point_blast(n_side=64)
-        sample = "one oracle step of the blast at 64^3"
+    wl = W.c2_sod() if args.workload == "sod" else W.c3_point_blast(n_side=64)
     p = oracle.make_params(wl.box, **wl.params)
     m = oracle.tessellate(wl.pos, wl.box)
     Q = oracle.init_charges(m, p, wl.prim)
     m.free()
-    t0 = time.perf_counter()
-    oracle.step(wl.pos, Q, p)
+    pos = wl.pos
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        pos, Q, *_ = oracle.step(pos, Q, p)
+        steps += 1
+        if time.perf_counter() - t0 >= args.cpu_seconds or steps >= 20:
+            break
     dt = time.perf_counter() - t0
-    return {"value": wl.n / dt, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": sample, "seconds": dt}
+    what = "Sod tube 256x64x64 (1,048,576 cells)" if args.workload == "sod" else "blast 64^3"
+    return {"value": wl.n * steps / dt, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} whole oracle steps of the {what}", "seconds": dt}
 
 
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+def tess_traffic(n_launch_cells):
+    """HBM bytes per launch of the cell-construction kernel from the committed
+    counter summary, or None when it was taken on another kernel source."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"source_sha1:\s*([0-9a-f]{40})", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    c = re.search(r"cells_per_launch:\s*([0-9]+)", text)
+    if not (m and b and c):
+        return None
+    sha = hashlib.sha1(open(TESS_SOURCE, "rb").read()).hexdigest()
+    if sha != m.group(1) or int(c.group(1)) != n_launch_cells:
+        return None
+    return float(b.group(1))
+
+
+def run_single(M, torch, wl, precision, steps, warmup, timing=True):
+    """Steps one simulation through the one-simulation context.  Returns
+    (elapsed seconds, per-stage ms, faces per step, state tensors)."""
+    params = M.make_params(box=wl.box, precision=precision, **wl.params)
+    mm = M.MovingMesh(wl.n, params)
+    pos = torch.from_numpy(wl.pos.copy()).cuda()
+    prim = torch.from_numpy(wl.prim.copy()).cuda()
+    mm.tessellate(pos)
+    Q = mm.init_charges(prim)
+    if wl.energy_cells is not None:
+        Q[torch.from_numpy(wl.energy_cells).cuda(), 4] += wl.energy_amount
+    w = torch.empty_like(pos)
+    for _ in range(warmup):
+        mm.step(pos, w, Q)
+    mm.set_stage_timing(timing)
+    stage_tot, faces_tot = {k: 0.0 for k in M.STAGE_NAMES}, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        info = mm.step(pos, w, Q)
+        if timing:
+            for k, v in mm.stage_ms().items():
+                stage_tot[k] += v
+        faces_tot += info["n_faces"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    mm.set_stage_timing(False)
+    stage_ms = {k: v / max(steps, 1) for k, v in stage_tot.items()}
+    return elapsed, stage_ms, faces_tot / max(steps, 1), (mm, pos, Q, w)
+
+
+def mixed_object(M, torch, args):
+    """Point blast 128^3, 100 steps: mixed precision against FP64."""
+    import workloads as W
+    wl = W.c3_point_blast()
+    res = {}
+    for prec in ("fp64", "mixed"):
+        log(f"blast 128^3 {prec}, {args.mixed_steps} steps")
+        elapsed, _, _, (mm, pos, Q, w) = run_single(M, torch, wl, prec, args.mixed_steps, 0, timing=False)
+        mm.tessellate(pos)
+        V = mm.mesh_export().V
+        res[prec] = dict(rate=wl.n * args.mixed_steps / elapsed, rho=Q[:, 0] / V, V=V, Q=Q.clone())
+        mm.close()
+    # Totals at the start (the same charges for both paths).
+    _, _, _, (mm0, _, Q0, _) = run_single(M, torch, wl, "fp64", 0, 0, timing=False)
+    tot0 = Q0.sum(dim=0)
+    mm0.close()
+    r64, r32, V = res["fp64"]["rho"], res["mixed"]["rho"], res["fp64"]["V"]
+    l1 = float((r32 - r64).abs().sum() / r64.abs().sum())
+    l1v = float(((r32 - r64).abs() * V).sum() / (r64.abs() * V).sum())
+
+    def drift(Q):
+        t = Q.sum(dim=0)
+        pabs = Q[:, 1:4].norm(dim=1).sum()
+        return {"mass": float((t[0] - tot0[0]).abs() / tot0[0].abs()),
+                "momentum": float((t[1:4] - tot0[1:4]).norm() / pabs),
+                "energy": float((t[4] - tot0[4]).abs() / tot0[4].abs())}
+
+    return {"workload": "blast_128^3", "cells": wl.n, "steps": args.mixed_steps,
+            "value": res["mixed"]["rate"], "fp64_value": res["fp64"]["rate"], "unit": "cell-updates/s",
+            "speedup_vs_fp64": res["mixed"]["rate"] / res["fp64"]["rate"],
+            "l1_rho_rel_vs_fp64": l1, "l1_rho_rel_volume_weighted": l1v,
+            "drift_mixed": drift(res["mixed"]["Q"]), "drift_fp64": drift(res["fp64"]["Q"]),
+            "reference": "the FP64 GPU path, which matches the FP64 oracle to 1e-10 in the parity tests"}
+
+
+def serving_object(M, torch, args):
+    """A Poisson stream of Kelvin-Helmholtz runs through the serving loop."""
+    import numpy as np
+    import workloads as W
+    nreq = args.serve_requests
+    log(f"serving: generating {nreq} Kelvin-Helmholtz requests")
+    wls = [W.c4_kelvin_helmholtz(k) for k in range(nreq)]
+    prec = "mixed"
+    budget = int(args.serve_budget_gib * (1 << 30))
+
+    def requests(arrivals):
+        reqs = []
+        for t, wl in zip(arrivals, wls):
+            reqs.append(dict(arrival=float(t), params=M.make_params(box=wl.box, precision=prec, **wl.params),
+                             pos=torch.from_numpy(wl.pos).cuda(), prim=torch.from_numpy(wl.prim).cuda(),
+                             steps=wl.steps))
+        return reqs
+
+    # Calibration: the first 32 requests at once give the sustained rate;
+    # arrivals then come at 0.8 of that rate divided by the mean request cost.
+    B = M.Batch(budget, max_sims=1024, precision=prec)
+    cal = requests([0.0] * 32)[:32]
+    _, st = B.serve(cal)
+    cost = float(np.mean([wl.n * wl.steps for wl in wls]))
+    rate = 0.8 * st["cell_updates_per_s"] / cost
+    arrivals = W.poisson_arrivals(nreq, rate, seed=4)
+    log(f"serving: calibration {st['cell_updates_per_s']:.3e} cell-updates/s, arrival rate {rate:.1f}/s")
+    reqs = requests(arrivals)
+    res, stats = B.serve(reqs)
+    ok = sum(1 for r in res if r["status"] == 0)
+    B.close()
+    return {"workload": f"kelvin_helmholtz_stream_{nreq}", "requests": nreq, "completed_ok": ok,
+            "cells_total": int(sum(wl.n for wl in wls)), "steps_per_request": 20, "precision": prec,
+            "hbm_budget_bytes": budget, "arrival_rate_per_s": rate,
+            "value": stats["cell_updates_per_s"], "unit": "cell-updates/s",
+            "step_latency_p50_ms": stats["step_p50"], "step_latency_p99_ms": stats["step_p99"],
+            "step_latency_mean_ms": stats["step_mean"],
+            "turnaround_p50_s": stats["turnaround_p50"], "turnaround_p99_s": stats["turnaround_p99"],
+            "batch_steps": stats["batch_steps"], "max_resident": stats["max_resident"], "wall_s": stats["wall"]}
 
 
 def main():
@@ -87,7 +232,6 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_1707_05333_amd as M
@@ -96,52 +240,26 @@ def main():
     wl = make_workload(args.workload)
     n = wl.n
     log(f"workload {args.workload} n={n} precision={args.precision}")
-    params = M.make_params(box=wl.box, precision=args.precision, **wl.params)
-    mm = M.MovingMesh(n, params)
-    pos = torch.from_numpy(wl.pos.copy()).cuda()
-    prim = torch.from_numpy(wl.prim.copy()).cuda()
-    mm.tessellate(pos)
-    Q = mm.init_charges(prim)
-    if wl.energy_cells is not None:
-        idx = torch.from_numpy(wl.energy_cells).cuda()
-        Q[idx, 4] += wl.energy_amount
-    w = torch.empty_like(pos)
-    log("tessellated and charged")
-    for _ in range(args.warmup):
-        mm.step(pos, w, Q)
-    log(f"warmup done ({args.warmup} steps)")
-
-    mm.set_stage_timing(True)
-    stage_tot = {k: 0.0 for k in M.STAGE_NAMES}
-    faces_tot = 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        info = mm.step(pos, w, Q)
-        for k, v in mm.stage_ms().items():
-            stage_tot[k] += v
-        faces_tot += info["n_faces"]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    mm.set_stage_timing(False)
+    elapsed, stage_ms, faces, (mm, *_rest) = run_single(M, torch, wl, args.precision, args.steps, args.warmup)
+    mm.close()
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
     ms_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
-    stage_ms = {k: v / args.steps for k, v in stage_tot.items()}
-    faces = faces_tot / args.steps
 
     if args.copy_calibration:
         a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
 
-    # Dominant kernel: cell construction (FP64 ALU, latency bound).
+    # Dominant kernel: cell construction (FP64 ALU bound).
     t_cells = stage_ms["cells"] * 1e-3
     ach = TESS_FLOP_PER_CELL * n / t_cells / 1e12
     roofline = {"bound": "alu", "kernel": "k_tess_pass1 + k_tess_pass2", "achieved": ach,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
-                "algorithmic_flop_per_cell": TESS_FLOP_PER_CELL}
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
+                "traffic": tess_traffic(n) if args.workload == "sod" else None,
+                "algorithmic_flop_per_cell": TESS_FLOP_PER_CELL, "launch_ms": stage_ms["cells"]}
     t_flux = stage_ms["flux"] * 1e-3
     flux_bytes = faces * FLUX_FACE_BYTES[args.precision] + n * FLUX_CELL_BYTES[args.precision]
     flux_gbs = flux_bytes / t_flux / 1e9 if t_flux > 0 else float("nan")
@@ -166,8 +284,17 @@ def main():
         "roofline": roofline,
         "stage_ms": stage_ms,
         "flux_kernel": {"bound": "hbm", "achieved": flux_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": flux_gbs / PEAK_HBM_GBS, "algorithmic_bytes": flux_bytes},
+                        "frac": flux_gbs / PEAK_HBM_GBS, "algorithmic_bytes": flux_bytes,
+                        "launch_ms": stage_ms["flux"]},
     }
+    if not args.no_mixed:
+        out["mixed"] = mixed_object(M, torch, args)
+        log(f"mixed: {out['mixed']['value']:.3e} vs fp64 {out['mixed']['fp64_value']:.3e}, "
+            f"L1 {out['mixed']['l1_rho_rel_vs_fp64']:.2e}")
+    if not args.no_serve:
+        out["serving"] = serving_object(M, torch, args)
+        log(f"serving: {out['serving']['value']:.3e} cell-updates/s, p50 {out['serving']['step_latency_p50_ms']:.2f} ms"
+            f" p99 {out['serving']['step_latency_p99_ms']:.2f} ms")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args)
