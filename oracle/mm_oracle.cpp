@@ -12,7 +12,7 @@
 // function names the passage of the paper it follows.  Where the paper is
 // silent or garbled, the reading taken is stated where it is used:
 //   R-upd   update sign: F is the flux from i to j along the face normal;
-//           Q_i loses dt*A*F, Q_j gains it (Sec. 4, eq. "time evolution").
+//           Q_i loses dt*A*F, Q_j gains it (Sec. 4, update of the charges).
 //   R-s10   S10 limiter displacement is c_j - c_i (+ periodic shift); the
 //           extrema include cell i itself (Sec. 4.1, limiter definition).
 //   R-dm    the Duffell-MacFadyen factor reads max[theta dU/Delta, 0]
@@ -33,7 +33,7 @@
 //           keep density and velocity and raise the pressure (Sec. 4.1,
 //           floors paragraph; values are not given by the paper).
 //   R-box   the starting cell is the box r_i +- L/2, the exact Voronoi cell
-//           of i's own periodic images (Sec. 3, "large rectangular cell").
+//           of i's own periodic images (Sec. 3, the large box each cell is cut from).
 //   R-area  a face is kept iff its computed area is positive.  (A threshold
 //           relative to each cell's own volume would differ between the two
 //           cells of a face and keep a face on one side only.)
@@ -772,8 +772,8 @@ double dm_factor(double theta, double dU, double D) {
 inline bool owns(int i, int j, int code) { return i < j || (i == j && code > 13); }
 
 // Face geometry and the two reconstructed states of the face (i, e) of cell
-// i, seen from i (Sec. 4 item 1; Sec. 4.1 eq. "state vector face" and the
-// limiter of Duffell & MacFadyen, R-dm).  Returns the number of face floors.
+// i, seen from i (Sec. 4 item 1; Sec. 4.1 reconstruction of the state at
+// the face and the limiter of Duffell & MacFadyen, R-dm).  Returns the number of face floors.
 struct FaceSetup {
   double UL[5], UR[5];
   double n[3];   // unit normal from i toward the neighbour image
@@ -816,8 +816,8 @@ int setup_face(const Mesh& M, const Params& p, int64_t i, size_t e, const double
   return hits;
 }
 
-// Fluxes of all faces and their accumulation into dQ (Sec. 4, eq. "time
-// evolution" and items 1-5).  Each face's flux is computed once, by the cell
+// Fluxes of all faces and their accumulation into dQ (Sec. 4, update of the
+// charges and items 1-5).  Each face's flux is computed once, by the cell
 // with the lower index, with that cell's face geometry; R-upd fixes the
 // signs.
 int fluxes(const Mesh& M, const Params& p, const double* Uh, const double* Gh, const double* w, double dt,

@@ -2,7 +2,7 @@
 // prefix-sum and fill kernels the rest of the path uses.
 //
 // The sort realises the neighbour search the paper leaves to a tree
-// (Sec. 3: "rapid nearest-neighbor search"): points are binned into a
+// (Sec. 3, the fast nearest-neighbour search): points are binned into a
 // periodic grid of buckets, bucket-major with x fastest, so that the
 // candidate stencil of a cell reads contiguous runs of positions.  Inside a
 // bucket points keep their caller order, which makes the internal order, and

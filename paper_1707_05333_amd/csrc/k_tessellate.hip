@@ -169,7 +169,7 @@ struct CellRegs {
 };
 
 // Starting cell: the box r +- L/2, bounded by the bisectors of the
-// generator's six axis images (the "large rectangular cell" of Sec. 3).
+// generator's six axis images (the large box each cell is cut from, Sec. 3).
 __device__ void init_box(TessLds& S, const GridParams& g, CellRegs& C) {
   const int lane = __lane_id();
   if (lane < 6) {
