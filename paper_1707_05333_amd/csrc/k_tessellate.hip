@@ -37,16 +37,26 @@ namespace {
 #endif
 constexpr int kWaves = MM_TESS_WAVES;   // cells (wavefronts) per workgroup
 
+// 10.8 KB per wavefront, so 15 cells fit the 160 KB of LDS of a CU.  The
+// candidate list is only needed while cutting and the vertex copies only in
+// the epilogue (while cutting, vertices live in registers and move between
+// lanes by permutes), so the two share storage.
 struct __align__(16) TessLds {
   double4 pl[kPlanes];                 // plane: d.x, d.y, d.z, h
-  double vx[kVerts], vy[kVerts], vz[kVerts];
-  double4 cd[kCands];                  // candidate image: d, |d|^2
+  union {
+    struct {
+      double4 cd[kCands];              // candidate image: d, |d|^2
+      int32_t cjk[kCands];             // candidate: j << 5 | image code
+      uint8_t order[kCands];
+    };
+    struct {
+      double vx[kVerts], vy[kVerts], vz[kVerts];
+      int32_t first[kPlanes];
+    };
+  };
   uint32_t tri[kVerts];                // a | b << 8 | c << 16
   int32_t pcand[kPlanes];              // neighbour of each plane slot (j << 5 | image code); -1 - k for box plane k
-  int32_t cjk[kCands];                 // candidate: j << 5 | image code
-  int32_t first[kPlanes];
   uint8_t E[kPlanes * kPlanes];
-  uint8_t order[kCands];
   uint8_t freelist[kVerts];
   uint16_t elist[kVerts];              // boundary edges of one cut: x | y << 8
 };
@@ -180,15 +190,18 @@ __device__ void init_box(TessLds& S, const GridParams& g, CellRegs& C) {
     S.pl[lane] = make_double4(d[0], d[1], d[2], 0.5 * (g.L[ax] * g.L[ax]));
     S.pcand[lane] = -1 - lane;
   }
+  C.t0 = C.t1 = 0u;
+  C.v0x = C.v0y = C.v0z = C.v1x = C.v1y = C.v1z = 0.0;
   if (lane < 8) {
     const int sx = (lane & 1) ? -1 : 1, sy = (lane & 2) ? -1 : 1, sz = (lane & 4) ? -1 : 1;
     const int px = sx > 0 ? 0 : 1, py = sy > 0 ? 2 : 3, pz = sz > 0 ? 4 : 5;
     int a1 = py, a2 = pz;
     if (sx * sy * sz < 0) { a1 = pz; a2 = py; }   // orientation: det(d_a, d_b, d_c) > 0
-    S.tri[lane] = (uint32_t)(px | (a1 << 8) | (a2 << 16));
-    S.vx[lane] = sx * (0.5 * g.L[0]);
-    S.vy[lane] = sy * (0.5 * g.L[1]);
-    S.vz[lane] = sz * (0.5 * g.L[2]);
+    C.t0 = (uint32_t)(px | (a1 << 8) | (a2 << 16));
+    S.tri[lane] = C.t0;
+    C.v0x = sx * (0.5 * g.L[0]);
+    C.v0y = sy * (0.5 * g.L[1]);
+    C.v0z = sz * (0.5 * g.L[2]);
     S.E[px * kPlanes + a1] = (uint8_t)lane;
     S.E[a1 * kPlanes + a2] = (uint8_t)lane;
     S.E[a2 * kPlanes + px] = (uint8_t)lane;
@@ -197,10 +210,6 @@ __device__ void init_box(TessLds& S, const GridParams& g, CellRegs& C) {
   C.L0 = 0xffull;
   C.L1 = 0ull;
   C.np = 6;
-  C.t0 = S.tri[lane];
-  C.t1 = S.tri[lane + 64];
-  C.v0x = S.vx[lane]; C.v0y = S.vy[lane]; C.v0z = S.vz[lane];
-  C.v1x = S.vx[lane + 64]; C.v1y = S.vy[lane + 64]; C.v1z = S.vz[lane + 64];
   C.rmax2 = wave_max_bound(lane < 8 ? C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z : 0.0);
 }
 
@@ -214,58 +223,90 @@ __device__ int ring_for(const GridParams& g, const double edge[3], double r2) {
   return ring;
 }
 
+// One stencil bucket of a lane: its first point, its point count and the
+// periodic image (code and shift) under which its points are seen.
+struct StencilBucket {
+  int bst, cnt, code;
+  double sx, sy, sz;
+};
+
+__device__ inline StencilBucket stencil_bucket(const TessArgs& A, const GridParams& g, const int b[3], int ring,
+                                               int o, int W3) {
+  StencilBucket B{0, 0, 13, 0.0, 0.0, 0.0};
+  if (o < W3) {
+    const int W = 2 * ring + 1;
+    const int oo[3] = {o % W - ring, (o / W) % W - ring, o / (W * W) - ring};
+    int kk[3], bb[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int t = b[a] + oo[a];
+      kk[a] = t < 0 ? -1 : (t >= g.nb[a] ? 1 : 0);
+      bb[a] = t - kk[a] * g.nb[a];
+    }
+    const int64_t key = g.base + bb[0] + g.nb[0] * (bb[1] + g.nb[1] * bb[2]);
+    const unsigned long long b0 = A.boff[key];
+    B.bst = (int)b0;
+    B.cnt = (int)(A.boff[key + 1] - b0);
+    B.code = code_of(kk[0], kk[1], kk[2]);
+    B.sx = kk[0] * g.L[0];
+    B.sy = kk[1] * g.L[1];
+    B.sz = kk[2] * g.L[2];
+  }
+  return B;
+}
+
 // Gathers the neighbour images with lo2 <= |d|^2 < hi2 from the stencil of
 // half-width `ring` into LDS (at most kCands of them); returns their number.
-// Lanes take one bucket each and step through its points together.  The
+// Each lane takes two buckets of the stencil at a time and the wave steps
+// through their points together, so the loads of 128 buckets are in flight
+// at once (two memory round trips for the usual 125-bucket stencil).  The
 // generator's own images are not gathered: the box planes stand for them.
 __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const int s, const double r[3],
                       const int b[3], const int ring, const double lo2, const double hi2) {
   const int W = 2 * ring + 1, W3 = W * W * W;
+  const int lane = __lane_id();
   int nc = 0;
-  for (int chunk = 0; chunk < W3; chunk += 64) {
-    const int o = chunk + __lane_id();
-    int bst = 0, cnt = 0;
-    double sx = 0.0, sy = 0.0, sz = 0.0;
-    int code = 13;
-    if (o < W3) {
-      const int oo[3] = {o % W - ring, (o / W) % W - ring, o / (W * W) - ring};
-      int kk[3], bb[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const int t = b[a] + oo[a];
-        kk[a] = t < 0 ? -1 : (t >= g.nb[a] ? 1 : 0);
-        bb[a] = t - kk[a] * g.nb[a];
-      }
-      const int64_t key = g.base + bb[0] + g.nb[0] * (bb[1] + g.nb[1] * bb[2]);
-      const unsigned long long b0 = A.boff[key];
-      bst = (int)b0;
-      cnt = (int)(A.boff[key + 1] - b0);
-      code = code_of(kk[0], kk[1], kk[2]);
-      sx = kk[0] * g.L[0];
-      sy = kk[1] * g.L[1];
-      sz = kk[2] * g.L[2];
-    }
-    const int maxc = (int)wave_umax32((unsigned)cnt);
+  for (int chunk = 0; chunk < W3; chunk += 128) {
+    const StencilBucket B0 = stencil_bucket(A, g, b, ring, chunk + lane, W3);
+    const StencilBucket B1 = stencil_bucket(A, g, b, ring, chunk + 64 + lane, W3);
+    const int maxc = (int)wave_umax32((unsigned)max(B0.cnt, B1.cnt));
     for (int k = 0; k < maxc; ++k) {
-      bool keep = false;
-      double dx = 0, dy = 0, dz = 0, d2 = 0;
-      const int j = bst + k;
-      if (k < cnt && j != s) {
-        dx = (A.spos[3 * (int64_t)j] + sx) - r[0];
-        dy = (A.spos[3 * (int64_t)j + 1] + sy) - r[1];
-        dz = (A.spos[3 * (int64_t)j + 2] + sz) - r[2];
-        d2 = dx * dx + dy * dy + dz * dz;
-        keep = (d2 >= lo2) && (d2 < hi2);
+      const int j0 = B0.bst + k, j1 = B1.bst + k;
+      const bool v0 = k < B0.cnt && j0 != s, v1 = k < B1.cnt && j1 != s;
+      double x0 = 0, y0 = 0, z0 = 0, x1 = 0, y1 = 0, z1 = 0;
+      if (v0) {
+        x0 = A.spos[3 * (int64_t)j0];
+        y0 = A.spos[3 * (int64_t)j0 + 1];
+        z0 = A.spos[3 * (int64_t)j0 + 2];
       }
-      const unsigned long long mk = __ballot(keep);
-      if (keep) {
-        const int idx = nc + __popcll(mk & lanes_below());
+      if (v1) {
+        x1 = A.spos[3 * (int64_t)j1];
+        y1 = A.spos[3 * (int64_t)j1 + 1];
+        z1 = A.spos[3 * (int64_t)j1 + 2];
+      }
+      const double dx0 = (x0 + B0.sx) - r[0], dy0 = (y0 + B0.sy) - r[1], dz0 = (z0 + B0.sz) - r[2];
+      const double dx1 = (x1 + B1.sx) - r[0], dy1 = (y1 + B1.sy) - r[1], dz1 = (z1 + B1.sz) - r[2];
+      const double d20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
+      const double d21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
+      const bool keep0 = v0 && (d20 >= lo2) && (d20 < hi2);
+      const bool keep1 = v1 && (d21 >= lo2) && (d21 < hi2);
+      const unsigned long long mk0 = __ballot(keep0), mk1 = __ballot(keep1);
+      if (keep0) {
+        const int idx = nc + __popcll(mk0 & lanes_below());
         if (idx < kCands) {
-          S.cd[idx] = make_double4(dx, dy, dz, d2);
-          S.cjk[idx] = (j << 5) | code;
+          S.cd[idx] = make_double4(dx0, dy0, dz0, d20);
+          S.cjk[idx] = (j0 << 5) | B0.code;
         }
       }
-      nc += __popcll(mk);
+      const int n0 = __popcll(mk0);
+      if (keep1) {
+        const int idx = nc + n0 + __popcll(mk1 & lanes_below());
+        if (idx < kCands) {
+          S.cd[idx] = make_double4(dx1, dy1, dz1, d21);
+          S.cjk[idx] = (j1 << 5) | B1.code;
+        }
+      }
+      nc += n0 + __popcll(mk1);
     }
   }
   wave_sync();
@@ -382,35 +423,55 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     }
     wave_sync();   // every E lookup above is done before any write below
 
-    // One new vertex per lane: the fan of triangles (x, y, p) around the
-    // new face, in the free slots.
+    // One new vertex per boundary edge: the fan of triangles (x, y, p)
+    // around the new face, in the free slots.  Lane e computes edge e (and
+    // e + 64 when the cap has more boundary edges than lanes).
+    double ax = 0.0, ay = 0.0, az = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
     for (int base = 0; base < B; base += 64) {
       const int ee = base + lane;
+      double nx = 0.0, ny = 0.0, nz = 0.0;
       if (ee < B) {
         const int xy = S.elist[ee];
         const int x = xy & 255, y = xy >> 8;
         const int ns = S.freelist[ee];
         S.tri[ns] = (uint32_t)(x | (y << 8) | (p << 16));
-        double nx, ny, nz;
         intersect3(S.pl[x], S.pl[y], S.pl[p], nx, ny, nz);
-        S.vx[ns] = nx;
-        S.vy[ns] = ny;
-        S.vz[ns] = nz;
         S.E[x * kPlanes + y] = (uint8_t)ns;
         S.E[y * kPlanes + p] = (uint8_t)ns;
         S.E[p * kPlanes + x] = (uint8_t)ns;
       }
+      if (base == 0) {
+        ax = nx; ay = ny; az = nz;
+      } else {
+        bx = nx; by = ny; bz = nz;
+      }
     }
     wave_sync();
 
-    const bool nl0 = kept0 || (((F0 >> lane) & 1ull) && r0 < B);
-    const bool nl1 = kept1 || (((F1 >> lane) & 1ull) && r1 < B);
+    // A free slot of rank r took the vertex of boundary edge r, computed by
+    // lane r mod 64: fetch it from that lane.
+    const bool new0 = ((F0 >> lane) & 1ull) && r0 < B;
+    const bool new1 = ((F1 >> lane) & 1ull) && r1 < B;
+    double g0x = __shfl(ax, r0 & 63, 64), g0y = __shfl(ay, r0 & 63, 64), g0z = __shfl(az, r0 & 63, 64);
+    double g1x = __shfl(ax, r1 & 63, 64), g1y = __shfl(ay, r1 & 63, 64), g1z = __shfl(az, r1 & 63, 64);
+    if (B > 64) {
+      const double h0x = __shfl(bx, r0 & 63, 64), h0y = __shfl(by, r0 & 63, 64), h0z = __shfl(bz, r0 & 63, 64);
+      const double h1x = __shfl(bx, r1 & 63, 64), h1y = __shfl(by, r1 & 63, 64), h1z = __shfl(bz, r1 & 63, 64);
+      if (r0 >= 64) { g0x = h0x; g0y = h0y; g0z = h0z; }
+      if (r1 >= 64) { g1x = h1x; g1y = h1y; g1z = h1z; }
+    }
+    if (new0) {
+      C.v0x = g0x; C.v0y = g0y; C.v0z = g0z;
+      C.t0 = S.tri[lane];
+    }
+    if (new1) {
+      C.v1x = g1x; C.v1y = g1y; C.v1z = g1z;
+      C.t1 = S.tri[lane + 64];
+    }
+    const bool nl0 = kept0 || new0;
+    const bool nl1 = kept1 || new1;
     C.L0 = __ballot(nl0);
     C.L1 = __ballot(nl1);
-    C.t0 = S.tri[lane];
-    C.t1 = S.tri[lane + 64];
-    C.v0x = S.vx[lane]; C.v0y = S.vy[lane]; C.v0z = S.vz[lane];
-    C.v1x = S.vx[lane + 64]; C.v1y = S.vy[lane + 64]; C.v1z = S.vz[lane + 64];
     double m2 = 0.0;
     if (nl0) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
     if (nl1) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
@@ -423,6 +484,10 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
 __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const CellRegs& C) {
   const int lane = __lane_id();
   const bool live0 = (C.L0 >> lane) & 1ull, live1 = (C.L1 >> lane) & 1ull;
+  // The candidate list is dead now: its storage takes the vertex copies.
+  wave_sync();
+  S.vx[lane] = C.v0x; S.vy[lane] = C.v0y; S.vz[lane] = C.v0z;
+  S.vx[lane + 64] = C.v1x; S.vy[lane + 64] = C.v1y; S.vz[lane + 64] = C.v1z;
   S.first[lane] = kVerts;
   wave_sync();
   if (live0) {

@@ -281,7 +281,10 @@ mm_status Engine::check_flags(int flags, int bad_cell, std::string& msg) const {
   if (flags & F_BADPOS) { msg = "a position is not finite or lies outside [0, L): " + at; return MM_EINVAL; }
   if (flags & F_PLANES) { msg = "a cell has more than 64 live faces: " + at; return MM_ECAPACITY; }
   if (flags & F_VERTS) { msg = "a cell has more than 128 vertices: " + at; return MM_ECAPACITY; }
-  if (flags & F_CANDS) { msg = "more than 128 neighbour candidates in a cell's stencil: " + at; return MM_ECAPACITY; }
+  if (flags & F_CANDS) {
+    msg = "more than " + std::to_string(kCands) + " neighbour candidates in one distance shell of a cell: " + at;
+    return MM_ECAPACITY;
+  }
   if (flags & F_FACECAP) { msg = "more unique faces than the face capacity: " + at; return MM_ECAPACITY; }
   if (flags & F_BOX) { msg = "a cell is too large for the periodic box (needs 2 R_max < L): " + at; return MM_EDEGENERATE; }
   if (flags & F_INCOMPLETE) { msg = "a cell could not be completed: " + at; return MM_EDEGENERATE; }
