@@ -436,6 +436,30 @@ __global__ __launch_bounds__(kThreads) void k_predict(const SegDesc* __restrict_
   for (int q = 0; q < 5; ++q) Uh[5 * s + q] = uh[q];
 }
 
+// Scheme values one face needs from its segment.  When a wavefront's faces
+// all belong to one segment (every launch of a single simulation, and all
+// but the boundary wavefronts of a batch) they come through scalar loads.
+struct FaceParams {
+  double L[3];
+  double theta, gamma, rho_floor, p_floor, dt;
+};
+
+__device__ inline FaceParams face_params(const SegDesc* segs, const SegStatus* dt_src, double dt_fixed, int seg) {
+  const int s0 = __builtin_amdgcn_readfirstlane(seg);
+  const int sg = __all(seg == s0) ? s0 : seg;
+  const HydroParams& hp = segs[sg].hp;
+  FaceParams P;
+  P.L[0] = hp.L[0];
+  P.L[1] = hp.L[1];
+  P.L[2] = hp.L[2];
+  P.theta = hp.theta;
+  P.gamma = hp.gamma;
+  P.rho_floor = hp.rho_floor;
+  P.p_floor = hp.p_floor;
+  P.dt = seg_dt(segs, dt_src, sg, dt_fixed);
+  return P;
+}
+
 // One thread per unique face (Sec. 4 items 1-5, Sec. 4.1 reconstruction):
 // phi = dt A F, F the lab-frame flux from the owner i toward j.  Each XCD
 // takes one contiguous eighth of the face list (faces are in owner order, so
@@ -455,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
     const FluxCell<R> A = rec[F.i];
     const FluxCell<R> B = rec[F.j];
     const int seg = F.seg;
-    const HydroParams& hp = segs[seg].hp;
+    const FaceParams hp = face_params(segs, dt_src, dt_fixed, seg);
     int kx, ky, kz;
     decode(F.code, kx, ky, kz);
     // Geometry in double: r_j + s - r_i, face centre and centroid offsets.
@@ -491,7 +515,7 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
     if (hit) atomicAdd(&segst[seg].floor_hits[2], (unsigned long long)hit);
     R Fx[5];
     moving_hllc(UL, UR, nrm, wt, (R)hp.gamma, Fx);
-    const R scale = (R)(seg_dt(segs, dt_src, seg, dt_fixed) * F.A);
+    const R scale = (R)(hp.dt * F.A);
 #pragma unroll
     for (int q = 0; q < 5; ++q) phi[5 * f + q] = scale * Fx[q];
   }
