@@ -347,14 +347,46 @@ __device__ void sort_candidates(TessLds& S, const int nc) {
   wave_sync();
 }
 
+// A value every lane holds equally (read from LDS at a uniform address),
+// moved to a scalar register so branches on it are uniform.
+__device__ inline int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline double uniform_f64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Squared distance bound of the farthest live vertex (float, rounded up).
+__device__ inline double farthest_bound(const CellRegs& C) {
+  const int lane = __lane_id();
+  double m2 = 0.0;
+  if ((C.L0 >> lane) & 1ull) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
+  if ((C.L1 >> lane) & 1ull) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
+  return wave_max_bound(m2);
+}
+
 // Cuts the cell by the ordered candidates, stopping at the first one farther
 // than twice the farthest vertex (Sec. 3).  Returns 0 or a failure bit.
+// A cut only moves vertices inward (new vertices are convex combinations of
+// old ones), so the bound of the farthest vertex stays valid after a cut: it
+// is recomputed after every fourth cut, when the stop test would fire, and
+// at the end.
 __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
   const int lane = __lane_id();
+  bool stale = false;
+  int since = 0;   // cuts since the bound was last recomputed
   for (int k = 0; k < nc; ++k) {
-    const int c = S.order[k];
-    const double4 q = S.cd[c];
-    if (q.w >= 4.0 * C.rmax2) break;   // farther images cannot cut the cell
+    const int c = uniform_i32(S.order[k]);
+    const double4 ql = S.cd[c];
+    const double4 q = make_double4(uniform_f64(ql.x), uniform_f64(ql.y), uniform_f64(ql.z), uniform_f64(ql.w));
+    if (q.w >= 4.0 * C.rmax2) {   // farther images cannot cut the cell
+      if (!stale) break;
+      C.rmax2 = farthest_bound(C);
+      stale = false;
+      since = 0;
+      if (q.w >= 4.0 * C.rmax2) break;
+    }
     const double h = 0.5 * q.w;
     const bool live0 = (C.L0 >> lane) & 1ull, live1 = (C.L1 >> lane) & 1ull;
     const bool out0 = live0 && (q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h);
@@ -472,11 +504,14 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     const bool nl1 = kept1 || new1;
     C.L0 = __ballot(nl0);
     C.L1 = __ballot(nl1);
-    double m2 = 0.0;
-    if (nl0) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
-    if (nl1) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
-    C.rmax2 = wave_max_bound(m2);
+    stale = true;
+    if (++since == 4) {
+      C.rmax2 = farthest_bound(C);
+      stale = false;
+      since = 0;
+    }
   }
+  if (stale) C.rmax2 = farthest_bound(C);
   return 0;
 }
 
