@@ -196,14 +196,18 @@ def serving_object(M, torch, args):
     prec = "mixed"
     budget = int(args.serve_budget_gib * (1 << 30))
 
-    def requests(arrivals):
+    def requests(arrivals, precision=prec):
         reqs = []
         for t, wl in zip(arrivals, wls):
-            reqs.append(dict(arrival=float(t), params=M.make_params(box=wl.box, precision=prec, **wl.params),
+            reqs.append(dict(arrival=float(t), params=M.make_params(box=wl.box, precision=precision, **wl.params),
                              pos=torch.from_numpy(wl.pos).cuda(), prim=torch.from_numpy(wl.prim).cuda(),
                              steps=wl.steps))
         return reqs
 
+    # Saturated rate of the same 32 requests served in plain FP64.
+    B64 = M.Batch(budget, max_sims=1024, precision="fp64")
+    _, st64 = B64.serve(requests([0.0] * 32, "fp64")[:32])
+    B64.close()
     # Calibration: the first 32 requests at once give the sustained rate;
     # arrivals then come at 0.8 of that rate divided by the mean request cost.
     B = M.Batch(budget, max_sims=1024, precision=prec)
@@ -220,6 +224,8 @@ def serving_object(M, torch, args):
     return {"workload": f"kelvin_helmholtz_stream_{nreq}", "requests": nreq, "completed_ok": ok,
             "cells_total": int(sum(wl.n for wl in wls)), "steps_per_request": 20, "precision": prec,
             "hbm_budget_bytes": budget, "arrival_rate_per_s": rate,
+            "saturated_value": st["cell_updates_per_s"], "saturated_fp64_value": st64["cell_updates_per_s"],
+            "saturated_speedup_vs_fp64": st["cell_updates_per_s"] / st64["cell_updates_per_s"],
             "value": stats["cell_updates_per_s"], "unit": "cell-updates/s",
             "step_latency_p50_ms": stats["step_p50"], "step_latency_p99_ms": stats["step_p99"],
             "step_latency_mean_ms": stats["step_mean"],

@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
                                                        const R* __restrict__ U,
                                                        const unsigned long long* __restrict__ counts,
                                                        const unsigned long long* __restrict__ soff,
-                                                       const NbrEntry* __restrict__ nbr,
+                                                       const NbrEntry<R>* __restrict__ nbr,
                                                        const double* __restrict__ minv, int limit, R* __restrict__ G,
                                                        const double* __restrict__ w, const SegStatus* dt_src,
                                                        double dt_fixed, R* __restrict__ Uh,
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int nf = (int)(counts[s] >> 32);
-  const NbrEntry* list = nbr + sell_slot(soff, s, 0);   // entry e at list[64 e]
+  const NbrEntry<R>* list = nbr + sell_slot(soff, s, 0);   // entry e at list[64 e]
   R ui[5], umax[5], umin[5], b[15];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
@@ -312,8 +312,8 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
 #pragma unroll
   for (int k = 0; k < 15; ++k) b[k] = R(0);
   for (int e = 0; e < nf; ++e) {
-    const NbrEntry E = list[64 * e];
-    const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2], wg = (R)E.wgt;
+    const NbrEntry<R> E = list[64 * e];
+    const R dx = E.d[0], dy = E.d[1], dz = E.d[2], wg = E.wgt;
     const R* uo = U + 5 * (int64_t)E.o;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -350,8 +350,8 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
 #pragma unroll
     for (int q = 0; q < 5; ++q) dpos[q] = dneg[q] = R(0);
     for (int e = 0; e < nf; ++e) {
-      const NbrEntry E = list[64 * e];
-      const R dx = (R)E.d[0], dy = (R)E.d[1], dz = (R)E.d[2];
+      const NbrEntry<R> E = list[64 * e];
+      const R dx = E.d[0], dy = E.d[1], dz = E.d[2];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
         const R D = g[3 * q] * dx + g[3 * q + 1] * dy + g[3 * q + 2] * dz;
@@ -682,7 +682,7 @@ void launch_cell_state(const SegDesc* segs, const int32_t* sseg, int64_t n, cons
 
 template <typename R>
 void launch_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U,
-                     const unsigned long long* counts, const unsigned long long* soff, const NbrEntry* nbr,
+                     const unsigned long long* counts, const unsigned long long* soff, const NbrEntry<R>* nbr,
                      const double* minv, int limit, R* G, const double* w, const SegStatus* dt_src, double dt_fixed,
                      R* U_half, FluxCell<R>* rec, const double* geo, const double* spos, SegStatus* segst,
                      hipStream_t st) {
@@ -769,7 +769,7 @@ void launch_copy_rows(const double* src, double* dst, int64_t n, int width, hipS
   template void launch_cell_state<R>(const SegDesc*, const int32_t*, int64_t, const double*, const int32_t*,      \
                                      const double*, double*, R*, double*, DevStatus*, SegStatus*, hipStream_t);   \
   template void launch_gradient<R>(const SegDesc*, const int32_t*, int64_t, const R*, const unsigned long long*,  \
-                                   const unsigned long long*, const NbrEntry*, const double*, int, R*,            \
+                                   const unsigned long long*, const NbrEntry<R>*, const double*, int, R*,         \
                                    const double*, const SegStatus*, double, R*, FluxCell<R>*, const double*,      \
                                    const double*, SegStatus*, hipStream_t);                                       \
   template void launch_pack_flux_cells<R>(int64_t, const R*, const R*, const double*, const double*,              \

@@ -38,12 +38,13 @@ __global__ __launch_bounds__(256) void k_slice_width(const unsigned long long* _
 // Sixteen lanes per cell; lane l takes the cell's faces l, l + 16, ...
 // The packed prefix sum off[] holds, for cell s, the index of its first
 // unique face in its low 32 bits.
+template <typename R>
 __global__ __launch_bounds__(kMeshThreads) void k_build_mesh(
     const double* __restrict__ spos, const double* __restrict__ geo, int64_t n, const SegDesc* __restrict__ segs,
     const int32_t* __restrict__ sseg, const StageNbr* __restrict__ stage_nb, const StageGeo* __restrict__ stage_geo,
     const unsigned long long* __restrict__ counts, const unsigned long long* __restrict__ off,
     const unsigned long long* __restrict__ soff, int64_t face_cap, int64_t sell_cap, Face* __restrict__ faces,
-    int32_t* __restrict__ csr, NbrEntry* __restrict__ nbr, double* __restrict__ minv, DevStatus* st,
+    int32_t* __restrict__ csr, NbrEntry<R>* __restrict__ nbr, double* __restrict__ minv, DevStatus* st,
     SegStatus* segst) {
   __shared__ int smax[kMeshThreads / 64];
   const int l = threadIdx.x & (kGroup - 1);
@@ -81,13 +82,12 @@ __global__ __launch_bounds__(kMeshThreads) void k_build_mesh(
       const double dy = dry + geo[4 * (int64_t)j + 2] - ciy;
       const double dz = drz + geo[4 * (int64_t)j + 3] - ciz;
       const double wgt = F.A / (dx * dx + dy * dy + dz * dz);
-      NbrEntry E;
+      NbrEntry<R> E{};
       E.o = j;
-      E.pad = 0;
-      E.d[0] = dx;
-      E.d[1] = dy;
-      E.d[2] = dz;
-      E.wgt = wgt;
+      E.d[0] = (R)dx;
+      E.d[1] = (R)dy;
+      E.d[2] = (R)dz;
+      E.wgt = (R)wgt;
       const int64_t slot = sbase + 64ll * e;
       nbr[slot] = E;
       m00 += wgt * dx * dx;
@@ -116,13 +116,19 @@ __global__ __launch_bounds__(kMeshThreads) void k_build_mesh(
         }
       } else {
         // The same face in the neighbour's list: neighbour s, opposite image.
+        // Two staged entries per 16-byte load (rows are 512-byte aligned).
         const int want = 26 - code;
         const int nfj = (int)(counts[j] >> 32);
+        const int4* row = reinterpret_cast<const int4*>(stage_nb + (int64_t)j * kMaxFaces);
         int found_meta = -1;
-        for (int t = 0; t < nfj; ++t) {
-          const StageNbr G = stage_nb[(int64_t)j * kMaxFaces + t];
-          if (G.j == (int)s && (G.meta & 255) == want) {
-            found_meta = G.meta;
+        for (int t = 0; t < nfj; t += 2) {
+          const int4 G = row[t >> 1];
+          if (G.x == (int)s && (G.y & 255) == want) {
+            found_meta = G.y;
+            break;
+          }
+          if (t + 1 < nfj && G.z == (int)s && (G.w & 255) == want) {
+            found_meta = G.w;
             break;
           }
         }
@@ -224,14 +230,19 @@ void launch_build_mesh(const double* spos, const double* geo, int64_t n, const S
                        const StageNbr* stage_nb, const StageGeo* stage_geo, const unsigned long long* counts,
                        const unsigned long long* off, unsigned long long* sw, unsigned long long* soff,
                        unsigned long long* scan_tmp, int64_t face_cap, int64_t sell_cap, Face* faces, int32_t* csr,
-                       NbrEntry* nbr, double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
+                       void* nbr, int precision, double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
   if (n > 0) {
     const int64_t nslices = (n + 63) / 64;
     hipLaunchKernelGGL(k_slice_width, dim3(blocks_for(nslices, 4)), dim3(256), 0, st, counts, n, sw);
     scan_u64(sw, soff, nslices, scan_tmp, st);
-    hipLaunchKernelGGL(k_build_mesh, dim3(blocks_for(n, kCellsPerBlock)), dim3(kMeshThreads), 0, st, spos, geo, n,
-                       segs, sseg, stage_nb, stage_geo, counts, off, soff, face_cap, sell_cap, faces, csr, nbr, minv,
-                       st_dev, segst);
+    if (precision == 1)   // MM_MIXED
+      hipLaunchKernelGGL(k_build_mesh<float>, dim3(blocks_for(n, kCellsPerBlock)), dim3(kMeshThreads), 0, st, spos,
+                         geo, n, segs, sseg, stage_nb, stage_geo, counts, off, soff, face_cap, sell_cap, faces, csr,
+                         (NbrEntry<float>*)nbr, minv, st_dev, segst);
+    else
+      hipLaunchKernelGGL(k_build_mesh<double>, dim3(blocks_for(n, kCellsPerBlock)), dim3(kMeshThreads), 0, st, spos,
+                         geo, n, segs, sseg, stage_nb, stage_geo, counts, off, soff, face_cap, sell_cap, faces, csr,
+                         (NbrEntry<double>*)nbr, minv, st_dev, segst);
   }
   hipLaunchKernelGGL(k_copy_totals, dim3(1), dim3(64), 0, st, off, n, st_dev);
 }

@@ -45,7 +45,7 @@ struct Engine {
   StageGeo* stage_geo = nullptr;
   Face* faces = nullptr;
   int32_t* csr = nullptr;
-  NbrEntry* nbr = nullptr;
+  void* nbr = nullptr;   // NbrEntry<R>[sell_cap]
   // State in internal order.
   void *U = nullptr, *G = nullptr, *Uh = nullptr, *rec = nullptr, *phi = nullptr;   // rec: FluxCell<R>[n]
   double *w = nullptr, *Qs = nullptr;

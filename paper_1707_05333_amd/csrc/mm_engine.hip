@@ -24,7 +24,7 @@ int64_t engine_bytes_per_cell(int precision) {
                            + 8 * (3 + 4 + 1 + 6 + 1 + 1)               // spos, geo, rmax2, minv, counts, off
                            + 16                                        // bucket count and offset
                            + (int64_t)kMaxFaces * (sizeof(StageNbr) + sizeof(StageGeo))
-                           + kListPerCell * (4 + sizeof(NbrEntry))     // per-cell lists
+                           + kListPerCell * (4 + (r == 4 ? sizeof(NbrEntry<float>) : sizeof(NbrEntry<double>)))
                            + r * (5 + 15 + 5) + 8 * (3 + 5)            // U, G, Uh, w, Qs
                            + (r == 4 ? sizeof(FluxCell<float>) : sizeof(FluxCell<double>));
   const int64_t per_face = sizeof(Face) + 5 * r;                       // face, phi
@@ -134,7 +134,8 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
   ok &= dalloc(&stage_geo, (size_t)N * kMaxFaces) == hipSuccess;
   ok &= dalloc(&faces, F) == hipSuccess;
   ok &= dalloc(&csr, sell_cap) == hipSuccess;
-  ok &= dalloc(&nbr, sell_cap) == hipSuccess;
+  ok &= hipMalloc(&nbr, std::max<size_t>(sell_cap * (precision == MM_MIXED ? sizeof(NbrEntry<float>)
+                                                                            : sizeof(NbrEntry<double>)), 1)) == hipSuccess;
   ok &= hipMalloc(&U, std::max<size_t>(5 * N * rs, 1)) == hipSuccess;
   ok &= hipMalloc(&G, std::max<size_t>(15 * N * rs, 1)) == hipSuccess;
   ok &= hipMalloc(&Uh, std::max<size_t>(5 * N * rs, 1)) == hipSuccess;
@@ -206,7 +207,7 @@ void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int3
   mark(2);
   scan_u64(counts, off, n_cells, scan_tmp, stream);
   launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, sw, soff, scan_tmp, fcap,
-                    sell_cap, faces, csr, nbr, minv, st, segst, stream);
+                    sell_cap, faces, csr, nbr, precision, minv, st, segst, stream);
 }
 
 namespace {
@@ -219,10 +220,10 @@ void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n
   if (any_fresh) launch_init_charges(E.segs, E.sseg, n, Q, E.perm, E.geo, Q, 1, E.stream);
   launch_cell_state<R>(E.segs, E.sseg, n, Q, E.perm, E.geo, E.Qs, U, E.w, E.st, E.segst, E.stream);
   E.mark(4);
-  launch_gradient<R>(E.segs, E.sseg, n, U, E.counts, E.soff, E.nbr, E.minv, kLimitMaskBit0, nullptr, E.w, E.segst,
+  launch_gradient<R>(E.segs, E.sseg, n, U, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv, kLimitMaskBit0, nullptr, E.w, E.segst,
                      0.0, Uh, nullptr, nullptr, nullptr, E.segst, E.stream);
   E.mark(5);
-  launch_gradient<R>(E.segs, E.sseg, n, Uh, E.counts, E.soff, E.nbr, E.minv, kLimitMaskBit1, nullptr, E.w, nullptr,
+  launch_gradient<R>(E.segs, E.sseg, n, Uh, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv, kLimitMaskBit1, nullptr, E.w, nullptr,
                      0.0, nullptr, rec, E.geo, E.spos, E.segst, E.stream);
   E.mark(6);
   launch_flux<R>(E.segs, E.fcap, nf_dev, E.faces, rec, E.segst, 0.0, phi, E.segst, E.stream);

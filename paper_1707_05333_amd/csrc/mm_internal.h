@@ -122,13 +122,25 @@ struct __align__(16) FluxCell {
   double r[3];
 };
 
+static_assert(sizeof(StageNbr) == 8, "two staged entries per 16-byte load");
+
 // Per-cell neighbour entry used by the gradient kernel: neighbour index,
-// centroid displacement d = c_j + s - c_i and LSQ weight A / |d|^2.
-struct NbrEntry {
+// centroid displacement d = c_j + s - c_i and LSQ weight A / |d|^2, in the
+// precision of the gradient arithmetic (40 bytes in FP64, 20 in mixed).
+template <typename R>
+struct NbrEntry;
+template <>
+struct NbrEntry<double> {
   int32_t o;
   int32_t pad;
   double d[3];
   double wgt;
+};
+template <>
+struct NbrEntry<float> {
+  int32_t o;
+  float d[3];
+  float wgt;
 };
 
 // Bucket of one coordinate; the sort and the tessellation must agree on it.
@@ -212,7 +224,7 @@ void launch_build_mesh(const double* spos, const double* geo, int64_t n, const S
                        const StageNbr* stage_nb, const StageGeo* stage_geo, const unsigned long long* counts,
                        const unsigned long long* off, unsigned long long* sw, unsigned long long* soff,
                        unsigned long long* scan_tmp, int64_t face_cap, int64_t sell_cap, Face* faces, int32_t* csr,
-                       NbrEntry* nbr, double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
+                       void* nbr, int precision, double* minv, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
 // Hydro kernels, instantiated for double (MM_FP64) and float (MM_MIXED).
 // Slot-space arrays (Q, pos, w, prim) are indexed through perm.  dt_src
@@ -229,7 +241,7 @@ enum : int { kLimitOff = 0, kLimitOn = 1, kLimitMaskBit0 = 2, kLimitMaskBit1 = 3
 // spos).
 template <typename R>
 void launch_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* U,
-                     const unsigned long long* counts, const unsigned long long* soff, const NbrEntry* nbr,
+                     const unsigned long long* counts, const unsigned long long* soff, const NbrEntry<R>* nbr,
                      const double* minv, int limit, R* G, const double* w, const SegStatus* dt_src, double dt_fixed,
                      R* U_half, FluxCell<R>* rec, const double* geo, const double* spos, SegStatus* segst,
                      hipStream_t st);

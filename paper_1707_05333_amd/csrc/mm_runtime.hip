@@ -263,12 +263,12 @@ mm_status mm_gradients(mm_ctx* c, const void* U, void* grad, int32_t limit) {
   const int lim = limit ? kLimitOn : kLimitOff;
   if (c->p.precision == MM_MIXED) {
     launch_gather_rows<float>((const float*)U, E.perm, n, 5, (float*)E.U, E.stream);
-    launch_gradient<float>(E.segs, E.sseg, n, (const float*)E.U, E.counts, E.soff, E.nbr, E.minv, lim, (float*)E.G, nullptr,
+    launch_gradient<float>(E.segs, E.sseg, n, (const float*)E.U, E.counts, E.soff, (const NbrEntry<float>*)E.nbr, E.minv, lim, (float*)E.G, nullptr,
                            nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, E.segst, E.stream);
     launch_scatter_rows<float>((const float*)E.G, E.perm, n, 15, (float*)grad, E.stream);
   } else {
     launch_gather_rows<double>((const double*)U, E.perm, n, 5, (double*)E.U, E.stream);
-    launch_gradient<double>(E.segs, E.sseg, n, (const double*)E.U, E.counts, E.soff, E.nbr, E.minv, lim, (double*)E.G,
+    launch_gradient<double>(E.segs, E.sseg, n, (const double*)E.U, E.counts, E.soff, (const NbrEntry<double>*)E.nbr, E.minv, lim, (double*)E.G,
                             nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, E.segst, E.stream);
     launch_scatter_rows<double>((const double*)E.G, E.perm, n, 15, (double*)grad, E.stream);
   }
