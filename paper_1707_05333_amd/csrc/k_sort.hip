@@ -134,6 +134,7 @@ __global__ void k_status_reset(DevStatus* s, SegStatus* segst, int nseg) {
   if (t == 0) {
     s->flags = 0;
     s->n_deferred = 0;
+    s->n_overflow = 0;
     s->max_faces = 0;
     s->bad_cell = 0x7fffffff;
     s->n_faces = 0;

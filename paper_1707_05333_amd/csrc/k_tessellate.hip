@@ -664,6 +664,7 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
     const double hi2 = fmin(reach * reach, g.r_filter * g.r_filter);
     const int nc = gather(S, A, g, s, r, b, g.ring, 0.0, hi2);
     if (nc > kCands) {
+      if (__lane_id() == 0) atomicAdd(&A.st->n_overflow, 1);
       defer_cell(A, s, -1.0);
       return;
     }
@@ -748,7 +749,9 @@ void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const
   TessArgs A{spos, n, segs, sseg, boff, stage_nb, stage_geo, counts, geo, rmax2, deferred, st_dev, segst};
   const unsigned blocks = (unsigned)((n + kWaves - 1) / kWaves);
   hipLaunchKernelGGL(k_tess_pass1, dim3(blocks), dim3(64 * kWaves), 0, st, A);
-  const unsigned blocks2 = (unsigned)std::min<int64_t>(blocks, 1024);
+  // The deferred count is known on the device only: enough blocks for a
+  // large share of deferred cells, each exits at once when there is none.
+  const unsigned blocks2 = (unsigned)std::min<int64_t>(blocks, 16384);
   hipLaunchKernelGGL(k_tess_pass2, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
 }
 

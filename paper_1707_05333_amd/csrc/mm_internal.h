@@ -46,6 +46,8 @@ struct DevStatus {
   int n_deferred;                // cells handed to the wide-stencil pass
   int max_faces;
   int bad_cell;                  // lowest internal cell index with a failure
+  int n_overflow;                // of those, cells whose first-pass candidates overflowed
+  int pad;
   unsigned long long n_faces;    // unique faces (copy of the scan total)
   unsigned long long n_csr;      // directed faces (copy of the scan total)
   int asym_cell, asym_nbr;       // one face without a partner (internal cells), for diagnostics
