@@ -16,6 +16,8 @@ Also reported on the same line:
   mixed        the point blast (128^3, 100 steps) in mixed precision against
                the FP64 path: cell-updates/s of both, relative L1 density
                error, conservation drift;
+  gresho       the Gresho-Chan vortex to t = 2 at 32^2, 64^2, 128^2: L1 of the
+               tangential speed and its rate of convergence;
   serving      a Poisson stream of Kelvin-Helmholtz simulations (1e3..2e5
                points each, 20 steps, mixed) through the batch serving loop
                under an explicit device budget: throughput, p50/p99 step
@@ -58,6 +60,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision blast object")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving object")
+    ap.add_argument("--no-gresho", action="store_true", help="skip the Gresho-Chan convergence object")
     ap.add_argument("--mixed-steps", type=int, default=100)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -186,6 +189,43 @@ def mixed_object(M, torch, args):
             "reference": "the FP64 GPU path, which matches the FP64 oracle to 1e-10 in the parity tests"}
 
 
+def gresho_object(M, torch, args):
+    """Gresho-Chan vortex to t = 2 at 32^2, 64^2, 128^2 (FP64): L1 of the
+    tangential speed at the generators and its convergence rate."""
+    import numpy as np
+    import workloads as W
+    out = {"workload": "gresho_chan_vortex_t2", "precision": "fp64", "runs": []}
+    for N in (32, 64, 128):
+        wl = W.gresho(N)
+        mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, **wl.params))
+        pos = torch.from_numpy(wl.pos.copy()).cuda()
+        mm.tessellate(pos)
+        Q = mm.init_charges(torch.from_numpy(wl.prim.copy()).cuda())
+        w = torch.empty_like(pos)
+        t, steps = 0.0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while t < 2.0 * (1 - 1e-12):
+            t += mm.step(pos, w, Q, dt_max=2.0 - t)["dt"]
+            steps += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        x, q = pos.cpu().numpy(), Q.cpu().numpy()
+        dx, dy = x[:, 0] - 0.5, x[:, 1] - 0.5
+        r = np.hypot(dx, dy)
+        v = q[:, 1:3] / q[:, :1]
+        vphi = (-dy * v[:, 0] + dx * v[:, 1]) / r
+        l1 = float(np.mean(np.abs(vphi - W.gresho_profile(r)[1])))
+        out["runs"].append({"N": N, "cells": wl.n, "steps": steps, "l1_vphi": l1,
+                            "cell_updates_per_s": wl.n * steps / wall})
+        mm.close()
+        log(f"gresho N={N}: L1 {l1:.4e} in {steps} steps")
+    l1 = [r["l1_vphi"] for r in out["runs"]]
+    out["l1_slope"] = math.log(l1[0] / l1[-1]) / math.log(4.0)
+    out["paper_slope"] = 0.88
+    return out
+
+
 def serving_object(M, torch, args):
     """A Poisson stream of Kelvin-Helmholtz runs through the serving loop."""
     import numpy as np
@@ -297,6 +337,8 @@ def main():
         out["mixed"] = mixed_object(M, torch, args)
         log(f"mixed: {out['mixed']['value']:.3e} vs fp64 {out['mixed']['fp64_value']:.3e}, "
             f"L1 {out['mixed']['l1_rho_rel_vs_fp64']:.2e}")
+    if not args.no_gresho:
+        out["gresho"] = gresho_object(M, torch, args)
     if not args.no_serve:
         out["serving"] = serving_object(M, torch, args)
         log(f"serving: {out['serving']['value']:.3e} cell-updates/s, p50 {out['serving']['step_latency_p50_ms']:.2f} ms"

@@ -171,6 +171,16 @@ def test_step_parity_poisson_smooth(orc):
     assert np.abs(pg - po).max() < TOL
 
 
+def test_step_parity_gresho(orc):
+    # The Gresho-Chan vortex (Sec. 5) at an equivalent 2D resolution of 16^2:
+    # a rotating, pressure-supported state on a thin periodic slab.
+    wl = W.gresho(16)
+    _print_case("step gresho", n=wl.n, steps=3)
+    pg, Qg, wg, po, Qo, wo = _run_steps(orc, wl, 3)
+    assert scaled_err(Qg, Qo) < TOL
+    assert np.abs(pg - po).max() < TOL
+
+
 def test_step_parity_blast(orc):
     wl = W.c3_point_blast(n_side=16)
     _print_case("step blast", n=wl.n, steps=3)

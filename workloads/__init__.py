@@ -182,6 +182,42 @@ def c4_kelvin_helmholtz(k, n_min=1000, n_max=200000, base_seed=4000) -> Workload
                     steps=20, meta=dict(shape=(side,) * 3, request=int(k)))
 
 
+def gresho_profile(r):
+    """Gresho-Chan vortex (Sec. 5 test problems): the steady pressure and
+    tangential speed at cylinder radius r (rho = 1)."""
+    r = np.asarray(r, dtype=np.float64)
+    inner, mid = r < 0.2, (r >= 0.2) & (r < 0.4)
+    P = np.full(r.shape, 3.0 + 4.0 * math.log(2.0))
+    P = np.where(inner, 5.0 + 12.5 * r * r, P)
+    with np.errstate(divide="ignore"):
+        P = np.where(mid, 9.0 + 12.5 * r * r - 20.0 * r + 4.0 * np.log(np.maximum(5.0 * r, 1e-300)), P)
+    vphi = np.where(inner, 5.0 * r, np.where(mid, 2.0 - 5.0 * r, 0.0))
+    return P, vphi
+
+
+def gresho(N=64, seed=6, gamma=5.0 / 3.0, jitter=0.25) -> Workload:
+    """Gresho-Chan vortex at an equivalent 2D resolution N^2: an N x N x nz
+    lattice with nz = round(0.2 N) in the periodic box 1 x 1 x nz/N (about
+    0.2), vortex axis along z through (0.5, 0.5).  The default jitter of a
+    quarter spacing breaks the lattice's alignment with the flow, as a glass
+    does, while keeping the local spacing regular."""
+    nz = max(1, int(round(0.2 * N)))
+    box = (1.0, 1.0, nz / N)
+    pos = jittered_lattice((N, N, nz), box, jitter=jitter, seed=seed)
+    n = pos.shape[0]
+    dx, dy = pos[:, 0] - 0.5, pos[:, 1] - 0.5
+    r = np.sqrt(dx * dx + dy * dy)
+    P, vphi = gresho_profile(r)
+    rs = np.where(r > 0.0, r, 1.0)
+    prim = np.zeros((n, 5))
+    prim[:, 0] = 1.0
+    prim[:, 1] = -vphi * dy / rs
+    prim[:, 2] = vphi * dx / rs
+    prim[:, 4] = P
+    return Workload(f"gresho_{N}", pos, prim, box, _params(gamma=gamma), steps=0,
+                    meta=dict(shape=(N, N, nz), t_end=2.0))
+
+
 def poisson_arrivals(n, rate, seed=4) -> np.ndarray:
     """Arrival times (seconds, non-decreasing, first at 0) of n requests of a
     Poisson stream with the given rate (requests per second)."""
