@@ -57,7 +57,6 @@ struct __align__(16) TessLds {
   uint32_t tri[kVerts];                // a | b << 8 | c << 16
   int32_t pcand[kPlanes];              // neighbour of each plane slot (j << 5 | image code); -1 - k for box plane k
   uint8_t E[kPlanes * kPlanes];
-  uint8_t freelist[kVerts];
   uint16_t elist[kVerts];              // boundary edges of one cut: x | y << 8
 };
 
@@ -129,11 +128,12 @@ __device__ __forceinline__ unsigned long long wave_or(unsigned long long v) {
          (unsigned)__builtin_amdgcn_readlane((int)lo, 63);
 }
 
-// Upper bound of the wave's largest non-negative value: each value is
-// rounded up to float, whose bit patterns order like the values.
+// Upper bound of the wave's largest non-negative finite value.  Bit patterns
+// of non-negative doubles order like the values, so the high word plus one
+// (low word zero) lies above every value with that high word.
 __device__ __forceinline__ double wave_max_bound(double x) {
-  const unsigned b = __float_as_uint(__double2float_ru(x));
-  return (double)__uint_as_float(wave_umax32(b));
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(x) >> 32) + 1u;
+  return __longlong_as_double((long long)((unsigned long long)wave_umax32(hi) << 32));
 }
 
 // Butterfly sum: every lane ends with the bitwise-same result.
@@ -198,7 +198,6 @@ __device__ void init_box(TessLds& S, const GridParams& g, CellRegs& C) {
     int a1 = py, a2 = pz;
     if (sx * sy * sz < 0) { a1 = pz; a2 = py; }   // orientation: det(d_a, d_b, d_c) > 0
     C.t0 = (uint32_t)(px | (a1 << 8) | (a2 << 16));
-    S.tri[lane] = C.t0;
     C.v0x = sx * (0.5 * g.L[0]);
     C.v0y = sy * (0.5 * g.L[1]);
     C.v0z = sz * (0.5 * g.L[2]);
@@ -412,10 +411,13 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     // Boundary of the removed cap: edges of removed vertices whose
     // neighbour across the edge survives (bit k of bm: edge k of the slot).
     const unsigned long long L0 = C.L0, L1 = C.L1;
-    auto is_kept = [&](int t) -> bool {
-      const bool lv = t < 64 ? ((L0 >> t) & 1ull) : ((L1 >> (t - 64)) & 1ull);
-      const bool ot = t < 64 ? ((M0 >> t) & 1ull) : ((M1 >> (t - 64)) & 1ull);
-      return lv && !ot;
+    const unsigned long long K0 = L0 & ~M0, K1 = L1 & ~M1;   // slots that survive the cut
+    // Slot t < 128 picks its half by a mask (a plain select here is turned
+    // into a two-entry table in private memory).
+    auto is_kept = [K0, K1](int t) -> bool {
+      const unsigned long long hi = 0ull - (unsigned long long)((unsigned)t >> 6);
+      const unsigned long long k = K0 ^ ((K0 ^ K1) & hi);
+      return (k >> (t & 63)) & 1ull;
     };
     auto boundary = [&](uint32_t T) -> int {
       const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
@@ -434,10 +436,6 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     const unsigned long long F0 = ~L0 | M0, F1 = ~L1 | M1;   // free slots after the cut
     const int nf0 = __popcll(F0);
     if (B > nf0 + __popcll(F1)) return F_VERTS;
-    const int r0 = __popcll(F0 & lanes_below());
-    const int r1 = nf0 + __popcll(F1 & lanes_below());
-    if ((F0 >> lane) & 1ull) S.freelist[r0] = (uint8_t)lane;
-    if ((F1 >> lane) & 1ull) S.freelist[r1] = (uint8_t)(lane + 64);
     if (lane == 0) {
       S.pl[p] = make_double4(q.x, q.y, q.z, h);
       S.pcand[p] = S.cjk[c];   // the neighbour itself: later shells reuse the candidate slots
@@ -456,50 +454,32 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     wave_sync();   // every E lookup above is done before any write below
 
     // One new vertex per boundary edge: the fan of triangles (x, y, p)
-    // around the new face, in the free slots.  Lane e computes edge e (and
-    // e + 64 when the cap has more boundary edges than lanes).
-    double ax = 0.0, ay = 0.0, az = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
-    for (int base = 0; base < B; base += 64) {
-      const int ee = base + lane;
-      double nx = 0.0, ny = 0.0, nz = 0.0;
-      if (ee < B) {
-        const int xy = S.elist[ee];
-        const int x = xy & 255, y = xy >> 8;
-        const int ns = S.freelist[ee];
-        S.tri[ns] = (uint32_t)(x | (y << 8) | (p << 16));
-        intersect3(S.pl[x], S.pl[y], S.pl[p], nx, ny, nz);
-        S.E[x * kPlanes + y] = (uint8_t)ns;
-        S.E[y * kPlanes + p] = (uint8_t)ns;
-        S.E[p * kPlanes + x] = (uint8_t)ns;
-      }
-      if (base == 0) {
-        ax = nx; ay = ny; az = nz;
-      } else {
-        bx = nx; by = ny; bz = nz;
-      }
-    }
-    wave_sync();
-
-    // A free slot of rank r took the vertex of boundary edge r, computed by
-    // lane r mod 64: fetch it from that lane.
+    // around the new face.  Boundary edge r goes to the free slot of rank r
+    // (slots of the first register in lane order, then of the second), and
+    // the lane holding that slot builds it in place.
+    const int r0 = __popcll(F0 & lanes_below());
+    const int r1 = nf0 + __popcll(F1 & lanes_below());
     const bool new0 = ((F0 >> lane) & 1ull) && r0 < B;
     const bool new1 = ((F1 >> lane) & 1ull) && r1 < B;
-    double g0x = __shfl(ax, r0 & 63, 64), g0y = __shfl(ay, r0 & 63, 64), g0z = __shfl(az, r0 & 63, 64);
-    double g1x = __shfl(ax, r1 & 63, 64), g1y = __shfl(ay, r1 & 63, 64), g1z = __shfl(az, r1 & 63, 64);
-    if (B > 64) {
-      const double h0x = __shfl(bx, r0 & 63, 64), h0y = __shfl(by, r0 & 63, 64), h0z = __shfl(bz, r0 & 63, 64);
-      const double h1x = __shfl(bx, r1 & 63, 64), h1y = __shfl(by, r1 & 63, 64), h1z = __shfl(bz, r1 & 63, 64);
-      if (r0 >= 64) { g0x = h0x; g0y = h0y; g0z = h0z; }
-      if (r1 >= 64) { g1x = h1x; g1y = h1y; g1z = h1z; }
-    }
     if (new0) {
-      C.v0x = g0x; C.v0y = g0y; C.v0z = g0z;
-      C.t0 = S.tri[lane];
+      const int xy = S.elist[r0];
+      const int x = xy & 255, y = xy >> 8;
+      C.t0 = (uint32_t)(x | (y << 8) | (p << 16));
+      intersect3(S.pl[x], S.pl[y], S.pl[p], C.v0x, C.v0y, C.v0z);
+      S.E[x * kPlanes + y] = (uint8_t)lane;
+      S.E[y * kPlanes + p] = (uint8_t)lane;
+      S.E[p * kPlanes + x] = (uint8_t)lane;
     }
     if (new1) {
-      C.v1x = g1x; C.v1y = g1y; C.v1z = g1z;
-      C.t1 = S.tri[lane + 64];
+      const int xy = S.elist[r1];
+      const int x = xy & 255, y = xy >> 8;
+      C.t1 = (uint32_t)(x | (y << 8) | (p << 16));
+      intersect3(S.pl[x], S.pl[y], S.pl[p], C.v1x, C.v1y, C.v1z);
+      S.E[x * kPlanes + y] = (uint8_t)(lane + 64);
+      S.E[y * kPlanes + p] = (uint8_t)(lane + 64);
+      S.E[p * kPlanes + x] = (uint8_t)(lane + 64);
     }
+    wave_sync();
     const bool nl0 = kept0 || new0;
     const bool nl1 = kept1 || new1;
     C.L0 = __ballot(nl0);
@@ -523,6 +503,8 @@ __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const Cel
   wave_sync();
   S.vx[lane] = C.v0x; S.vy[lane] = C.v0y; S.vz[lane] = C.v0z;
   S.vx[lane + 64] = C.v1x; S.vy[lane + 64] = C.v1y; S.vz[lane + 64] = C.v1z;
+  S.tri[lane] = C.t0;
+  S.tri[lane + 64] = C.t1;
   S.first[lane] = kVerts;
   wave_sync();
   if (live0) {
