@@ -18,6 +18,8 @@ Also reported on the same line:
                error, conservation drift;
   gresho       the Gresho-Chan vortex to t = 2 at 32^2, 64^2, 128^2: L1 of the
                tangential speed and its rate of convergence;
+  sod_paper    the paper's Sod tube to t = 2, moving and static mesh, HLLC and
+               HLL: L1 of density against the exact solution, oscillations;
   serving      a Poisson stream of Kelvin-Helmholtz simulations (1e3..2e5
                points each, 20 steps, mixed) through the batch serving loop
                under an explicit device budget: throughput, p50/p99 step
@@ -61,6 +63,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision blast object")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving object")
     ap.add_argument("--no-gresho", action="store_true", help="skip the Gresho-Chan convergence object")
+    ap.add_argument("--no-sod-paper", action="store_true", help="skip the paper's Sod tube object")
     ap.add_argument("--mixed-steps", type=int, default=100)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -226,6 +229,110 @@ def gresho_object(M, torch, args):
     return out
 
 
+def _exact_riemann_rho(left, right, gamma, xi):
+    """Density of the exact ideal-gas Riemann solution at x/t = xi (the
+    textbook construction: star pressure by bisection on the sum of the
+    two wave curves, then the wave pattern sampled at xi)."""
+    import numpy as np
+    (rl, ul, pl), (rr, ur, pr) = left, right
+    cl, cr = math.sqrt(gamma * pl / rl), math.sqrt(gamma * pr / rr)
+
+    def f(p, r, pk, c):
+        if p > pk:
+            a, b = 2.0 / ((gamma + 1) * r), (gamma - 1) / (gamma + 1) * pk
+            return (p - pk) * math.sqrt(a / (p + b))
+        return 2 * c / (gamma - 1) * ((p / pk) ** ((gamma - 1) / (2 * gamma)) - 1)
+
+    lo, hi = 1e-12, 10 * max(pl, pr)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid, rl, pl, cl) + f(mid, rr, pr, cr) + ur - ul < 0 else (lo, mid)
+    ps = 0.5 * (lo + hi)
+    us = 0.5 * (ul + ur) + 0.5 * (f(ps, rr, pr, cr) - f(ps, rl, pl, cl))
+    g1 = (gamma - 1) / (gamma + 1)
+
+    def side(r, p, c, sgn):   # sgn -1: left wave, +1: right wave; returns star density and wave bounds
+        if ps > p:
+            rs = r * (ps / p + g1) / (g1 * ps / p + 1)
+            S = sgn * c * math.sqrt((gamma + 1) / (2 * gamma) * ps / p + (gamma - 1) / (2 * gamma))
+            return rs, S, S
+        rs = r * (ps / p) ** (1 / gamma)
+        cs = c * (ps / p) ** ((gamma - 1) / (2 * gamma))
+        return rs, sgn * c, us + sgn * cs
+
+    rsl, hl, tl = side(rl, pl, cl, -1)
+    rsr, hr, tr = side(rr, pr, cr, +1)
+    hl += ul; hr += ur
+    if ps > pl: tl = hl
+    if ps > pr: tr = hr
+    xi = np.asarray(xi, dtype=np.float64)
+    out = np.empty_like(xi)
+    for i, s in enumerate(xi):
+        if s < us:
+            if s < hl: out[i] = rl
+            elif s > tl: out[i] = rsl
+            else:
+                c = 2 / (gamma + 1) * (cl + (gamma - 1) / 2 * (ul - s))
+                out[i] = rl * (c / cl) ** (2 / (gamma - 1))
+        else:
+            if s > hr: out[i] = rr
+            elif s < tr: out[i] = rsr
+            else:
+                c = 2 / (gamma + 1) * (cr - (gamma - 1) / 2 * (ur - s))
+                out[i] = rr * (c / cr) ** (2 / (gamma - 1))
+    return out
+
+
+def sod_paper_object(M, torch, args):
+    """The paper's Sod tube (16 x 1 x 1, rho_R = 0.25, P_R = 0.1795) to t = 2
+    on the moving and the static mesh with HLLC and HLL: L1 of density
+    against the exact solution and the total-variation excess of the
+    x-profile (oscillations)."""
+    import numpy as np
+    import workloads as W
+    k = 14
+    runs = []
+    for sm in (False, True):
+        for rs in ("hllc", "hll"):
+            wl = W.sod_paper(k=k, riemann=rs, static_mesh=sm)
+            mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, **wl.params))
+            pos = torch.from_numpy(wl.pos.copy()).cuda()
+            mm.tessellate(pos)
+            Q = mm.init_charges(torch.from_numpy(wl.prim.copy()).cuda())
+            w = torch.empty_like(pos)
+            t, steps = 0.0, 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while t < 2.0 * (1 - 1e-12):
+                t += mm.step(pos, w, Q, dt_max=2.0 - t)["dt"]
+                steps += 1
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            mm.tessellate(pos)
+            V = mm.mesh_export().V.cpu().numpy()
+            x, q = pos.cpu().numpy(), Q.cpu().numpy()
+            mm.close()
+            rho = q[:, 0] / V
+            xx = x[:, 0]
+            mid = (xx >= 4.0) & (xx < 12.0)
+            ex = np.empty_like(xx)
+            L, R = wl.meta["left"], wl.meta["right"]
+            ex[mid] = _exact_riemann_rho(L, R, 1.4, (xx[mid] - 8.0) / 2.0)
+            xe = np.where(xx[~mid] < 4.0, xx[~mid], xx[~mid] - 16.0)
+            ex[~mid] = _exact_riemann_rho(R, L, 1.4, xe / 2.0)
+            nb = 16 * k
+            b = np.minimum((xx / 16.0 * nb).astype(int), nb - 1)
+            cnt = np.maximum(np.bincount(b, minlength=nb), 1)
+            tv = lambda p: float(np.abs(np.diff(np.r_[p, p[:1]])).sum())
+            runs.append({"mesh": "static" if sm else "moving", "riemann": rs, "cells": wl.n, "steps": steps,
+                         "l1_rho": float(np.mean(np.abs(rho - ex))),
+                         "tv_excess": tv(np.bincount(b, weights=rho, minlength=nb) / cnt)
+                         - tv(np.bincount(b, weights=ex, minlength=nb) / cnt),
+                         "cell_updates_per_s": wl.n * steps / wall})
+            log(f"sod_paper {runs[-1]['mesh']} {rs}: L1 {runs[-1]['l1_rho']:.3e} in {steps} steps")
+    return {"workload": "sod_paper_16x1x1_t2", "precision": "fp64", "theta": 0.49, "runs": runs}
+
+
 def serving_object(M, torch, args):
     """A Poisson stream of Kelvin-Helmholtz runs through the serving loop."""
     import numpy as np
@@ -339,6 +446,8 @@ def main():
             f"L1 {out['mixed']['l1_rho_rel_vs_fp64']:.2e}")
     if not args.no_gresho:
         out["gresho"] = gresho_object(M, torch, args)
+    if not args.no_sod_paper:
+        out["sod_paper"] = sod_paper_object(M, torch, args)
     if not args.no_serve:
         out["serving"] = serving_object(M, torch, args)
         log(f"serving: {out['serving']['value']:.3e} cell-updates/s, p50 {out['serving']['step_latency_p50_ms']:.2f} ms"

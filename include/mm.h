@@ -60,7 +60,9 @@ typedef enum {
 } mm_status;
 
 enum { MM_FP64 = 0, MM_MIXED = 1 };
-enum { MM_HLLC = 0 };
+/* Riemann solver of the face fluxes (Sec. 4 item 4): HLLC, the paper's
+ * default, or the more diffusive HLL; both with Davis wave-speed bounds. */
+enum { MM_HLLC = 0, MM_HLL = 1 };
 
 /* Scheme parameters.  Defaults (mm_default_params): gamma = 5/3, cfl = 0.3,
  * eta = 1 (Lagrangian mesh, Sec. 4.2), chi = 1 and zeta = 0.25 (roundness
@@ -79,7 +81,7 @@ typedef struct {
   double p_floor;            /* pressure floor (Sec. 4.1) */
   int32_t precision;         /* MM_FP64, or MM_MIXED: gradients, predictor, reconstruction and
                                 Riemann solves in float; geometry and charge sums in double */
-  int32_t riemann;           /* MM_HLLC */
+  int32_t riemann;           /* MM_HLLC or MM_HLL */
   int32_t limit_mask;        /* S10 limiter: bit 0 on the time-n gradient, bit 1 on the half-step one */
   int32_t predictor_frame;   /* 0: rate following the generator, -div F + w . grad U; 1: Eulerian -div F */
 } mm_params;

@@ -40,18 +40,19 @@ class Params(ctypes.Structure):
         ("limiter_disp", ctypes.c_int32),
         ("predictor_frame", ctypes.c_int32),
         ("limit_mask", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("riemann", ctypes.c_int32),
     ]
 
 
 def make_params(box, gamma, cfl=0.3, eta=1.0, chi=1.0, zeta=0.25, theta=0.49,
                 rho_floor=1e-12, p_floor=1e-14, limiter_disp=0, predictor_frame=0,
-                limit_mask=3, **_ignored) -> Params:
+                limit_mask=3, riemann=0, **_ignored) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.gamma, p.cfl, p.eta, p.chi, p.zeta, p.theta = gamma, cfl, eta, chi, zeta, theta
     p.rho_floor, p.p_floor = rho_floor, p_floor
     p.limiter_disp, p.predictor_frame, p.limit_mask = limiter_disp, predictor_frame, limit_mask
+    p.riemann = riemann
     return p
 
 
@@ -91,7 +92,8 @@ def lib():
         L.orc_step.argtypes = [ctypes.c_int64, _dp, _dp, _dp, P, ctypes.c_double, ctypes.c_int32, _dp, _i64p]
         L.orc_step.restype = ctypes.c_int32
         L.orc_face_velocity.argtypes = [_dp] * 6
-        L.orc_moving_face_flux.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.orc_moving_face_flux.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int32, _dp]
+        L.orc_hll_prim.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_hllc_prim.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
         L.orc_dm_factor.argtypes = [ctypes.c_double] * 3
         L.orc_dm_factor.restype = ctypes.c_double
@@ -256,10 +258,11 @@ def face_velocity(ri, rj_img, wi, wj, f) -> np.ndarray:
     return out
 
 
-def moving_face_flux(UL, UR, n, wt, gamma) -> np.ndarray:
+def moving_face_flux(UL, UR, n, wt, gamma, riemann=0) -> np.ndarray:
+    """Lab-frame flux across a moving face; riemann 0 is HLLC, 1 is HLL."""
     a = [_f64(x) for x in (UL, UR, n, wt)]
     F = np.empty(5)
-    lib().orc_moving_face_flux(*[_p(x) for x in a], float(gamma), _p(F))
+    lib().orc_moving_face_flux(*[_p(x) for x in a], float(gamma), int(riemann), _p(F))
     return F
 
 
@@ -267,6 +270,13 @@ def hllc_prim(WL, WR, n, gamma) -> np.ndarray:
     a = [_f64(x) for x in (WL, WR, n)]
     F = np.empty(5)
     lib().orc_hllc_prim(*[_p(x) for x in a], float(gamma), _p(F))
+    return F
+
+
+def hll_prim(WL, WR, n, gamma) -> np.ndarray:
+    a = [_f64(x) for x in (WL, WR, n)]
+    F = np.empty(5)
+    lib().orc_hll_prim(*[_p(x) for x in a], float(gamma), _p(F))
     return F
 
 

@@ -28,7 +28,8 @@
 //           dU/dt = -div F + w . grad U (Sec. 4.1, eqs. for the time
 //           derivative and the half-step state; Sec. 4 item 2).
 //   R-hllc  HLLC with Davis wave-speed bounds, written in normal/tangential
-//           form (Sec. 4 items 3-5; the paper follows Toro 2009).
+//           form (Sec. 4 items 3-5; the paper follows Toro 2009).  The HLL
+//           alternative (same item) uses the same wave-speed bounds.
 //   R-floor floors keep the velocity and pressure and raise the density, or
 //           keep density and velocity and raise the pressure (Sec. 4.1,
 //           floors paragraph; values are not given by the paper).
@@ -482,7 +483,7 @@ struct Params {
   int32_t limiter_disp;     // 0: c_j - c_i (R-s10); 1: face centroid - c_i
   int32_t predictor_frame;  // 0: moving generator (R-pred); 1: Eulerian
   int32_t limit_mask;       // S10 limiter on: bit 0 time-n gradient, bit 1 half-step gradient (default 3)
-  int32_t reserved;
+  int32_t riemann;          // 0: HLLC (the paper's default), 1: HLL (Sec. 4 item 4)
 };
 
 // R-floor (Sec. 4.1, floors paragraph).  U = (rho, m, E) densities.
@@ -746,17 +747,49 @@ void hllc(const Prim& L, const Prim& R, const double n[3], double gamma, double 
   for (int q = 0; q < 5; ++q) F[q] = FK[q] + SK * (Us[q] - UK[q]);
 }
 
+// HLL flux in the rest frame of the face (Sec. 4 item 4, Toro 2009 sec. 10.3):
+// one intermediate state between the fastest left- and right-going waves,
+// whose average over the fan follows from the integral form of the
+// conservation law.  Wave-speed bounds as in hllc().
+void hll(const Prim& L, const Prim& R, const double n[3], double gamma, double F[5]) {
+  const double uL = L.v[0] * n[0] + L.v[1] * n[1] + L.v[2] * n[2];
+  const double uR = R.v[0] * n[0] + R.v[1] * n[1] + R.v[2] * n[2];
+  const double cL = std::sqrt(gamma * L.P / L.rho), cR = std::sqrt(gamma * R.P / R.rho);
+  const double SL = std::min(uL - cL, uR - cR);
+  const double SR = std::max(uL + cL, uR + cR);
+  double FL[5], FR[5];
+  phys_flux(L.rho, L.v, L.P, n, gamma, FL);
+  phys_flux(R.rho, R.v, R.P, n, gamma, FR);
+  if (SL >= 0) {
+    for (int q = 0; q < 5; ++q) F[q] = FL[q];
+    return;
+  }
+  if (SR < 0) {
+    for (int q = 0; q < 5; ++q) F[q] = FR[q];
+    return;
+  }
+  const double EL = L.P / (gamma - 1.0) + 0.5 * L.rho * (L.v[0] * L.v[0] + L.v[1] * L.v[1] + L.v[2] * L.v[2]);
+  const double ER = R.P / (gamma - 1.0) + 0.5 * R.rho * (R.v[0] * R.v[0] + R.v[1] * R.v[1] + R.v[2] * R.v[2]);
+  const double UL[5] = {L.rho, L.rho * L.v[0], L.rho * L.v[1], L.rho * L.v[2], EL};
+  const double UR[5] = {R.rho, R.rho * R.v[0], R.rho * R.v[1], R.rho * R.v[2], ER};
+  for (int q = 0; q < 5; ++q) F[q] = (SR * FL[q] - SL * FR[q] + SL * SR * (UR[q] - UL[q])) / (SR - SL);
+}
+
 // Lab-frame flux across a face moving with velocity wt (Sec. 4 items 3-5):
-// boost both states into the face frame, solve, boost the flux back.
+// boost both states into the face frame, solve (HLLC, or HLL when riemann
+// is 1), boost the flux back.
 void moving_face_flux(const double UL[5], const double UR[5], const double n[3], const double wt[3],
-                      double gamma, double F[5]) {
+                      double gamma, int riemann, double F[5]) {
   Prim L = to_prim(UL, gamma), R = to_prim(UR, gamma);
   for (int a = 0; a < 3; ++a) {
     L.v[a] -= wt[a];
     R.v[a] -= wt[a];
   }
   double Ff[5];
-  hllc(L, R, n, gamma, Ff);
+  if (riemann == 1)
+    hll(L, R, n, gamma, Ff);
+  else
+    hllc(L, R, n, gamma, Ff);
   const double w2 = wt[0] * wt[0] + wt[1] * wt[1] + wt[2] * wt[2];
   F[0] = Ff[0];
   for (int a = 0; a < 3; ++a) F[1 + a] = Ff[1 + a] + wt[a] * Ff[0];
@@ -834,7 +867,7 @@ int fluxes(const Mesh& M, const Params& p, const double* Uh, const double* Gh, c
       FaceSetup S;
       hits += setup_face(M, p, i, e, Uh, Gh, w, S);
       double F[5];
-      moving_face_flux(S.UL, S.UR, S.n, S.wt, p.gamma, F);
+      moving_face_flux(S.UL, S.UR, S.n, S.wt, p.gamma, p.riemann, F);
       for (int q = 0; q < 5; ++q) phi[i][e][q] = dt * C.A[e] * F[q];
     }
   }
@@ -1121,10 +1154,17 @@ void orc_face_velocity(const double* ri, const double* rj_img, const double* wi,
 }
 
 // Lab-frame flux of conserved states UL, UR across a face with unit normal n
-// moving with velocity wt.
+// moving with velocity wt; riemann 0 is HLLC, 1 is HLL.
 void orc_moving_face_flux(const double* UL, const double* UR, const double* n, const double* wt, double gamma,
-                          double* F) {
-  moving_face_flux(UL, UR, n, wt, gamma, F);
+                          int32_t riemann, double* F) {
+  moving_face_flux(UL, UR, n, wt, gamma, riemann, F);
+}
+
+// HLL in the face frame on primitive states (rho, vx, vy, vz, P).
+void orc_hll_prim(const double* WL, const double* WR, const double* n, double gamma, double* F) {
+  Prim L{WL[0], {WL[1], WL[2], WL[3]}, WL[4]};
+  Prim R{WR[0], {WR[1], WR[2], WR[3]}, WR[4]};
+  hll(L, R, n, gamma, F);
 }
 
 // HLLC in the face frame on primitive states (rho, vx, vy, vz, P).

@@ -16,6 +16,7 @@ from dataclasses import dataclass
 from .build import LIB_PATH
 
 MM_FP64, MM_MIXED = 0, 1
+MM_HLLC, MM_HLL = 0, 1
 _STATUS = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_ECAPACITY", -4: "MM_EDEGENERATE",
            -5: "MM_ENONFINITE", -6: "MM_EHIP", -7: "MM_ESTATE", -8: "MM_EFULL"}
 N_STAGES = 8
@@ -213,6 +214,8 @@ def make_params(box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, precision="fp64", **kw) ->
             setattr(p, k, float(v))
         elif k in ("limit_mask", "predictor_frame"):
             setattr(p, k, int(v))
+        elif k == "riemann":
+            p.riemann = {"hllc": MM_HLLC, "hll": MM_HLL}.get(v, v) if isinstance(v, str) else int(v)
         else:
             raise TypeError(f"unknown parameter {k}")
     return p

@@ -105,12 +105,13 @@ __device__ inline void euler_flux(T rho, const T v[3], T P, const T n[3], T ig1,
 }
 
 // Flux across a face with unit normal n moving with velocity wt (Sec. 4,
-// items 3-5): both lab-frame states are boosted to the face frame, HLLC with
-// Davis wave-speed bounds gives the face-frame flux, and the flux is boosted
-// back (mass flux unchanged; momentum + wt F_rho; energy + wt.F_m +
+// items 3-5): both lab-frame states are boosted to the face frame, HLLC (or
+// HLL when hll is set) with Davis wave-speed bounds gives the face-frame
+// flux, and the flux is boosted back (mass flux unchanged; momentum + wt F_rho; energy + wt.F_m +
 // |wt|^2/2 F_rho).  The reciprocal densities are formed once per side.
 template <typename T>
-__device__ inline void moving_hllc(const T UL[5], const T UR[5], const T n[3], const T wt[3], T gamma, T F[5]) {
+__device__ inline void moving_flux(const T UL[5], const T UR[5], const T n[3], const T wt[3], T gamma, bool hll,
+                                   T F[5]) {
   const T g1 = gamma - T(1);
   const T ig1 = quot(T(1), g1);
   const T rL = UL[0], rR = UR[0];
@@ -138,6 +139,18 @@ __device__ inline void moving_hllc(const T UL[5], const T UR[5], const T n[3], c
     euler_flux(rL, vL, PL, n, ig1, Ff);
   } else if (SR < T(0)) {
     euler_flux(rR, vR, PR, n, ig1, Ff);
+  } else if (hll) {
+    // HLL: the one state between the bounding waves that conserves the
+    // integral over the fan, F = (SR FL - SL FR + SL SR (UR - UL)) / (SR - SL).
+    T FL[5], FR[5];
+    euler_flux(rL, vL, PL, n, ig1, FL);
+    euler_flux(rR, vR, PR, n, ig1, FR);
+    const T EL = PL * ig1 + T(0.5) * rL * (vL[0] * vL[0] + vL[1] * vL[1] + vL[2] * vL[2]);
+    const T ER = PR * ig1 + T(0.5) * rR * (vR[0] * vR[0] + vR[1] * vR[1] + vR[2] * vR[2]);
+    const T dU[5] = {rR - rL, rR * vR[0] - rL * vL[0], rR * vR[1] - rL * vL[1], rR * vR[2] - rL * vL[2], ER - EL};
+    const T iw = quot(T(1), SR - SL), sLR = SL * SR;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Ff[q] = (SR * FL[q] - SL * FR[q] + sLR * dU[q]) * iw;
   } else {
     const T Ss = quot(PR - PL + rL * uL * (SL - uL) - rR * uR * (SR - uR), rL * (SL - uL) - rR * (SR - uR));
     const bool left = Ss >= T(0);
@@ -442,6 +455,7 @@ __global__ __launch_bounds__(kThreads) void k_predict(const SegDesc* __restrict_
 struct FaceParams {
   double L[3];
   double theta, gamma, rho_floor, p_floor, dt;
+  bool hll;
 };
 
 __device__ inline FaceParams face_params(const SegDesc* segs, const SegStatus* dt_src, double dt_fixed, int seg) {
@@ -456,6 +470,7 @@ __device__ inline FaceParams face_params(const SegDesc* segs, const SegStatus* d
   P.gamma = hp.gamma;
   P.rho_floor = hp.rho_floor;
   P.p_floor = hp.p_floor;
+  P.hll = hp.riemann == kRiemannHll;
   P.dt = seg_dt(segs, dt_src, sg, dt_fixed);
   return P;
 }
@@ -514,7 +529,7 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
     hit += apply_floors(UR, g1, (R)hp.rho_floor, (R)hp.p_floor);
     if (hit) atomicAdd(&segst[seg].floor_hits[2], (unsigned long long)hit);
     R Fx[5];
-    moving_hllc(UL, UR, nrm, wt, (R)hp.gamma, Fx);
+    moving_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, Fx);
     const R scale = (R)(hp.dt * F.A);
 #pragma unroll
     for (int q = 0; q < 5; ++q) phi[5 * f + q] = scale * Fx[q];

@@ -65,6 +65,8 @@ GridParams make_grid(const mm_params& p, int64_t n, double rfac, int64_t base) {
   return g;
 }
 
+static_assert(MM_HLLC == kRiemannHllc && MM_HLL == kRiemannHll, "solver codes of the interface and the kernels");
+
 HydroParams hydro_params(const mm_params& p) {
   HydroParams h;
   for (int a = 0; a < 3; ++a) h.L[a] = p.box[a];
@@ -78,6 +80,8 @@ HydroParams hydro_params(const mm_params& p) {
   h.p_floor = p.p_floor;
   h.limit_mask = p.limit_mask;
   h.predictor_frame = p.predictor_frame;
+  h.riemann = p.riemann;
+  h.pad = 0;
   return h;
 }
 
@@ -89,7 +93,7 @@ bool params_ok(const mm_params* p, std::string& why) {
   if (!(p->zeta > 0.0)) { why = "zeta must be positive"; return false; }
   if (!(p->rho_floor > 0.0 && p->p_floor > 0.0)) { why = "floors must be positive"; return false; }
   if (p->precision != MM_FP64 && p->precision != MM_MIXED) { why = "precision must be MM_FP64 or MM_MIXED"; return false; }
-  if (p->riemann != MM_HLLC) { why = "riemann must be MM_HLLC"; return false; }
+  if (p->riemann != MM_HLLC && p->riemann != MM_HLL) { why = "riemann must be MM_HLLC or MM_HLL"; return false; }
   if (p->limit_mask < 0 || p->limit_mask > 3) { why = "limit_mask must be in 0..3"; return false; }
   if (p->predictor_frame != 0 && p->predictor_frame != 1) { why = "predictor_frame must be 0 or 1"; return false; }
   return true;

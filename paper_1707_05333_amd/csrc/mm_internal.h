@@ -75,11 +75,15 @@ struct GridParams {
 };
 
 // Scheme parameters as the kernels need them.
+constexpr int kRiemannHllc = 0, kRiemannHll = 1;
+
 struct HydroParams {
   double L[3];
   double gamma, cfl, eta, chi, zeta, theta, rho_floor, p_floor;
   int limit_mask;
   int predictor_frame;
+  int riemann;      // kRiemannHllc or kRiemannHll (the MM_HLLC / MM_HLL values)
+  int pad;
 };
 
 // One segment as the kernels see it.

@@ -254,3 +254,24 @@ def test_error_paths(orc):
     with pytest.raises(M.MMError) as e:
         small.tessellate(dev(W.jittered_lattice((4, 4, 4), (1, 1, 1), seed=1)))
     assert e.value.name == "MM_ECAPACITY"
+
+
+def test_step_parity_hll_sod_strip(orc):
+    # HLL face fluxes (Sec. 4 item 4) on the shock-tube strip.
+    wl = W.c2_sod(shape=(64, 8, 8), box=(4.0, 0.5, 0.5))
+    _print_case("step sod strip hll", n=wl.n, steps=5)
+    pg, Qg, wg, po, Qo, wo = _run_steps(orc, wl, 5, riemann=1)
+    assert scaled_err(Qg, Qo) < TOL
+    assert np.abs(pg - po).max() < TOL
+
+
+@pytest.mark.parametrize("riemann", [0, 1], ids=["hllc", "hll"])
+def test_step_parity_static_mesh_paper_sod(orc, riemann):
+    # The paper's Sod tube (16 x 1 x 1, rho_R = 0.25, P_R = 0.1795) on a
+    # static mesh (w = 0, Sec. 4.2): generators stay exactly in place.
+    wl = W.sod_paper(k=4, static_mesh=True, riemann=("hllc", "hll")[riemann])
+    _print_case("step paper sod static", n=wl.n, steps=5, riemann=riemann)
+    pg, Qg, wg, po, Qo, wo = _run_steps(orc, wl, 5)
+    assert scaled_err(Qg, Qo) < TOL
+    assert np.array_equal(pg, wl.pos) and np.array_equal(po, wl.pos)
+    assert not wg.any()

@@ -115,7 +115,84 @@ def test_hllc_matches_exact_godunov_flux_for_weak_waves(orc):
         assert np.abs(F - Fex).max() < 20 * eps * eps
 
 
-def test_moving_face_flux_is_galilean(orc):
+def _prim_state(rng):
+    return np.array([rng.uniform(0.1, 3), *rng.uniform(-2, 2, 3), rng.uniform(0.1, 3)])
+
+
+def test_hll_consistency_and_upwinding(orc):
+    # HLL (Sec. 4 item 4): equal states give the physical flux; when every
+    # wave moves one way the flux is that side's physical flux.
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        gamma = rng.uniform(1.1, 1.8)
+        W = _prim_state(rng)
+        n = rng.normal(size=3); n /= np.linalg.norm(n)
+        np.testing.assert_allclose(orc.hll_prim(W, W, n, gamma), phys_flux(cons(W, gamma), n, gamma),
+                                   rtol=1e-12, atol=1e-12)
+    gamma = 1.4
+    n = np.array([0.0, 1.0, 0.0])
+    WL = np.array([1.0, 0.1, 3.0, 0.0, 1.0])     # u - c > 0 on both sides
+    WR = np.array([0.5, -0.2, 2.5, 0.3, 0.4])
+    np.testing.assert_array_equal(orc.hll_prim(WL, WR, n, gamma), phys_flux(cons(WL, gamma), n, gamma))
+    WL[2], WR[2] = -3.0, -2.8                     # u + c < 0 on both sides
+    np.testing.assert_array_equal(orc.hll_prim(WL, WR, n, gamma), phys_flux(cons(WR, gamma), n, gamma))
+
+
+def test_hll_satisfies_jump_conditions_of_its_two_waves(orc):
+    # Toro 2009 sec. 10.3: the single HLL state U* is the average of the
+    # exact solution over the wave fan, from the integral form of the
+    # conservation law, and the flux obeys the Rankine-Hugoniot relation
+    # across each of the two bounding waves:
+    #   F* = F_L + S_L (U* - U_L) = F_R + S_R (U* - U_R).
+    rng = np.random.default_rng(12)
+    for _ in range(40):
+        gamma = rng.uniform(1.2, 1.7)
+        WL, WR = _prim_state(rng), _prim_state(rng)
+        WL[1:4] *= 0.2; WR[1:4] *= 0.2             # subsonic: S_L < 0 < S_R
+        n = rng.normal(size=3); n /= np.linalg.norm(n)
+        uL, uR = WL[1:4] @ n, WR[1:4] @ n
+        cL, cR = np.sqrt(gamma * WL[4] / WL[0]), np.sqrt(gamma * WR[4] / WR[0])
+        SL, SR = min(uL - cL, uR - cR), max(uL + cL, uR + cR)
+        assert SL < 0 < SR
+        UL, UR = cons(WL, gamma), cons(WR, gamma)
+        FL, FR = phys_flux(UL, n, gamma), phys_flux(UR, n, gamma)
+        Us = (SR * UR - SL * UL - (FR - FL)) / (SR - SL)
+        F = orc.hll_prim(WL, WR, n, gamma)
+        np.testing.assert_allclose(F, FL + SL * (Us - UL), rtol=1e-11, atol=1e-11)
+        np.testing.assert_allclose(F, FR + SR * (Us - UR), rtol=1e-11, atol=1e-11)
+
+
+def test_hll_diffuses_a_contact_that_hllc_keeps(orc):
+    # A stationary contact (equal pressure, no normal velocity, a density
+    # jump) is an exact steady solution.  HLLC, which restores the contact
+    # wave, carries no mass across it; HLL, which does not, carries
+    # -(s/2)(rho_R - rho_L) with s = max(c_L, c_R) (Davis bounds, S_L = -S_R).
+    gamma = 1.4
+    n = np.array([1.0, 0.0, 0.0])
+    WL = np.array([1.0, 0.0, 0.3, -0.1, 1.0])
+    WR = np.array([0.25, 0.0, 0.3, -0.1, 1.0])
+    s = max(np.sqrt(gamma * WL[4] / WL[0]), np.sqrt(gamma * WR[4] / WR[0]))
+    assert orc.hllc_prim(WL, WR, n, gamma)[0] == 0.0
+    Fh = orc.hll_prim(WL, WR, n, gamma)
+    assert abs(Fh[0] - (-0.5 * s * (WR[0] - WL[0]))) < 1e-14
+    assert abs(Fh[1] - WL[4]) < 1e-14               # pressure force is unchanged
+
+
+def test_hll_and_hllc_reverse_under_side_swap(orc):
+    # Seen from the other side (states swapped, normal reversed) both solvers
+    # give the same physical flux: every component changes sign.
+    rng = np.random.default_rng(13)
+    for _ in range(30):
+        gamma = rng.uniform(1.2, 1.7)
+        WL, WR = _prim_state(rng), _prim_state(rng)
+        n = rng.normal(size=3); n /= np.linalg.norm(n)
+        for solver in (orc.hll_prim, orc.hllc_prim):
+            np.testing.assert_allclose(solver(WR, WL, -n, gamma), -solver(WL, WR, n, gamma),
+                                       rtol=1e-11, atol=1e-11)
+
+
+@pytest.mark.parametrize("riemann", [0, 1])
+def test_moving_face_flux_is_galilean(orc, riemann):
     # For equal states the lab-frame flux through a face moving with wt is
     # F(U).n - (wt.n) U.
     rng = np.random.default_rng(3)
@@ -125,11 +202,12 @@ def test_moving_face_flux_is_galilean(orc):
         U = cons(Wp, gamma)
         n = rng.normal(size=3); n /= np.linalg.norm(n)
         wt = rng.uniform(-1, 1, 3)
-        F = orc.moving_face_flux(U, U, n, wt, gamma)
+        F = orc.moving_face_flux(U, U, n, wt, gamma, riemann)
         np.testing.assert_allclose(F, phys_flux(U, n, gamma) - (wt @ n) * U, rtol=1e-12, atol=1e-12)
 
 
-def test_moving_face_flux_boost_invariance(orc):
+@pytest.mark.parametrize("riemann", [0, 1])
+def test_moving_face_flux_boost_invariance(orc, riemann):
     # Boosting both states and the face by V0 changes the flux by the
     # Galilean transformation of mass, momentum and energy fluxes.
     rng = np.random.default_rng(4)
@@ -140,10 +218,10 @@ def test_moving_face_flux_boost_invariance(orc):
         n = rng.normal(size=3); n /= np.linalg.norm(n)
         wt = rng.uniform(-1, 1, 3)
         V0 = rng.uniform(-1, 1, 3)
-        F0 = orc.moving_face_flux(cons(WL, gamma), cons(WR, gamma), n, wt, gamma)
+        F0 = orc.moving_face_flux(cons(WL, gamma), cons(WR, gamma), n, wt, gamma, riemann)
         WLb, WRb = WL.copy(), WR.copy()
         WLb[1:4] += V0; WRb[1:4] += V0
-        F1 = orc.moving_face_flux(cons(WLb, gamma), cons(WRb, gamma), n, wt + V0, gamma)
+        F1 = orc.moving_face_flux(cons(WLb, gamma), cons(WRb, gamma), n, wt + V0, gamma, riemann)
         exp = np.concatenate([[F0[0]], F0[1:4] + V0 * F0[0], [F0[4] + V0 @ F0[1:4] + 0.5 * V0 @ V0 * F0[0]]])
         np.testing.assert_allclose(F1, exp, rtol=1e-11, atol=1e-11)
 

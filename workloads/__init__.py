@@ -218,6 +218,29 @@ def gresho(N=64, seed=6, gamma=5.0 / 3.0, jitter=0.25) -> Workload:
                     meta=dict(shape=(N, N, nz), t_end=2.0))
 
 
+def sod_paper(k=14, seed=7, jitter=0.25, riemann="hllc", static_mesh=False) -> Workload:
+    """The paper's Sod tube (Sec. 5, Sod shock-tube test): periodic box
+    16 x 1 x 1, left half rho = 1, P = 1, right half rho = 0.25,
+    P = 0.1795, v = 0, gamma = 1.4, run to t = 2.  Points: a 16k x k x k
+    lattice jittered by a quarter spacing (k = 14: 43,904 points; the paper
+    uses about 41K).  The box is shifted by half its length, so the central
+    discontinuity sits at x = 8 and the periodic one at x = 0.  riemann is
+    "hllc" or "hll" (stored as the solver code 0 or 1); a static mesh sets
+    the generator velocity to zero (eta = chi = 0)."""
+    box = (16.0, 1.0, 1.0)
+    pos = jittered_lattice((16 * k, k, k), box, jitter=jitter, seed=seed)
+    n = pos.shape[0]
+    prim = np.zeros((n, 5))
+    left = pos[:, 0] < 8.0
+    prim[:, 0] = np.where(left, 1.0, 0.25)
+    prim[:, 4] = np.where(left, 1.0, 0.1795)
+    over = dict(gamma=1.4, riemann={"hllc": 0, "hll": 1}[riemann])
+    if static_mesh:
+        over.update(eta=0.0, chi=0.0)
+    return Workload(f"sod_paper_{k}", pos, prim, box, _params(**over), steps=0,
+                    meta=dict(shape=(16 * k, k, k), t_end=2.0, left=(1.0, 0.0, 1.0), right=(0.25, 0.0, 0.1795)))
+
+
 def poisson_arrivals(n, rate, seed=4) -> np.ndarray:
     """Arrival times (seconds, non-decreasing, first at 0) of n requests of a
     Poisson stream with the given rate (requests per second)."""
