@@ -41,18 +41,21 @@ class Params(ctypes.Structure):
         ("predictor_frame", ctypes.c_int32),
         ("limit_mask", ctypes.c_int32),
         ("riemann", ctypes.c_int32),
+        ("half_step_mesh", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
 
 def make_params(box, gamma, cfl=0.3, eta=1.0, chi=1.0, zeta=0.25, theta=0.49,
                 rho_floor=1e-12, p_floor=1e-14, limiter_disp=0, predictor_frame=0,
-                limit_mask=3, riemann=0, **_ignored) -> Params:
+                limit_mask=3, riemann=0, half_step_mesh=0, **_ignored) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.gamma, p.cfl, p.eta, p.chi, p.zeta, p.theta = gamma, cfl, eta, chi, zeta, theta
     p.rho_floor, p.p_floor = rho_floor, p_floor
     p.limiter_disp, p.predictor_frame, p.limit_mask = limiter_disp, predictor_frame, limit_mask
     p.riemann = riemann
+    p.half_step_mesh = half_step_mesh
     return p
 
 

@@ -42,6 +42,12 @@
 //   R-w     the mesh velocity of a step is evaluated from the state at the
 //           start of the step and used both for the face velocities and
 //           the drift (Sec. 2 outline; Sec. 4.2).
+//   R-tess  optional half-step geometry (Sec. 6, first future improvement:
+//           rebuild the tessellation at the half step): the predictor runs
+//           on the time-n mesh; the generators are moved by w dt/2, the
+//           mesh is rebuilt there, and the second gradient, the face
+//           states and the fluxes use that mesh; the floors after the
+//           update use its volumes; the drift is still r^n + w dt.
 
 #include <algorithm>
 #include <array>
@@ -484,6 +490,8 @@ struct Params {
   int32_t predictor_frame;  // 0: moving generator (R-pred); 1: Eulerian
   int32_t limit_mask;       // S10 limiter on: bit 0 time-n gradient, bit 1 half-step gradient (default 3)
   int32_t riemann;          // 0: HLLC (the paper's default), 1: HLL (Sec. 4 item 4)
+  int32_t half_step_mesh;   // 1: fluxes on the mesh of the half-step positions (R-tess)
+  int32_t pad;
 };
 
 // R-floor (Sec. 4.1, floors paragraph).  U = (rho, m, E) densities.
@@ -1112,13 +1120,33 @@ int32_t orc_step(int64_t n, double* pos, double* Q, double* w_out, const orc_par
   dt = std::min(dt, dt_max);
   orc_gradient(mh, p, U.data(), G.data(), p->limit_mask & 1);
   orc_predict(mh, p, U.data(), G.data(), w_out, dt, Uh.data(), 0, &c1);
-  orc_gradient(mh, p, Uh.data(), Gh.data(), (p->limit_mask >> 1) & 1);
-  const int rc = fluxes(*M, *p, Uh.data(), Gh.data(), w_out, dt, dQ.data(), &c2);
-  if (rc) { delete M; return rc; }
+  // R-tess: the second half of the step works on the mesh of the generators
+  // moved to the half step.
+  Mesh* F = M;
+  if (p->half_step_mesh) {
+    std::vector<double> ph(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        double x = pos[3 * i + a] + w_out[3 * i + a] * (0.5 * dt);
+        if (x < 0) x += p->box[a];
+        if (x >= p->box[a]) x -= p->box[a];
+        ph[3 * i + a] = x;
+      }
+    F = (Mesh*)orc_mesh_build(n, ph.data(), p->box, method, 0, 0);
+    if (F->status) { delete F; delete M; return 1; }
+  }
+  orc_gradient(F, p, Uh.data(), Gh.data(), (p->limit_mask >> 1) & 1);
+  const int rc = fluxes(*F, *p, Uh.data(), Gh.data(), w_out, dt, dQ.data(), &c2);
+  if (rc) {
+    if (F != M) delete F;
+    delete M;
+    return rc;
+  }
   for (int64_t i = 0; i < n; ++i) {
     for (int q = 0; q < 5; ++q) Q[5 * i + q] += dQ[5 * i + q];
-    // Floors at the cell centre after the step, with the time-n volume.
-    const double V = M->cells[i].V;
+    // Floors at the cell centre after the step, with the volume of the mesh
+    // the fluxes used (time n, or the half step under R-tess).
+    const double V = F->cells[i].V;
     double Ui[5];
     for (int q = 0; q < 5; ++q) Ui[q] = Q[5 * i + q] / V;
     if (apply_floors(Ui, *p)) {
@@ -1140,6 +1168,7 @@ int32_t orc_step(int64_t n, double* pos, double* Q, double* w_out, const orc_par
     counters[2] = c2;
     counters[3] = c3;
   }
+  if (F != M) delete F;
   delete M;
   return 0;
 }
