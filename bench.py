@@ -20,6 +20,8 @@ Also reported on the same line:
                tangential speed and its rate of convergence;
   sod_paper    the paper's Sod tube to t = 2, moving and static mesh, HLLC and
                HLL: L1 of density against the exact solution, oscillations;
+  half_step    start-of-step against half-step geometry: Gresho vortex
+               accuracy, angular momentum and cost; free-stream error order;
   serving      a Poisson stream of Kelvin-Helmholtz simulations (1e3..2e5
                points each, 20 steps, mixed) through the batch serving loop
                under an explicit device budget: throughput, p50/p99 step
@@ -64,6 +66,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving object")
     ap.add_argument("--no-gresho", action="store_true", help="skip the Gresho-Chan convergence object")
     ap.add_argument("--no-sod-paper", action="store_true", help="skip the paper's Sod tube object")
+    ap.add_argument("--no-half-step", action="store_true", help="skip the half-step mesh object")
     ap.add_argument("--mixed-steps", type=int, default=100)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -226,6 +229,64 @@ def gresho_object(M, torch, args):
     l1 = [r["l1_vphi"] for r in out["runs"]]
     out["l1_slope"] = math.log(l1[0] / l1[-1]) / math.log(4.0)
     out["paper_slope"] = 0.88
+    return out
+
+
+def half_step_object(M, torch, args):
+    """Start-of-step against half-step geometry: the Gresho vortex (64^2,
+    t = 2; L1 of the tangential speed, relative change of the angular
+    momentum about the vortex axis, time per step) and the free-stream
+    density error of a uniform flow on a drifting 24^3 mesh at CFL 0.4 and
+    0.1 (its ratio shows the order in time)."""
+    import numpy as np
+    import workloads as W
+    out = {"workload": "gresho_64_t2 + free_stream_24^3", "precision": "fp64", "gresho": [], "free_stream": []}
+    wl = W.gresho(64)
+    for half in (0, 1):
+        mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, half_step_mesh=half, **wl.params))
+        pos = torch.from_numpy(wl.pos.copy()).cuda()
+        mm.tessellate(pos)
+        Q = mm.init_charges(torch.from_numpy(wl.prim.copy()).cuda())
+        w = torch.empty_like(pos)
+
+        def lz():
+            x, q = pos.cpu().numpy(), Q.cpu().numpy()
+            return float(np.sum((x[:, 0] - 0.5) * q[:, 2] - (x[:, 1] - 0.5) * q[:, 1]))
+        L0 = lz()
+        t, steps = 0.0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while t < 2.0 * (1 - 1e-12):
+            t += mm.step(pos, w, Q, dt_max=2.0 - t)["dt"]
+            steps += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        x, q = pos.cpu().numpy(), Q.cpu().numpy()
+        dx, dy = x[:, 0] - 0.5, x[:, 1] - 0.5
+        r = np.hypot(dx, dy)
+        v = q[:, 1:3] / q[:, :1]
+        l1 = float(np.mean(np.abs((-dy * v[:, 0] + dx * v[:, 1]) / r - W.gresho_profile(r)[1])))
+        out["gresho"].append({"half_step_mesh": half, "steps": steps, "l1_vphi": l1,
+                              "dLz_rel": (lz() - L0) / L0, "ms_per_step": 1e3 * wall / steps})
+        mm.close()
+        log(f"half-step {half}: gresho L1 {l1:.4e}, dLz {out['gresho'][-1]['dLz_rel']:.3e}")
+    fpos = W.jittered_lattice((24, 24, 24), (1, 1, 1), jitter=0.2, seed=3)
+    fw = W.uniform_state(fpos, (1, 1, 1), rho=1.3, vel=(0.4, -0.2, 0.1), P=0.7)
+    for half in (0, 1):
+        for cfl in (0.4, 0.1):
+            mm = M.MovingMesh(fw.n, M.make_params(box=fw.box, half_step_mesh=half, **dict(fw.params, cfl=cfl)))
+            pos = torch.from_numpy(fw.pos.copy()).cuda()
+            mm.tessellate(pos)
+            Q = mm.init_charges(torch.from_numpy(fw.prim.copy()).cuda())
+            w = torch.empty_like(pos)
+            t = 0.0
+            while t < 0.05 * (1 - 1e-12):
+                t += mm.step(pos, w, Q, dt_max=0.05 - t)["dt"]
+            mm.tessellate(pos)
+            V = mm.mesh_export().V.cpu().numpy()
+            err = float(np.abs(Q[:, 0].cpu().numpy() / V - 1.3).max())
+            out["free_stream"].append({"half_step_mesh": half, "cfl": cfl, "max_density_error": err})
+            mm.close()
     return out
 
 
@@ -448,6 +509,8 @@ def main():
         out["gresho"] = gresho_object(M, torch, args)
     if not args.no_sod_paper:
         out["sod_paper"] = sod_paper_object(M, torch, args)
+    if not args.no_half_step:
+        out["half_step"] = half_step_object(M, torch, args)
     if not args.no_serve:
         out["serving"] = serving_object(M, torch, args)
         log(f"serving: {out['serving']['value']:.3e} cell-updates/s, p50 {out['serving']['step_latency_p50_ms']:.2f} ms"

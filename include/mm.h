@@ -84,6 +84,12 @@ typedef struct {
   int32_t riemann;           /* MM_HLLC or MM_HLL */
   int32_t limit_mask;        /* S10 limiter: bit 0 on the time-n gradient, bit 1 on the half-step one */
   int32_t predictor_frame;   /* 0: rate following the generator, -div F + w . grad U; 1: Eulerian -div F */
+  int32_t half_step_mesh;    /* 1: the second gradient, the face states and the fluxes use a mesh rebuilt
+                                at the half-step positions r + w dt/2 (the paper's first future
+                                improvement, Sec. 6), at the cost of a second tessellation per step;
+                                0 (default): the mesh of the start of the step, as in the paper's runs.
+                                Single simulations only (mm_batch_admit rejects 1). */
+  int32_t reserved;          /* must be 0 */
 } mm_params;
 
 /* Per-step report, filled by mm_step (and partly by mm_tessellate). */
@@ -205,8 +211,10 @@ const char *mm_version(void);
 /* Stage timing of mm_step, for profiling.  When enabled, mm_step records HIP
  * events on the context stream around its stages: [0] sort, [1] cell
  * construction, [2] mesh assembly, [3] cell states, [4] gradient + predictor,
- * [5] half-step gradient, [6] face fluxes, [7] update + drift.
- * mm_get_stage_ms writes up to n_stages milliseconds of the last step. */
+ * [5] half-step gradient, [6] face fluxes, [7] update + drift, [8] the
+ * rebuild of the mesh at the half step (half_step_mesh = 1; else 0).
+ * mm_get_stage_ms writes up to n_stages (at most 9) milliseconds of the last
+ * step. */
 mm_status mm_set_stage_timing(mm_ctx *ctx, int32_t enable);
 mm_status mm_get_stage_ms(const mm_ctx *ctx, double *ms, int32_t n_stages);
 

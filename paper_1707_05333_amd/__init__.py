@@ -19,8 +19,8 @@ MM_FP64, MM_MIXED = 0, 1
 MM_HLLC, MM_HLL = 0, 1
 _STATUS = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ENOMEM", -3: "MM_ECAPACITY", -4: "MM_EDEGENERATE",
            -5: "MM_ENONFINITE", -6: "MM_EHIP", -7: "MM_ESTATE", -8: "MM_EFULL"}
-N_STAGES = 8
-STAGE_NAMES = ("sort", "cells", "mesh", "cell_state", "gradient_predict", "gradient_half", "flux", "update")
+N_STAGES = 9
+STAGE_NAMES = ("sort", "cells", "mesh", "cell_state", "gradient_predict", "gradient_half", "flux", "update", "remesh")
 
 
 class MMError(RuntimeError):
@@ -45,6 +45,8 @@ class Params(ctypes.Structure):
         ("riemann", ctypes.c_int32),
         ("limit_mask", ctypes.c_int32),
         ("predictor_frame", ctypes.c_int32),
+        ("half_step_mesh", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -212,7 +214,7 @@ def make_params(box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, precision="fp64", **kw) ->
     for k, v in kw.items():
         if k in ("cfl", "eta", "chi", "zeta", "theta", "rho_floor", "p_floor"):
             setattr(p, k, float(v))
-        elif k in ("limit_mask", "predictor_frame"):
+        elif k in ("limit_mask", "predictor_frame", "half_step_mesh"):
             setattr(p, k, int(v))
         elif k == "riemann":
             p.riemann = {"hllc": MM_HLLC, "hll": MM_HLL}.get(v, v) if isinstance(v, str) else int(v)

@@ -585,7 +585,8 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
                                                      const double* __restrict__ Qs, double* __restrict__ Qc,
                                                      const double* __restrict__ spos, const double* __restrict__ w,
                                                      double* __restrict__ posc, double* __restrict__ wc,
-                                                     const SegStatus* dt_src, DevStatus* st, SegStatus* segst) {
+                                                     const SegStatus* dt_src, DevStatus* st, SegStatus* segst,
+                                                     bool drift_from_slots) {
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int seg = sseg[s];
@@ -611,12 +612,13 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
     Qc[5 * c + q] = Q[q];
     if (!isfinite(Q[q])) bad = 1;
   }
-  // Drift by the full step with periodic wrap.
+  // Drift by the full step with periodic wrap, from the start-of-step
+  // position (the caller's slot when the mesh is a half-step one).
   const double dt = seg_dt(segs, dt_src, seg, 0.0);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double wa = w[3 * s + a];
-    double x = spos[3 * s + a] + wa * dt;
+    double x = (drift_from_slots ? posc[3 * c + a] : spos[3 * s + a]) + wa * dt;
     if (x < 0.0) x += hp.L[a];
     if (x >= hp.L[a]) x -= hp.L[a];
     posc[3 * c + a] = x;
@@ -739,10 +741,71 @@ void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const un
                    const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo,
                    const int32_t* perm, const double* Qs, double* Q_slots, const double* spos, const double* w,
                    double* pos_slots, double* w_slots, const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst,
-                   hipStream_t st) {
+                   hipStream_t st, bool drift_from_slots) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_update<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, counts, soff,
-                     csr, phi, geo, perm, Qs, Q_slots, spos, w, pos_slots, w_slots, dt_src, st_dev, segst);
+                     csr, phi, geo, perm, Qs, Q_slots, spos, w, pos_slots, w_slots, dt_src, st_dev, segst,
+                     drift_from_slots);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_half_park(const SegDesc* __restrict__ segs,
+                                                        const int32_t* __restrict__ sseg, int64_t n,
+                                                        const int32_t* __restrict__ perm, const R* __restrict__ Uh,
+                                                        const double* __restrict__ w, const SegStatus* dt_src,
+                                                        const double* __restrict__ posc, double* __restrict__ pos_half,
+                                                        R* __restrict__ Uhc, double* __restrict__ wc) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int seg = sseg[s];
+  const HydroParams& hp = segs[seg].hp;
+  const double hdt = 0.5 * seg_dt(segs, dt_src, seg, 0.0);
+  const int64_t c = perm[s];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) Uhc[5 * c + q] = Uh[5 * s + q];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double wa = w[3 * s + a];
+    wc[3 * c + a] = wa;
+    double x = posc[3 * c + a] + wa * hdt;
+    if (x < 0.0) x += hp.L[a];
+    if (x >= hp.L[a]) x -= hp.L[a];
+    pos_half[3 * c + a] = x;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_half_unpark(int64_t n, const int32_t* __restrict__ perm,
+                                                          const R* __restrict__ Uhc, const double* __restrict__ wc,
+                                                          const double* __restrict__ Qc, R* __restrict__ Uh,
+                                                          double* __restrict__ w, double* __restrict__ Qs) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int64_t c = perm[s];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    Uh[5 * s + q] = Uhc[5 * c + q];
+    Qs[5 * s + q] = Qc[5 * c + q];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) w[3 * s + a] = wc[3 * c + a];
+}
+
+template <typename R>
+void launch_half_park(const SegDesc* segs, const int32_t* sseg, int64_t n, const int32_t* perm, const R* Uh,
+                      const double* w, const SegStatus* dt_src, const double* pos_slots, double* pos_half,
+                      R* Uh_slots, double* w_slots, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_half_park<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, perm, Uh,
+                     w, dt_src, pos_slots, pos_half, Uh_slots, w_slots);
+}
+
+template <typename R>
+void launch_half_unpark(int64_t n, const int32_t* perm, const R* Uh_slots, const double* w_slots,
+                        const double* Q_slots, R* Uh, double* w, double* Qs, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_half_unpark<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, perm, Uh_slots,
+                     w_slots, Q_slots, Uh, w, Qs);
 }
 
 template <typename R>
@@ -796,7 +859,12 @@ void launch_copy_rows(const double* src, double* dst, int64_t n, int width, hipS
   template void launch_update<R>(const SegDesc*, const int32_t*, int64_t, const unsigned long long*,              \
                                  const unsigned long long*, const int32_t*, const R*, const double*,              \
                                  const int32_t*, const double*, double*, const double*, const double*, double*,   \
-                                 double*, const SegStatus*, DevStatus*, SegStatus*, hipStream_t);                 \
+                                 double*, const SegStatus*, DevStatus*, SegStatus*, hipStream_t, bool);           \
+  template void launch_half_park<R>(const SegDesc*, const int32_t*, int64_t, const int32_t*, const R*,            \
+                                    const double*, const SegStatus*, const double*, double*, R*, double*,         \
+                                    hipStream_t);                                                                 \
+  template void launch_half_unpark<R>(int64_t, const int32_t*, const R*, const double*, const double*, R*,         \
+                                      double*, double*, hipStream_t);                                             \
   template void launch_accumulate<R>(int64_t, const unsigned long long*, const unsigned long long*,               \
                                      const int32_t*, const R*, const int32_t*, double*, hipStream_t);             \
   template void launch_gather_rows<R>(const R*, const int32_t*, int64_t, int, R*, hipStream_t);                   \

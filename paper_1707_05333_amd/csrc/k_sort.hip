@@ -245,6 +245,19 @@ void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, v, n);
 }
 
+__global__ void k_remesh_reset(DevStatus* s) {
+  if (threadIdx.x == 0) {
+    s->n_deferred = 0;
+    s->n_overflow = 0;
+    s->n_faces = 0;
+    s->n_csr = 0;
+  }
+}
+
+void launch_remesh_reset(DevStatus* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_remesh_reset, dim3(1), dim3(64), 0, st, s);
+}
+
 void launch_status_reset(DevStatus* s, SegStatus* segst, int nseg, hipStream_t st) {
   hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(256), 0, st, s, segst, nseg);
 }

@@ -49,6 +49,11 @@ struct Engine {
   // State in internal order.
   void *U = nullptr, *G = nullptr, *Uh = nullptr, *rec = nullptr, *phi = nullptr;   // rec: FluxCell<R>[n]
   double *w = nullptr, *Qs = nullptr;
+  // Half-step mesh (single simulations): positions r + w dt/2 and the
+  // half-step states and mesh velocities parked in slot order while the
+  // mesh is rebuilt.  Reserved only when init is asked for them.
+  double* pos_half = nullptr;
+  void* Uh_slots = nullptr;
   // Segment table and status.
   SegDesc* segs = nullptr;
   SegStatus* segst = nullptr;
@@ -63,12 +68,14 @@ struct Engine {
   double rfac = 2.0;   // first-pass candidate radius in mean spacings (adapted per call)
   // Stage timing.
   bool timing = false;
-  hipEvent_t ev[9] = {};
-  double stage_ms[8] = {};
+  hipEvent_t ev[11] = {};   // 0-8 the step's stages, 9-10 around the half-step remesh
+  double stage_ms[9] = {};  // sort, cells, mesh, cell_state, gradient_predict, gradient_half, flux, update, remesh
+  bool remeshed = false;
   std::string err;
 
   // Reserves everything; returns MM_OK or MM_ENOMEM / MM_EHIP with err set.
-  mm_status init(int precision, int64_t ncap, int64_t slot_cap, int64_t fcap, int segcap, hipStream_t stream);
+  mm_status init(int precision, int64_t ncap, int64_t slot_cap, int64_t fcap, int segcap, hipStream_t stream,
+                 bool half_step_buffers = false);
   void release();
 
   // Host staging of the segment table, safe to write once returned; then
@@ -82,8 +89,11 @@ struct Engine {
   // One whole step: tessellation, charges of fresh segments, states, two
   // gradients with the predictor, fluxes, update and drift.  Q, pos and w
   // are slot-order arrays, updated in place.
+  // half_step: rebuild the mesh at r + w dt/2 after the predictor and take
+  // the second gradient, the fluxes and the update on it (single segment,
+  // n_slots == n, buffers reserved at init).
   void enqueue_step(double* pos, double* w, double* Q, int64_t n_slots, const int32_t* slot_seg, int64_t n,
-                    int64_t nbt, bool any_fresh);
+                    int64_t nbt, bool any_fresh, bool half_step = false);
   // Waits for the stream and copies the status of the launch set and of
   // the first nseg segments to the host mirrors.
   mm_status readback();

@@ -96,6 +96,8 @@ bool params_ok(const mm_params* p, std::string& why) {
   if (p->riemann != MM_HLLC && p->riemann != MM_HLL) { why = "riemann must be MM_HLLC or MM_HLL"; return false; }
   if (p->limit_mask < 0 || p->limit_mask > 3) { why = "limit_mask must be in 0..3"; return false; }
   if (p->predictor_frame != 0 && p->predictor_frame != 1) { why = "predictor_frame must be 0 or 1"; return false; }
+  if (p->half_step_mesh != 0 && p->half_step_mesh != 1) { why = "half_step_mesh must be 0 or 1"; return false; }
+  if (p->reserved != 0) { why = "reserved must be 0"; return false; }
   return true;
 }
 
@@ -106,7 +108,8 @@ double dt_from_bits(unsigned long long bits) {
   return d;
 }
 
-mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, int seg_cap, hipStream_t s) {
+mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, int seg_cap, hipStream_t s,
+                       bool half_step_buffers) {
   precision = prec;
   ncap = n_cap;
   slot_cap = s_cap;
@@ -148,6 +151,10 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
   ok &= hipMalloc(&phi, std::max<size_t>(5 * F * rs, 1)) == hipSuccess;
   ok &= dalloc(&w, 3 * N) == hipSuccess;
   ok &= dalloc(&Qs, 5 * N) == hipSuccess;
+  if (half_step_buffers) {
+    ok &= dalloc(&pos_half, 3 * slot_cap) == hipSuccess;
+    ok &= hipMalloc(&Uh_slots, std::max<size_t>(5 * slot_cap * rs, 1)) == hipSuccess;
+  }
   ok &= dalloc(&segs, segcap) == hipSuccess;
   ok &= dalloc(&segst, segcap) == hipSuccess;
   ok &= dalloc(&st, 1) == hipSuccess;
@@ -169,7 +176,8 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
 
 void Engine::release() {
   void* ptrs[] = {key, perm, sseg, deferred, spos, geo, rmax2, minv, bcount, boff, scan_tmp, counts, off, sw, soff,
-                  stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, segs, segst, st};
+                  stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, pos_half, Uh_slots,
+                  segs, segst, st};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   void* hptrs[] = {segs_host, segst_host, st_host};
@@ -217,7 +225,8 @@ void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int3
 namespace {
 
 template <typename R>
-void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n, bool any_fresh) {
+void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n, bool any_fresh, bool half,
+                   int64_t nbt) {
   const unsigned long long* nf_dev = &E.st->n_faces;
   R *U = (R*)E.U, *Uh = (R*)E.Uh, *phi = (R*)E.phi;
   FluxCell<R>* rec = (FluxCell<R>*)E.rec;
@@ -226,6 +235,18 @@ void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n
   E.mark(4);
   launch_gradient<R>(E.segs, E.sseg, n, U, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv, kLimitMaskBit0, nullptr, E.w, E.segst,
                      0.0, Uh, nullptr, nullptr, nullptr, E.segst, E.stream);
+  if (half) {
+    // Half-step geometry: park U_half and w in slot order, move the
+    // generators by w dt/2, rebuild the mesh there and bring the parked
+    // values (and the charges) into its cell order.
+    if (E.timing) (void)hipEventRecord(E.ev[9], E.stream);
+    launch_half_park<R>(E.segs, E.sseg, n, E.perm, Uh, E.w, E.segst, pos, E.pos_half, (R*)E.Uh_slots, w_slots,
+                        E.stream);
+    launch_remesh_reset(E.st, E.stream);
+    E.enqueue_tessellation(E.pos_half, n, nullptr, n, nbt);
+    launch_half_unpark<R>(n, E.perm, (const R*)E.Uh_slots, w_slots, Q, Uh, E.w, E.Qs, E.stream);
+    if (E.timing) (void)hipEventRecord(E.ev[10], E.stream);
+  }
   E.mark(5);
   launch_gradient<R>(E.segs, E.sseg, n, Uh, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv, kLimitMaskBit1, nullptr, E.w, nullptr,
                      0.0, nullptr, rec, E.geo, E.spos, E.segst, E.stream);
@@ -233,18 +254,20 @@ void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n
   launch_flux<R>(E.segs, E.fcap, nf_dev, E.faces, rec, E.segst, 0.0, phi, E.segst, E.stream);
   E.mark(7);
   launch_update<R>(E.segs, E.sseg, n, E.counts, E.soff, E.csr, phi, E.geo, E.perm, E.Qs, Q, E.spos, E.w, pos, w_slots, E.segst,
-                   E.st, E.segst, E.stream);
+                   E.st, E.segst, E.stream, half);
 }
 
 }  // namespace
 
 void Engine::enqueue_step(double* pos, double* w_slots, double* Q, int64_t n_slots, const int32_t* slot_seg,
-                          int64_t n_cells, int64_t n_buckets, bool any_fresh) {
+                          int64_t n_cells, int64_t n_buckets, bool any_fresh, bool half_step) {
+  const bool half = half_step && pos_half && Uh_slots && n_slots == n_cells && !slot_seg;
+  remeshed = half;
   reset_status();
   enqueue_tessellation(pos, n_slots, slot_seg, n_cells, n_buckets);
   mark(3);
-  if (precision == MM_MIXED) enqueue_hydro<float>(*this, pos, w_slots, Q, n_cells, any_fresh);
-  else enqueue_hydro<double>(*this, pos, w_slots, Q, n_cells, any_fresh);
+  if (precision == MM_MIXED) enqueue_hydro<float>(*this, pos, w_slots, Q, n_cells, any_fresh, half, n_buckets);
+  else enqueue_hydro<double>(*this, pos, w_slots, Q, n_cells, any_fresh, half, n_buckets);
   mark(8);
 }
 
@@ -265,6 +288,14 @@ void Engine::finish_timing() {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
     stage_ms[k] = ms;
+  }
+  stage_ms[8] = 0.0;
+  if (remeshed) {
+    // The remesh runs inside the predictor stage's events: report it apart.
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[9], ev[10]);
+    stage_ms[8] = ms;
+    stage_ms[4] -= ms;
   }
 }
 

@@ -200,6 +200,10 @@ void scan_u64(const unsigned long long* in, unsigned long long* out, int64_t n, 
 
 void launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t st);
 void launch_status_reset(DevStatus* s, SegStatus* segst, int nseg, hipStream_t st);
+// Clears the per-mesh counters (deferred and overflowing cells, face and
+// list totals) before a second tessellation in one step; failure flags, the
+// timestep minimum and the floor counts are kept.
+void launch_remesh_reset(DevStatus* s, hipStream_t st);
 
 // Bucket sort of the generators of every segment (grid hash, counting sort,
 // caller order inside a bucket).  pos covers n_slots slots; slot_seg[q] is
@@ -267,7 +271,18 @@ template <typename R>
 void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* counts,
                    const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo, const int32_t* perm, const double* Qs,
                    double* Q_slots, const double* spos, const double* w, double* pos_slots, double* w_slots,
-                   const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
+                   const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st,
+                   bool drift_from_slots = false);
+// Half-step mesh: U_half and w of internal cell s go to slot perm[s], and
+// pos_half[slot] = wrap(pos[slot] + w dt/2) (single segment, slots = cells).
+template <typename R>
+void launch_half_park(const SegDesc* segs, const int32_t* sseg, int64_t n, const int32_t* perm, const R* Uh,
+                      const double* w, const SegStatus* dt_src, const double* pos_slots, double* pos_half,
+                      R* Uh_slots, double* w_slots, hipStream_t st);
+// ... and back into the cell order of the rebuilt mesh, with the charges.
+template <typename R>
+void launch_half_unpark(int64_t n, const int32_t* perm, const R* Uh_slots, const double* w_slots,
+                        const double* Q_slots, R* Uh, double* w, double* Qs, hipStream_t st);
 template <typename R>
 void launch_accumulate(int64_t n, const unsigned long long* counts, const unsigned long long* soff, const int32_t* csr,
                        const R* phi,

@@ -153,7 +153,7 @@ mm_status mm_create(mm_ctx** out, const mm_params* p, int64_t n_capacity, int64_
   if (!c) return create_fail(MM_ENOMEM, "host allocation failed");
   c->p = *p;
   const int64_t fcap = face_capacity ? face_capacity : kFacesPerCell * n_capacity;
-  if (mm_status r = c->E.init(p->precision, n_capacity, n_capacity, fcap, 1, (hipStream_t)hip_stream)) {
+  if (mm_status r = c->E.init(p->precision, n_capacity, n_capacity, fcap, 1, (hipStream_t)hip_stream, true)) {
     const std::string msg = c->E.err;
     delete c;
     return create_fail(r, msg);
@@ -339,7 +339,7 @@ mm_status mm_step(mm_ctx* c, int64_t n, double* pos, double* w, double* Q, doubl
   c->grid = make_grid(c->p, n, c->E.rfac, 0);
   if (mm_status r = put_segment(c, dt_max)) return r;
   c->E.n = n;
-  c->E.enqueue_step(pos, w, Q, n, nullptr, n, c->grid.nbt, false);
+  c->E.enqueue_step(pos, w, Q, n, nullptr, n, c->grid.nbt, false, c->p.half_step_mesh != 0);
   if (mm_status r = readback(c)) return r;
   fill_info(c, info, dt_max);
   c->E.finish_timing();
@@ -356,7 +356,7 @@ mm_status mm_set_stage_timing(mm_ctx* c, int32_t enable) {
 
 mm_status mm_get_stage_ms(const mm_ctx* c, double* ms, int32_t n_stages) {
   if (!c || !ms || n_stages < 0) return MM_EINVAL;
-  for (int k = 0; k < std::min(n_stages, 8); ++k) ms[k] = c->E.stage_ms[k];
+  for (int k = 0; k < std::min(n_stages, 9); ++k) ms[k] = c->E.stage_ms[k];
   return MM_OK;
 }
 

@@ -275,3 +275,16 @@ def test_step_parity_static_mesh_paper_sod(orc, riemann):
     assert scaled_err(Qg, Qo) < TOL
     assert np.array_equal(pg, wl.pos) and np.array_equal(po, wl.pos)
     assert not wg.any()
+
+
+@pytest.mark.parametrize("name", ["gresho_16", "sod_strip"])
+def test_step_parity_half_step_mesh(orc, name):
+    # Fluxes on the mesh rebuilt at the half-step positions (the paper's
+    # first future improvement, Sec. 6): rotating and shocked flows, so the
+    # half-step mesh differs from the start-of-step one.
+    wl = W.gresho(16) if name == "gresho_16" else W.c2_sod(shape=(64, 8, 8), box=(4.0, 0.5, 0.5))
+    _print_case("step half-step mesh", name=name, n=wl.n, steps=4)
+    pg, Qg, wg, po, Qo, wo = _run_steps(orc, wl, 4, half_step_mesh=1)
+    assert scaled_err(Qg, Qo) < TOL
+    assert np.abs(pg - po).max() < TOL
+    assert scaled_err(wg, wo) < TOL
