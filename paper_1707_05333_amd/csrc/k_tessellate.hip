@@ -58,6 +58,7 @@ struct __align__(16) TessLds {
   int32_t pcand[kPlanes];              // neighbour of each plane slot (j << 5 | image code); -1 - k for box plane k
   uint8_t E[kPlanes * kPlanes];
   uint16_t elist[kVerts];              // boundary edges of one cut: x | y << 8
+  uint8_t kept[kVerts];                // 1 for a live vertex slot that survives the current cut
 };
 
 struct TessArgs {
@@ -229,12 +230,24 @@ struct StencilBucket {
   double sx, sy, sz;
 };
 
+// Division by the stencil width W: q = umulhi(o, m) with m = 2^32 / W
+// rounded up is exact for o * W < 2^32, which holds for every o < W^3 when
+// W < 256 (the quotient's error o (m W - 2^32) / 2^32 stays below 1 / W).
+struct WidthDiv {
+  unsigned W, m;
+};
+__device__ inline WidthDiv width_div(unsigned W) { return WidthDiv{W, 0xffffffffu / W + 1u}; }
+__device__ inline unsigned div_width(unsigned o, const WidthDiv& d) {
+  return d.W < 256u ? __umulhi(o, d.m) : o / d.W;
+}
+
 __device__ inline StencilBucket stencil_bucket(const TessArgs& A, const GridParams& g, const int b[3], int ring,
-                                               int o, int W3) {
+                                               int o, int W3, const WidthDiv& D) {
   StencilBucket B{0, 0, 13, 0.0, 0.0, 0.0};
   if (o < W3) {
-    const int W = 2 * ring + 1;
-    const int oo[3] = {o % W - ring, (o / W) % W - ring, o / (W * W) - ring};
+    const unsigned W = D.W;
+    const unsigned q1 = div_width((unsigned)o, D), q2 = div_width(q1, D);
+    const int oo[3] = {(int)((unsigned)o - q1 * W) - ring, (int)(q1 - q2 * W) - ring, (int)q2 - ring};
     int kk[3], bb[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -263,11 +276,12 @@ __device__ inline StencilBucket stencil_bucket(const TessArgs& A, const GridPara
 __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const int s, const double r[3],
                       const int b[3], const int ring, const double lo2, const double hi2) {
   const int W = 2 * ring + 1, W3 = W * W * W;
+  const WidthDiv D = width_div((unsigned)W);
   const int lane = __lane_id();
   int nc = 0;
   for (int chunk = 0; chunk < W3; chunk += 128) {
-    const StencilBucket B0 = stencil_bucket(A, g, b, ring, chunk + lane, W3);
-    const StencilBucket B1 = stencil_bucket(A, g, b, ring, chunk + 64 + lane, W3);
+    const StencilBucket B0 = stencil_bucket(A, g, b, ring, chunk + lane, W3, D);
+    const StencilBucket B1 = stencil_bucket(A, g, b, ring, chunk + 64 + lane, W3, D);
     const int maxc = (int)wave_umax32((unsigned)max(B0.cnt, B1.cnt));
     for (int k = 0; k < maxc; ++k) {
       const int j0 = B0.bst + k, j1 = B1.bst + k;
@@ -411,21 +425,16 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     // Boundary of the removed cap: edges of removed vertices whose
     // neighbour across the edge survives (bit k of bm: edge k of the slot).
     const unsigned long long L0 = C.L0, L1 = C.L1;
-    const unsigned long long K0 = L0 & ~M0, K1 = L1 & ~M1;   // slots that survive the cut
-    // Slot t < 128 picks its half by a mask (a plain select here is turned
-    // into a two-entry table in private memory).
-    auto is_kept = [K0, K1](int t) -> bool {
-      const unsigned long long hi = 0ull - (unsigned long long)((unsigned)t >> 6);
-      const unsigned long long k = K0 ^ ((K0 ^ K1) & hi);
-      return (k >> (t & 63)) & 1ull;
-    };
+    // Which slots survive the cut, as bytes every lane can look up.
+    S.kept[lane] = (uint8_t)kept0;
+    S.kept[lane + 64] = (uint8_t)kept1;
+    wave_sync();
     auto boundary = [&](uint32_t T) -> int {
       const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
-      int m = 0;
-      if (is_kept(S.E[bq * kPlanes + a] & (kVerts - 1))) m |= 1;
-      if (is_kept(S.E[cq * kPlanes + bq] & (kVerts - 1))) m |= 2;
-      if (is_kept(S.E[a * kPlanes + cq] & (kVerts - 1))) m |= 4;
-      return m;
+      const int m0 = S.kept[S.E[bq * kPlanes + a] & (kVerts - 1)];
+      const int m1 = S.kept[S.E[cq * kPlanes + bq] & (kVerts - 1)];
+      const int m2 = S.kept[S.E[a * kPlanes + cq] & (kVerts - 1)];
+      return m0 | (m1 << 1) | (m2 << 2);
     };
     const int bm0 = out0 ? boundary(C.t0) : 0;
     const int bm1 = out1 ? boundary(C.t1) : 0;
