@@ -11,7 +11,9 @@ Also reported on the same line:
   roofline     the dominant kernel (cell construction) against the FP64 ALU
                peak, its duration from HIP events on the context stream over
                the timed region, and the HBM traffic of the committed counter
-               summary when it was taken on the current kernel source;
+               summary when it was taken on the current kernel source; its
+               "issue" member puts the counted VALU instructions per cell over
+               the same duration against the VALU issue peak;
   flux_kernel  the face kernel against the HBM peak (algorithmic bytes);
   mixed        the point blast (128^3, 100 steps) in mixed precision against
                the FP64 path: cell-updates/s of both, relative L1 density
@@ -52,6 +54,10 @@ FLUX_FACE_BYTES = {"fp64": 48 + 40, "mixed": 48 + 20}      # face record + store
 FLUX_CELL_BYTES = {"fp64": 232, "mixed": 152}              # U_half, grad_half, c-r, w, r once per cell
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_tess_pass1_sod_256x64x64_traffic.md")
 TESS_SOURCE = os.path.join(ROOT, "paper_1707_05333_amd", "csrc", "k_tessellate.hip")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "k_tess_pass1_sod_256x64x64_valu.md")
+# VALU wave-instruction issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64
+# instruction per SIMD every 4 cycles.
+PEAK_VALU_WAVE_INSTR = 256 * 4 * 2.4e9 / 4
 
 
 def parse():
@@ -127,6 +133,24 @@ def tess_traffic(n_launch_cells):
     if sha != m.group(1) or int(c.group(1)) != n_launch_cells:
         return None
     return float(b.group(1))
+
+
+def tess_valu_per_cell(n_launch_cells):
+    """VALU wave instructions per cell of the cell-construction kernel from the
+    committed counter summary, or None when it was taken on another source."""
+    try:
+        text = open(VALU_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"source_sha1:\s*([0-9a-f]{40})", text)
+    v = re.search(r"valu_instructions_per_cell:\s*([0-9.eE+]+)", text)
+    c = re.search(r"cells_per_launch:\s*([0-9]+)", text)
+    if not (m and v and c):
+        return None
+    sha = hashlib.sha1(open(TESS_SOURCE, "rb").read()).hexdigest()
+    if sha != m.group(1) or int(c.group(1)) != n_launch_cells:
+        return None
+    return float(v.group(1))
 
 
 def run_single(M, torch, wl, precision, steps, warmup, timing=True):
@@ -474,6 +498,13 @@ def main():
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
                 "traffic": tess_traffic(n) if args.workload == "sod" else None,
                 "algorithmic_flop_per_cell": TESS_FLOP_PER_CELL, "launch_ms": stage_ms["cells"]}
+    vpc = tess_valu_per_cell(n) if args.workload == "sod" else None
+    if vpc is not None:
+        # What actually bounds the kernel: VALU issue (counted instructions
+        # over the live launch time, against the issue peak).
+        iss = vpc * n / t_cells
+        roofline["issue"] = {"valu_instr_per_cell": vpc, "achieved": iss, "peak": PEAK_VALU_WAVE_INSTR,
+                             "unit": "wave-instr/s", "frac": iss / PEAK_VALU_WAVE_INSTR}
     t_flux = stage_ms["flux"] * 1e-3
     flux_bytes = faces * FLUX_FACE_BYTES[args.precision] + n * FLUX_CELL_BYTES[args.precision]
     flux_gbs = flux_bytes / t_flux / 1e9 if t_flux > 0 else float("nan")
