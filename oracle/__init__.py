@@ -43,12 +43,13 @@ class Params(ctypes.Structure):
         ("riemann", ctypes.c_int32),
         ("half_step_mesh", ctypes.c_int32),
         ("pad", ctypes.c_int32),
+        ("mach_threshold", ctypes.c_double),
     ]
 
 
 def make_params(box, gamma, cfl=0.3, eta=1.0, chi=1.0, zeta=0.25, theta=0.49,
                 rho_floor=1e-12, p_floor=1e-14, limiter_disp=0, predictor_frame=0,
-                limit_mask=3, riemann=0, half_step_mesh=0, **_ignored) -> Params:
+                limit_mask=3, riemann=0, half_step_mesh=0, mach_threshold=0.0, **_ignored) -> Params:
     p = Params()
     p.box[:] = [float(b) for b in box]
     p.gamma, p.cfl, p.eta, p.chi, p.zeta, p.theta = gamma, cfl, eta, chi, zeta, theta
@@ -56,6 +57,7 @@ def make_params(box, gamma, cfl=0.3, eta=1.0, chi=1.0, zeta=0.25, theta=0.49,
     p.limiter_disp, p.predictor_frame, p.limit_mask = limiter_disp, predictor_frame, limit_mask
     p.riemann = riemann
     p.half_step_mesh = half_step_mesh
+    p.mach_threshold = mach_threshold
     return p
 
 
@@ -94,6 +96,12 @@ def lib():
         L.orc_fluxes.restype = ctypes.c_int32
         L.orc_step.argtypes = [ctypes.c_int64, _dp, _dp, _dp, P, ctypes.c_double, ctypes.c_int32, _dp, _i64p]
         L.orc_step.restype = ctypes.c_int32
+        L.orc_step_entropy.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, P, ctypes.c_double, ctypes.c_int32,
+                                       _dp, _i64p, _dp]
+        L.orc_step_entropy.restype = ctypes.c_int32
+        L.orc_init_entropy.argtypes = [ctypes.c_void_p, P, _dp, _dp]
+        L.orc_entropy_face.argtypes = [_dp, _dp, _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_double, _dp, _dp]
         L.orc_face_velocity.argtypes = [_dp] * 6
         L.orc_moving_face_flux.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int32, _dp]
         L.orc_hll_prim.argtypes = [_dp, _dp, _dp, ctypes.c_double, _dp]
@@ -198,6 +206,14 @@ def init_charges(mesh: Mesh, params: Params, prim) -> np.ndarray:
     return Q
 
 
+def init_entropy(mesh: Mesh, params: Params, prim) -> np.ndarray:
+    """Entropy charges S = m P rho^-gamma (Sec. 4.3) of primitive states."""
+    prim = _f64(prim, (mesh.n, 5))
+    S = np.empty(mesh.n)
+    lib().orc_init_entropy(mesh.handle, ctypes.byref(params), _p(prim), _p(S))
+    return S
+
+
 def cell_state(mesh: Mesh, params: Params, Q):
     Q = _f64(Q, (mesh.n, 5))
     U = np.empty((mesh.n, 5)); w = np.empty((mesh.n, 3)); dti = np.empty(mesh.n)
@@ -254,6 +270,20 @@ def step(pos, Q, params: Params, dt_max=1e300, method="grid"):
     return pos, Q, w, float(dt[0]), cnt
 
 
+def step_entropy(pos, Q, S, params: Params, dt_max=1e300, method="grid"):
+    """One whole step with the entropy column (Sec. 4.3).  Returns
+    (pos', Q', S', w, dt, counters, mach) with mach each cell's largest face
+    Mach number."""
+    pos = _f64(pos).copy(); Q = _f64(Q).copy(); S = _f64(S).copy()
+    n = pos.shape[0]
+    w = np.empty((n, 3)); dt = np.zeros(1); cnt = np.zeros(4, dtype=np.int64); mach = np.empty(n)
+    rc = lib().orc_step_entropy(n, _p(pos), _p(Q), _p(S), _p(w), ctypes.byref(params), float(dt_max),
+                                1 if method == "grid" else 0, _p(dt), cnt.ctypes.data_as(_i64p), _p(mach))
+    if rc:
+        raise RuntimeError(f"oracle step failed (code {rc})")
+    return pos, Q, S, w, float(dt[0]), cnt, mach
+
+
 def face_velocity(ri, rj_img, wi, wj, f) -> np.ndarray:
     a = [_f64(x) for x in (ri, rj_img, wi, wj, f)]
     out = np.empty(3)
@@ -274,6 +304,14 @@ def hllc_prim(WL, WR, n, gamma) -> np.ndarray:
     F = np.empty(5)
     lib().orc_hllc_prim(*[_p(x) for x in a], float(gamma), _p(F))
     return F
+
+
+def entropy_face(WL, WR, n, gamma, riemann, AL, AR):
+    """Face-frame flux of rho A and the face's shock Mach number (Sec. 4.3)."""
+    a = [_f64(x) for x in (WL, WR, n)]
+    FX, mach = np.zeros(1), np.zeros(1)
+    lib().orc_entropy_face(*[_p(x) for x in a], float(gamma), int(riemann), float(AL), float(AR), _p(FX), _p(mach))
+    return float(FX[0]), float(mach[0])
 
 
 def hll_prim(WL, WR, n, gamma) -> np.ndarray:

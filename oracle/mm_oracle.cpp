@@ -42,6 +42,15 @@
 //   R-w     the mesh velocity of a step is evaluated from the state at the
 //           start of the step and used both for the face velocities and
 //           the drift (Sec. 2 outline; Sec. 4.2).
+//   R-ent   entropy switch (Sec. 4.3): the state gains X = rho A with the
+//           entropic function A = P rho^-gamma, advected by the mass flux
+//           (its face value upwind by the contact, A_K = X_K / rho_K from
+//           the reconstructed, pre-floor face state).  The shock Mach number
+//           of a face is sqrt(1 + (gamma+1)/(2 gamma) max(0, p*/P_K - 1))
+//           maximised over its two sides, with p* the HLLC star pressure;
+//           a cell's Mach number is the maximum over its faces.  Cells below
+//           the threshold take the pressure from the entropy, the others keep
+//           the energy and reset X from the new state.
 //   R-tess  optional half-step geometry (Sec. 6, first future improvement:
 //           rebuild the tessellation at the half step): the predictor runs
 //           on the time-n mesh; the generators are moved by w dt/2, the
@@ -492,6 +501,7 @@ struct Params {
   int32_t riemann;          // 0: HLLC (the paper's default), 1: HLL (Sec. 4 item 4)
   int32_t half_step_mesh;   // 1: fluxes on the mesh of the half-step positions (R-tess)
   int32_t pad;
+  double mach_threshold;    // entropy switch (Sec. 4.3, R-ent): 0 = energy equation only
 };
 
 // R-floor (Sec. 4.1, floors paragraph).  U = (rho, m, E) densities.
@@ -819,6 +829,8 @@ struct FaceSetup {
   double UL[5], UR[5];
   double n[3];   // unit normal from i toward the neighbour image
   double wt[3];  // face velocity
+  double rhoL0, rhoR0;   // reconstructed densities before the face floors
+  V3 fi, fj;             // face centroid minus each side's centroid
 };
 int setup_face(const Mesh& M, const Params& p, int64_t i, size_t e, const double* Uh, const double* Gh,
                const double* w, FaceSetup& S) {
@@ -851,25 +863,132 @@ int setup_face(const Mesh& M, const Params& p, int64_t i, size_t e, const double
     S.UL[q] = Ui + dm_factor(p.theta, Uj - Ui, Di) * Di;
     S.UR[q] = Uj + dm_factor(p.theta, Ui - Uj, Dj) * Dj;
   }
+  S.rhoL0 = S.UL[0];
+  S.rhoR0 = S.UR[0];
+  S.fi = fi;
+  S.fj = fj;
   int hits = 0;
   hits += apply_floors(S.UL, p) > 0;
   hits += apply_floors(S.UR, p) > 0;
   return hits;
 }
 
+// R-ent, the gradient of the one-component column X: the same least squares
+// and S10 limiter as gradient_cell.
+void gradient_scalar(const Mesh& M, const Params& p, int i, const double* X, double g[3], bool limit) {
+  const CellOut& C = M.cells[i];
+  const V3 ci = centroid(M, i);
+  double Mm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double b[3] = {0, 0, 0};
+  std::vector<V3> dv(C.j.size());
+  for (size_t e = 0; e < C.j.size(); ++e) {
+    const V3 d = (centroid(M, C.j[e]) + shift_of(M, C.code[e])) - ci;
+    dv[e] = d;
+    const double wgt = C.A[e] / norm2(d);
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) Mm[r][c] += wgt * comp(d, r) * comp(d, c);
+    const double dX = X[C.j[e]] - X[i];
+    for (int r = 0; r < 3; ++r) b[r] += wgt * dX * comp(d, r);
+  }
+  const double a00 = Mm[1][1] * Mm[2][2] - Mm[1][2] * Mm[2][1];
+  const double a01 = Mm[0][2] * Mm[2][1] - Mm[0][1] * Mm[2][2];
+  const double a02 = Mm[0][1] * Mm[1][2] - Mm[0][2] * Mm[1][1];
+  const double a11 = Mm[0][0] * Mm[2][2] - Mm[0][2] * Mm[2][0];
+  const double a12 = Mm[0][2] * Mm[1][0] - Mm[0][0] * Mm[1][2];
+  const double a22 = Mm[0][0] * Mm[1][1] - Mm[0][1] * Mm[1][0];
+  const double det = Mm[0][0] * a00 + Mm[0][1] * (Mm[1][2] * Mm[2][0] - Mm[1][0] * Mm[2][2]) +
+                     Mm[0][2] * (Mm[1][0] * Mm[2][1] - Mm[1][1] * Mm[2][0]);
+  const double inv[3][3] = {{a00 / det, a01 / det, a02 / det},
+                            {a01 / det, a11 / det, a12 / det},
+                            {a02 / det, a12 / det, a22 / det}};
+  for (int r = 0; r < 3; ++r) g[r] = inv[r][0] * b[0] + inv[r][1] * b[1] + inv[r][2] * b[2];
+  if (!limit) return;
+  double xmax = X[i], xmin = X[i];
+  for (size_t e = 0; e < C.j.size(); ++e) {
+    xmax = std::max(xmax, X[C.j[e]]);
+    xmin = std::min(xmin, X[C.j[e]]);
+  }
+  double alpha = 1.0;
+  for (size_t e = 0; e < C.j.size(); ++e) {
+    const V3 disp = (p.limiter_disp == 0) ? dv[e] : (M.r[i] + C.f_rel[e]) - ci;
+    const double D = g[0] * disp.x + g[1] * disp.y + g[2] * disp.z;
+    double psi;
+    if (D > 0) psi = (xmax - X[i]) / D;
+    else if (D < 0) psi = (xmin - X[i]) / D;
+    else psi = 1.0;
+    alpha = std::min(alpha, psi);
+  }
+  for (int r = 0; r < 3; ++r) g[r] *= alpha;
+}
+
+// R-ent, time derivative of X = rho A for the predictor: -div(X v), plus
+// w . grad X for the moving generator (R-pred).
+double rate_entropy(const double U[5], const double G[5][3], double X, const double gX[3], const double w[3],
+                    bool moving) {
+  const double rho = U[0];
+  const double v[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
+  double divv = 0;
+  for (int a = 0; a < 3; ++a) divv += (G[1 + a][a] - v[a] * G[0][a]) / rho;
+  double r = -(v[0] * gX[0] + v[1] * gX[1] + v[2] * gX[2] + X * divv);
+  if (moving) r += w[0] * gX[0] + w[1] * gX[1] + w[2] * gX[2];
+  return r;
+}
+
+// R-ent, the face-frame flux of X and the face's shock Mach number, for the
+// face-frame primitive states L, R (after the face floors) and the entropic
+// functions A_L, A_R of the two sides.
+void entropy_face(const Prim& L, const Prim& R, const double n[3], double gamma, int riemann, double AL, double AR,
+                  double& FX, double& mach) {
+  const double uL = L.v[0] * n[0] + L.v[1] * n[1] + L.v[2] * n[2];
+  const double uR = R.v[0] * n[0] + R.v[1] * n[1] + R.v[2] * n[2];
+  const double cL = std::sqrt(gamma * L.P / L.rho), cR = std::sqrt(gamma * R.P / R.rho);
+  const double SL = std::min(uL - cL, uR - cR);
+  const double SR = std::max(uL + cL, uR + cR);
+  const double Ss = (R.P - L.P + L.rho * uL * (SL - uL) - R.rho * uR * (SR - uR)) /
+                    (L.rho * (SL - uL) - R.rho * (SR - uR));
+  const double ps = L.P + L.rho * (SL - uL) * (Ss - uL);
+  const double k = (gamma + 1.0) / (2.0 * gamma);
+  const double ML = std::sqrt(1.0 + k * std::max(0.0, ps / L.P - 1.0));
+  const double MR = std::sqrt(1.0 + k * std::max(0.0, ps / R.P - 1.0));
+  mach = std::max(ML, MR);
+  const double XL = L.rho * AL, XR = R.rho * AR;
+  if (SL >= 0) {
+    FX = XL * uL;
+  } else if (SR < 0) {
+    FX = XR * uR;
+  } else if (riemann == 1) {
+    FX = (SR * XL * uL - SL * XR * uR + SL * SR * (XR - XL)) / (SR - SL);
+  } else {
+    // HLLC: the star-region mass flux carries the entropic function of the
+    // side the contact leaves behind.
+    double F[5];
+    hllc(L, R, n, gamma, F);
+    FX = F[0] * (Ss >= 0 ? AL : AR);
+  }
+}
+
 // Fluxes of all faces and their accumulation into dQ (Sec. 4, update of the
 // charges and items 1-5).  Each face's flux is computed once, by the cell
 // with the lower index, with that cell's face geometry; R-upd fixes the
 // signs.
+// With the entropy column (Xh, gXh non-null, R-ent) also the flux of X into
+// dS and each cell's largest face Mach number into mach.
 int fluxes(const Mesh& M, const Params& p, const double* Uh, const double* Gh, const double* w, double dt,
-           double* dQ, int64_t* face_hits) {
+           double* dQ, int64_t* face_hits, const double* Xh = nullptr, const double* gXh = nullptr,
+           double* dS = nullptr, double* mach = nullptr) {
   const int64_t n = M.n;
+  const bool ent = Xh != nullptr;
   std::vector<std::vector<std::array<double, 5>>> phi(n);
+  std::vector<std::vector<double>> phiX(ent ? n : 0), machF(ent ? n : 0);
   int64_t hits = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : hits)
   for (int64_t i = 0; i < n; ++i) {
     const CellOut& C = M.cells[i];
     phi[i].assign(C.j.size(), {0, 0, 0, 0, 0});
+    if (ent) {
+      phiX[i].assign(C.j.size(), 0.0);
+      machF[i].assign(C.j.size(), 0.0);
+    }
     for (size_t e = 0; e < C.j.size(); ++e) {
       if (!owns((int)i, C.j[e], C.code[e])) continue;
       FaceSetup S;
@@ -877,6 +996,24 @@ int fluxes(const Mesh& M, const Params& p, const double* Uh, const double* Gh, c
       double F[5];
       moving_face_flux(S.UL, S.UR, S.n, S.wt, p.gamma, p.riemann, F);
       for (int q = 0; q < 5; ++q) phi[i][e][q] = dt * C.A[e] * F[q];
+      if (ent) {
+        const int j = C.j[e];
+        const double* gi = gXh + 3 * i;
+        const double* gj = gXh + 3 * (int64_t)j;
+        const double Di = gi[0] * S.fi.x + gi[1] * S.fi.y + gi[2] * S.fi.z;
+        const double Dj = gj[0] * S.fj.x + gj[1] * S.fj.y + gj[2] * S.fj.z;
+        const double XL = Xh[i] + dm_factor(p.theta, Xh[j] - Xh[i], Di) * Di;
+        const double XR = Xh[j] + dm_factor(p.theta, Xh[i] - Xh[j], Dj) * Dj;
+        Prim L = to_prim(S.UL, p.gamma), R = to_prim(S.UR, p.gamma);
+        for (int a = 0; a < 3; ++a) {
+          L.v[a] -= S.wt[a];
+          R.v[a] -= S.wt[a];
+        }
+        double FX, mf;
+        entropy_face(L, R, S.n, p.gamma, p.riemann, XL / S.rhoL0, XR / S.rhoR0, FX, mf);
+        phiX[i][e] = dt * C.A[e] * FX;
+        machF[i][e] = mf;
+      }
     }
   }
   int bad = 0;
@@ -884,10 +1021,15 @@ int fluxes(const Mesh& M, const Params& p, const double* Uh, const double* Gh, c
   for (int64_t i = 0; i < n; ++i) {
     const CellOut& C = M.cells[i];
     double acc[5] = {0, 0, 0, 0, 0};
+    double accX = 0.0, mx = 0.0;
     for (size_t e = 0; e < C.j.size(); ++e) {
       const int j = C.j[e];
       if (owns((int)i, j, C.code[e])) {
         for (int q = 0; q < 5; ++q) acc[q] -= phi[i][e][q];
+        if (ent) {
+          accX -= phiX[i][e];
+          mx = std::max(mx, machF[i][e]);
+        }
       } else {
         const CellOut& D = M.cells[j];
         const int want = kneg(C.code[e]);
@@ -896,9 +1038,17 @@ int fluxes(const Mesh& M, const Params& p, const double* Uh, const double* Gh, c
           if (D.j[t] == (int)i && D.code[t] == want) { e2 = t; break; }
         if (e2 == D.j.size()) { bad++; continue; }
         for (int q = 0; q < 5; ++q) acc[q] += phi[j][e2][q];
+        if (ent) {
+          accX += phiX[j][e2];
+          mx = std::max(mx, machF[j][e2]);
+        }
       }
     }
     for (int q = 0; q < 5; ++q) dQ[5 * i + q] = acc[q];
+    if (ent) {
+      dS[i] = accX;
+      mach[i] = mx;
+    }
   }
   if (face_hits) *face_hits = hits;
   return bad ? 2 : 0;
@@ -1105,12 +1255,11 @@ int32_t orc_fluxes(void* m, const orc_params* p, const double* Uh, const double*
   return fluxes(*(Mesh*)m, *p, Uh, Gh, w, dt, dQ, hits);
 }
 
-// One whole step (Sec. 2 outline).  pos, Q in/out; w_out receives the mesh
-// velocities used.  counters: [0] cell floors at the start, [1] predictor
-// floors, [2] face floors, [3] floors after the update.  Returns 0, or a
-// non-zero code when the tessellation or the face topology failed.
-int32_t orc_step(int64_t n, double* pos, double* Q, double* w_out, const orc_params* p, double dt_max,
-                 int32_t method, double* dt_out, int64_t* counters) {
+// The step, with the entropy column when S is non-null (R-ent); mach_out
+// (optional) receives each cell's largest face Mach number.
+static int32_t step_impl(int64_t n, double* pos, double* Q, double* S, double* w_out, const orc_params* p,
+                         double dt_max, int32_t method, double* dt_out, int64_t* counters, double* mach_out) {
+  if (S && p->half_step_mesh) return 3;   // the two options are not combined
   void* mh = orc_mesh_build(n, pos, p->box, method, 0, 0);
   Mesh* M = (Mesh*)mh;
   if (M->status) { delete M; return 1; }
@@ -1120,6 +1269,21 @@ int32_t orc_step(int64_t n, double* pos, double* Q, double* w_out, const orc_par
   dt = std::min(dt, dt_max);
   orc_gradient(mh, p, U.data(), G.data(), p->limit_mask & 1);
   orc_predict(mh, p, U.data(), G.data(), w_out, dt, Uh.data(), 0, &c1);
+  // R-ent: X = S / V, its gradient and its half-step value.
+  std::vector<double> X, Xh, gX, gXh, dS, mach;
+  if (S) {
+    X.resize(n); Xh.resize(n); gX.resize(3 * n); gXh.resize(3 * n); dS.resize(n); mach.resize(n);
+    for (int64_t i = 0; i < n; ++i) X[i] = S[i] / M->cells[i].V;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+      gradient_scalar(*M, *p, (int)i, X.data(), &gX[3 * i], p->limit_mask & 1);
+      double g[5][3];
+      for (int q = 0; q < 5; ++q)
+        for (int c = 0; c < 3; ++c) g[q][c] = G[15 * i + 3 * q + c];
+      Xh[i] = X[i] + 0.5 * dt * rate_entropy(&U[5 * i], g, X[i], &gX[3 * i], w_out + 3 * i,
+                                             p->predictor_frame == 0);
+    }
+  }
   // R-tess: the second half of the step works on the mesh of the generators
   // moved to the half step.
   Mesh* F = M;
@@ -1136,22 +1300,51 @@ int32_t orc_step(int64_t n, double* pos, double* Q, double* w_out, const orc_par
     if (F->status) { delete F; delete M; return 1; }
   }
   orc_gradient(F, p, Uh.data(), Gh.data(), (p->limit_mask >> 1) & 1);
-  const int rc = fluxes(*F, *p, Uh.data(), Gh.data(), w_out, dt, dQ.data(), &c2);
+  if (S) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i)
+      gradient_scalar(*F, *p, (int)i, Xh.data(), &gXh[3 * i], (p->limit_mask >> 1) & 1);
+  }
+  const int rc = S ? fluxes(*F, *p, Uh.data(), Gh.data(), w_out, dt, dQ.data(), &c2, Xh.data(), gXh.data(),
+                            dS.data(), mach.data())
+                   : fluxes(*F, *p, Uh.data(), Gh.data(), w_out, dt, dQ.data(), &c2);
   if (rc) {
     if (F != M) delete F;
     delete M;
     return rc;
   }
+  const double g = p->gamma, g1 = p->gamma - 1.0;
   for (int64_t i = 0; i < n; ++i) {
     for (int q = 0; q < 5; ++q) Q[5 * i + q] += dQ[5 * i + q];
     // Floors at the cell centre after the step, with the volume of the mesh
     // the fluxes used (time n, or the half step under R-tess).
     const double V = F->cells[i].V;
+    bool from_entropy = false;
+    if (S) {
+      S[i] += dS[i];
+      if (mach_out) mach_out[i] = mach[i];
+      if (mach[i] < p->mach_threshold) {
+        // R-ent: no shock at this cell: the pressure follows the entropy.
+        const double m = Q[5 * i];
+        const double A = S[i] / m;
+        const double P = A * std::pow(m / V, g);
+        const double p2 = Q[5 * i + 1] * Q[5 * i + 1] + Q[5 * i + 2] * Q[5 * i + 2] + Q[5 * i + 3] * Q[5 * i + 3];
+        Q[5 * i + 4] = P * V / g1 + 0.5 * p2 / m;
+        from_entropy = true;
+      }
+    }
     double Ui[5];
     for (int q = 0; q < 5; ++q) Ui[q] = Q[5 * i + q] / V;
-    if (apply_floors(Ui, *p)) {
+    const bool floored = apply_floors(Ui, *p) != 0;
+    if (floored) {
       c3++;
       for (int q = 0; q < 5; ++q) Q[5 * i + q] = Ui[q] * V;
+    }
+    if (S && (!from_entropy || floored)) {
+      // R-ent: the energy was integrated (or floored): the entropy follows
+      // the new state.
+      const Prim pr = to_prim(Ui, g);
+      S[i] = Q[5 * i] * pr.P / std::pow(pr.rho, g);
     }
     // Drift by a full step with periodic wrap (Sec. 2, item 5).
     for (int a = 0; a < 3; ++a) {
@@ -1173,6 +1366,32 @@ int32_t orc_step(int64_t n, double* pos, double* Q, double* w_out, const orc_par
   return 0;
 }
 
+// One whole step (Sec. 2 outline).  pos, Q in/out; w_out receives the mesh
+// velocities used.  counters: [0] cell floors at the start, [1] predictor
+// floors, [2] face floors, [3] floors after the update.  Returns 0, or a
+// non-zero code when the tessellation or the face topology failed.
+int32_t orc_step(int64_t n, double* pos, double* Q, double* w_out, const orc_params* p, double dt_max,
+                 int32_t method, double* dt_out, int64_t* counters) {
+  return step_impl(n, pos, Q, nullptr, w_out, p, dt_max, method, dt_out, counters, nullptr);
+}
+
+// As orc_step with the entropy charge S = m A (R-ent, Sec. 4.3) in/out and
+// each cell's largest face Mach number out (mach may be NULL).  Returns 3
+// when combined with the half-step mesh.
+int32_t orc_step_entropy(int64_t n, double* pos, double* Q, double* S, double* w_out, const orc_params* p,
+                         double dt_max, int32_t method, double* dt_out, int64_t* counters, double* mach) {
+  return step_impl(n, pos, Q, S, w_out, p, dt_max, method, dt_out, counters, mach);
+}
+
+// Entropy charges S = m P rho^-gamma of primitive states on a mesh (R-ent).
+void orc_init_entropy(void* m, const orc_params* p, const double* prim, double* S) {
+  const Mesh* M = (Mesh*)m;
+  for (int64_t i = 0; i < M->n; ++i) {
+    const double rho = prim[5 * i], P = prim[5 * i + 4];
+    S[i] = rho * M->cells[i].V * P / std::pow(rho, p->gamma);
+  }
+}
+
 void orc_face_velocity(const double* ri, const double* rj_img, const double* wi, const double* wj, const double* f,
                        double* wt) {
   const V3 r = face_velocity({ri[0], ri[1], ri[2]}, {rj_img[0], rj_img[1], rj_img[2]}, {wi[0], wi[1], wi[2]},
@@ -1187,6 +1406,15 @@ void orc_face_velocity(const double* ri, const double* rj_img, const double* wi,
 void orc_moving_face_flux(const double* UL, const double* UR, const double* n, const double* wt, double gamma,
                           int32_t riemann, double* F) {
   moving_face_flux(UL, UR, n, wt, gamma, riemann, F);
+}
+
+// R-ent: flux of X = rho A and shock Mach number of a face-frame Riemann
+// problem on primitive states (riemann 0 HLLC, 1 HLL).
+void orc_entropy_face(const double* WL, const double* WR, const double* n, double gamma, int32_t riemann,
+                      double AL, double AR, double* FX, double* mach) {
+  Prim L{WL[0], {WL[1], WL[2], WL[3]}, WL[4]};
+  Prim R{WR[0], {WR[1], WR[2], WR[3]}, WR[4]};
+  entropy_face(L, R, n, gamma, riemann, AL, AR, *FX, *mach);
 }
 
 // HLL in the face frame on primitive states (rho, vx, vy, vz, P).
