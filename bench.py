@@ -24,6 +24,8 @@ Also reported on the same line:
                HLL: L1 of density against the exact solution, oscillations;
   half_step    start-of-step against half-step geometry: Gresho vortex
                accuracy, angular momentum and cost; free-stream error order;
+  entropy      the entropy switch against the energy equation alone: the
+               paper's Sod tube and the cost of the extra column;
   serving      a Poisson stream of Kelvin-Helmholtz simulations (1e3..2e5
                points each, 20 steps, mixed) through the batch serving loop
                under an explicit device budget: throughput, p50/p99 step
@@ -73,6 +75,7 @@ def parse():
     ap.add_argument("--no-gresho", action="store_true", help="skip the Gresho-Chan convergence object")
     ap.add_argument("--no-sod-paper", action="store_true", help="skip the paper's Sod tube object")
     ap.add_argument("--no-half-step", action="store_true", help="skip the half-step mesh object")
+    ap.add_argument("--no-entropy", action="store_true", help="skip the entropy switch object")
     ap.add_argument("--mixed-steps", type=int, default=100)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
@@ -314,6 +317,65 @@ def half_step_object(M, torch, args):
     return out
 
 
+def entropy_object(M, torch, args):
+    """Entropy switch (Mach threshold 1.1) against the energy equation alone:
+    the paper's Sod tube to t = 2 (L1 of density against the exact solution,
+    cells above the threshold), and the cost of the extra column on the 1M
+    Sod step."""
+    import numpy as np
+    import workloads as W
+    out = {"workload": "sod_paper_16x1x1_t2 + sod_256x64x64", "precision": "fp64", "sod_paper": [],
+           "step_ms": {}}
+    wl = W.sod_paper(k=14)
+    for mth in (0.0, 1.1):
+        mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, mach_threshold=mth, **wl.params))
+        pos = torch.from_numpy(wl.pos.copy()).cuda()
+        mm.tessellate(pos)
+        prim = torch.from_numpy(wl.prim.copy()).cuda()
+        Q, S = mm.init_charges(prim), mm.init_entropy(prim)
+        w = torch.empty_like(pos)
+        mach = torch.empty(wl.n, dtype=torch.float32, device="cuda")
+        t, steps, shocked = 0.0, 0, 0
+        while t < 2.0 * (1 - 1e-12):
+            t += mm.step_entropy(pos, w, Q, S, mach, dt_max=2.0 - t)["dt"]
+            steps += 1
+        shocked = int((mach >= 1.1).sum())
+        mm.tessellate(pos)
+        V = mm.mesh_export().V.cpu().numpy()
+        x, q = pos.cpu().numpy(), Q.cpu().numpy()
+        mm.close()
+        xx = x[:, 0]
+        mid = (xx >= 4.0) & (xx < 12.0)
+        ex = np.empty_like(xx)
+        L, R = wl.meta["left"], wl.meta["right"]
+        ex[mid] = _exact_riemann_rho(L, R, 1.4, (xx[mid] - 8.0) / 2.0)
+        ex[~mid] = _exact_riemann_rho(R, L, 1.4, np.where(xx[~mid] < 4.0, xx[~mid], xx[~mid] - 16.0) / 2.0)
+        out["sod_paper"].append({"mach_threshold": mth, "steps": steps, "cells_above_threshold_at_end": shocked,
+                                 "l1_rho": float(np.mean(np.abs(q[:, 0] / V - ex)))})
+        log(f"entropy switch {mth}: sod_paper L1 {out['sod_paper'][-1]['l1_rho']:.3e}")
+    big = W.c2_sod()
+    for mth in (0.0, 1.1):
+        mm = M.MovingMesh(big.n, M.make_params(box=big.box, mach_threshold=mth, **big.params))
+        pos = torch.from_numpy(big.pos.copy()).cuda()
+        mm.tessellate(pos)
+        prim = torch.from_numpy(big.prim.copy()).cuda()
+        Q, S = mm.init_charges(prim), mm.init_entropy(prim)
+        w = torch.empty_like(pos)
+
+        def one():   # the energy equation alone goes through mm_step, without the column
+            return mm.step_entropy(pos, w, Q, S) if mth > 0 else mm.step(pos, w, Q)
+        for k in range(2):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(5):
+            one()
+        torch.cuda.synchronize()
+        out["step_ms"]["entropy_column" if mth > 0 else "energy_only"] = 1e3 * (time.perf_counter() - t0) / 5
+        mm.close()
+    return out
+
+
 def _exact_riemann_rho(left, right, gamma, xi):
     """Density of the exact ideal-gas Riemann solution at x/t = xi (the
     textbook construction: star pressure by bisection on the sum of the
@@ -542,6 +604,8 @@ def main():
         out["sod_paper"] = sod_paper_object(M, torch, args)
     if not args.no_half_step:
         out["half_step"] = half_step_object(M, torch, args)
+    if not args.no_entropy:
+        out["entropy"] = entropy_object(M, torch, args)
     if not args.no_serve:
         out["serving"] = serving_object(M, torch, args)
         log(f"serving: {out['serving']['value']:.3e} cell-updates/s, p50 {out['serving']['step_latency_p50_ms']:.2f} ms"

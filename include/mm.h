@@ -90,6 +90,10 @@ typedef struct {
                                 0 (default): the mesh of the start of the step, as in the paper's runs.
                                 Single simulations only (mm_batch_admit rejects 1). */
   int32_t reserved;          /* must be 0 */
+  double mach_threshold;     /* entropy switch (Sec. 4.3): a cell whose largest face shock Mach number
+                                stays below it takes its pressure from the advected entropy (the paper
+                                uses 1.1); 0 (default): the energy equation alone.  Above 0, steps go
+                                through mm_step_entropy; single simulations only. */
 } mm_params;
 
 /* Per-step report, filled by mm_step (and partly by mm_tessellate). */
@@ -198,9 +202,29 @@ mm_status mm_fluxes(mm_ctx *ctx, const void *U_half, const void *grad_half, cons
  * fluxes, update of Q with floors, drift pos += w dt with periodic wrap.
  * pos: dev [n][3] in/out; w: dev [n][3] out (the mesh velocities used);
  * Q: dev [n][5] in/out; info: host out (may be NULL).  Waits for the
- * stream once, at the end. */
+ * stream once, at the end.  MM_EINVAL when p.mach_threshold > 0 (use
+ * mm_step_entropy). */
 mm_status mm_step(mm_ctx *ctx, int64_t n, double *pos, double *w, double *Q, double dt_max,
                   mm_step_info *info);
+
+/* Entropy charges S_i = m_i P_i rho_i^-gamma (Sec. 4.3: the column rho s
+ * with the entropic function A = P rho^-gamma as s) of primitive states on
+ * the last tessellation.  prim: dev [n][5] as for mm_init_charges; S: dev
+ * [n] out, caller order, caller-owned.  Errors: MM_EINVAL, MM_ESTATE. */
+mm_status mm_init_entropy(mm_ctx *ctx, const double *prim, double *S);
+
+/* One whole step with the entropy column (Sec. 4.3), otherwise as mm_step.
+ * The state gains X = rho A, advected by the mass flux (reconstructed,
+ * limited and predicted like the other columns); every face reports a
+ * shock Mach number from its Riemann problem, and a cell whose largest one
+ * is below p.mach_threshold takes its pressure from S / m, while the others
+ * keep the energy and reset S from the new state.  S: dev [n] in/out
+ * entropy charges (caller order); mach: dev [n] float out, each cell's
+ * largest face Mach number (1 without compression), or NULL.  With
+ * mach_threshold = 0 the charges Q are exactly those of mm_step.
+ * Errors as mm_step, and MM_EINVAL with half_step_mesh = 1. */
+mm_status mm_step_entropy(mm_ctx *ctx, int64_t n, double *pos, double *w, double *Q, double *S, float *mach,
+                          double dt_max, mm_step_info *info);
 
 /* Message for the last error on this context (static storage of the context). */
 const char *mm_last_error(const mm_ctx *ctx);

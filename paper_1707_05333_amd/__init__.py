@@ -47,6 +47,7 @@ class Params(ctypes.Structure):
         ("predictor_frame", ctypes.c_int32),
         ("half_step_mesh", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("mach_threshold", ctypes.c_double),
     ]
 
 
@@ -152,6 +153,8 @@ SIGNATURES = {
     "mm_get_mesh_view": (_i32, [_vp, ctypes.POINTER(MeshView)]),
     "mm_mesh_export": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_i64)]),
     "mm_init_charges": (_i32, [_vp, _vp, _vp]),
+    "mm_init_entropy": (_i32, [_vp, _vp, _vp]),
+    "mm_step_entropy": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _d, ctypes.POINTER(StepInfo)]),
     "mm_cell_state": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
     "mm_gradients": (_i32, [_vp, _vp, _vp, _i32]),
     "mm_predict": (_i32, [_vp, _vp, _vp, _vp, _d, _vp]),
@@ -212,7 +215,7 @@ def make_params(box=(1.0, 1.0, 1.0), gamma=5.0 / 3.0, precision="fp64", **kw) ->
     p.gamma = float(gamma)
     p.precision = MM_MIXED if precision in ("mixed", MM_MIXED) else MM_FP64
     for k, v in kw.items():
-        if k in ("cfl", "eta", "chi", "zeta", "theta", "rho_floor", "p_floor"):
+        if k in ("cfl", "eta", "chi", "zeta", "theta", "rho_floor", "p_floor", "mach_threshold"):
             setattr(p, k, float(v))
         elif k in ("limit_mask", "predictor_frame", "half_step_mesh"):
             setattr(p, k, int(v))
@@ -364,6 +367,28 @@ class MovingMesh:
         self._check(self.lib.mm_step(self.ctx, n, _ptr(pos, torch.float64, (n, 3), "pos"),
                                      _ptr(w, torch.float64, (n, 3), "w"), _ptr(Q, torch.float64, (n, 5), "Q"),
                                      float(dt_max), ctypes.byref(info)))
+        self.n = n
+        return info.as_dict()
+
+    def init_entropy(self, prim):
+        """Entropy charges S = m P rho^-gamma (Sec. 4.3) on the last tessellation."""
+        torch = self._torch
+        S = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self._check(self.lib.mm_init_entropy(self.ctx, _ptr(prim, torch.float64, (self.n, 5), "prim"), _ptr(S)))
+        return S
+
+    def step_entropy(self, pos, w, Q, S, mach=None, dt_max=math.inf) -> dict:
+        """One whole step with the entropy column, in place on pos, w, Q and S;
+        mach (float32 [n], optional) receives each cell's largest face Mach number."""
+        torch = self._torch
+        n = int(pos.shape[0])
+        info = StepInfo()
+        self._check(self.lib.mm_step_entropy(self.ctx, n, _ptr(pos, torch.float64, (n, 3), "pos"),
+                                             _ptr(w, torch.float64, (n, 3), "w"),
+                                             _ptr(Q, torch.float64, (n, 5), "Q"),
+                                             _ptr(S, torch.float64, (n,), "S"),
+                                             _ptr(mach, torch.float32, (n,), "mach") if mach is not None else None,
+                                             float(dt_max), ctypes.byref(info)))
         self.n = n
         return info.as_dict()
 

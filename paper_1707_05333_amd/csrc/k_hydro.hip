@@ -175,6 +175,53 @@ __device__ inline void moving_flux(const T UL[5], const T UR[5], const T n[3], c
   F[4] = Ff[4] + wt[0] * Ff[1] + wt[1] * Ff[2] + wt[2] * Ff[3] + T(0.5) * w2 * Ff[0];
 }
 
+// Entropy column on one face (Sec. 4.3): the face-frame flux of X = rho A,
+// carried by the mass flux with the entropic function A of the side the
+// contact leaves behind (upwind side when all waves go one way; the HLL
+// average with hll), and the face's shock Mach number
+// sqrt(1 + (gamma+1)/(2 gamma) max(0, p*/P_K - 1)) maximised over both
+// sides, with p* the HLLC star pressure.  UL, UR are the face states after
+// the face floors; AL, AR the entropic functions of the reconstruction.
+template <typename T>
+__device__ inline void entropy_flux(const T UL[5], const T UR[5], const T n[3], const T wt[3], T gamma, bool hll,
+                                    T AL, T AR, T& FX, float& mach) {
+  const T g1 = gamma - T(1);
+  const T rL = UL[0], rR = UR[0];
+  const T irL = quot(T(1), rL), irR = quot(T(1), rR);
+  T vL[3], vR[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    vL[a] = UL[1 + a] * irL;
+    vR[a] = UR[1 + a] * irR;
+  }
+  const T PL = g1 * (UL[4] - T(0.5) * (UL[1] * vL[0] + UL[2] * vL[1] + UL[3] * vL[2]));
+  const T PR = g1 * (UR[4] - T(0.5) * (UR[1] * vR[0] + UR[2] * vR[1] + UR[3] * vR[2]));
+  const T uL = (vL[0] - wt[0]) * n[0] + (vL[1] - wt[1]) * n[1] + (vL[2] - wt[2]) * n[2];
+  const T uR = (vR[0] - wt[0]) * n[0] + (vR[1] - wt[1]) * n[1] + (vR[2] - wt[2]) * n[2];
+  const T cL = sqrt(gamma * PL * irL), cR = sqrt(gamma * PR * irR);
+  const T SL = fmin(uL - cL, uR - cR);
+  const T SR = fmax(uL + cL, uR + cR);
+  const T Ss = quot(PR - PL + rL * uL * (SL - uL) - rR * uR * (SR - uR), rL * (SL - uL) - rR * (SR - uR));
+  const T ps = PL + rL * (SL - uL) * (Ss - uL);
+  const T k = quot(gamma + T(1), T(2) * gamma);
+  const T ML = sqrt(T(1) + k * fmax(T(0), quot(ps, PL) - T(1)));
+  const T MR = sqrt(T(1) + k * fmax(T(0), quot(ps, PR) - T(1)));
+  mach = (float)fmax(ML, MR);
+  const T XL = rL * AL, XR = rR * AR;
+  if (SL >= T(0)) {
+    FX = XL * uL;
+  } else if (SR < T(0)) {
+    FX = XR * uR;
+  } else if (hll) {
+    FX = quot(SR * XL * uL - SL * XR * uR + SL * SR * (XR - XL), SR - SL);
+  } else {
+    const bool left = Ss >= T(0);
+    const T rK = left ? rL : rR, uK = left ? uL : uR, SK = left ? SL : SR;
+    const T fac = quot(rK * (SK - uK), SK - Ss);
+    FX = (rK * uK + SK * (fac - rK)) * (left ? AL : AR);
+  }
+}
+
 // Duffell-MacFadyen limit on one face (Sec. 4.1): the extrapolation D from
 // the centroid to the face may not exceed theta times the jump dU to the
 // neighbour, nor oppose its sign.  Returns beta D with
@@ -479,12 +526,16 @@ __device__ inline FaceParams face_params(const SegDesc* segs, const SegStatus* d
 // phi = dt A F, F the lab-frame flux from the owner i toward j.  Each XCD
 // takes one contiguous eighth of the face list (faces are in owner order, so
 // the cells it gathers stay in its L2) and its blocks stride through it.
-template <typename R>
+// With ENT the entropy column's face flux and the face's shock Mach number
+// are written as well (Sec. 4.3).
+template <typename R, bool ENT>
 __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ segs, int64_t nf_host,
                                                    const unsigned long long* __restrict__ nf_dev,
                                                    const Face* __restrict__ faces,
                                                    const FluxCell<R>* __restrict__ rec, const SegStatus* dt_src,
-                                                   double dt_fixed, R* __restrict__ phi, SegStatus* segst) {
+                                                   double dt_fixed, R* __restrict__ phi, SegStatus* segst,
+                                                   const XCell<R>* __restrict__ recx, R* __restrict__ phiX,
+                                                   float* __restrict__ machF) {
   const int64_t nf = nf_dev ? std::min<int64_t>((int64_t)*nf_dev, nf_host) : nf_host;
   const int64_t xcd = blockIdx.x % kXcds, kb = blockIdx.x / kXcds;
   const int64_t nbx = ((int64_t)gridDim.x - xcd + kXcds - 1) / kXcds;
@@ -525,6 +576,7 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
       UR[q] = uj + dm_limited(theta, ui - uj, Dj);
     }
     const R g1 = (R)(hp.gamma - 1.0);
+    const R rL0 = UL[0], rR0 = UR[0];   // before the face floors
     int hit = apply_floors(UL, g1, (R)hp.rho_floor, (R)hp.p_floor);
     hit += apply_floors(UR, g1, (R)hp.rho_floor, (R)hp.p_floor);
     if (hit) atomicAdd(&segst[seg].floor_hits[2], (unsigned long long)hit);
@@ -533,7 +585,103 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
     const R scale = (R)(hp.dt * F.A);
 #pragma unroll
     for (int q = 0; q < 5; ++q) phi[5 * f + q] = scale * Fx[q];
+    if constexpr (ENT) {
+      const XCell<R> XA = recx[F.i], XB = recx[F.j];
+      const R Di = XA.g[0] * fi[0] + XA.g[1] * fi[1] + XA.g[2] * fi[2];
+      const R Dj = XB.g[0] * fj[0] + XB.g[1] * fj[1] + XB.g[2] * fj[2];
+      const R XL = XA.X + dm_limited(theta, XB.X - XA.X, Di);
+      const R XR = XB.X + dm_limited(theta, XA.X - XB.X, Dj);
+      R FX;
+      float mach;
+      entropy_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, quot(XL, rL0), quot(XR, rR0), FX, mach);
+      phiX[f] = scale * FX;
+      machF[f] = mach;
+    }
   }
+}
+
+// Entropy column (Sec. 4.3): X = S / V of each internal cell, S gathered.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_entropy_state(int64_t n, const int32_t* __restrict__ perm,
+                                                            const double* __restrict__ geo,
+                                                            const double* __restrict__ Sc, double* __restrict__ Ss,
+                                                            R* __restrict__ X) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double S = Sc[perm[s]];
+  Ss[s] = S;
+  X[s] = (R)(S / geo[4 * s]);
+}
+
+// Gradient of the entropy column, with the same least squares and S10
+// limiter as k_gradient (one component); then either the half-step value
+// X + dt/2 (-div(X v) + w . grad X) or the face kernel's record.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_entropy_gradient(
+    const SegDesc* __restrict__ segs, const int32_t* __restrict__ sseg, int64_t n, const R* __restrict__ X,
+    const unsigned long long* __restrict__ counts, const unsigned long long* __restrict__ soff,
+    const NbrEntry<R>* __restrict__ nbr, const double* __restrict__ minv, int limit, const R* __restrict__ U,
+    const R* __restrict__ G, const double* __restrict__ w, const SegStatus* dt_src, R* __restrict__ Xh,
+    XCell<R>* __restrict__ recx) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int nf = (int)(counts[s] >> 32);
+  const NbrEntry<R>* list = nbr + sell_slot(soff, s, 0);
+  const R xi = X[s];
+  R xmax = xi, xmin = xi, b[3] = {R(0), R(0), R(0)};
+  for (int e = 0; e < nf; ++e) {
+    const NbrEntry<R> E = list[64 * e];
+    const R v = X[E.o];
+    const R t = E.wgt * (v - xi);
+    b[0] += t * E.d[0];
+    b[1] += t * E.d[1];
+    b[2] += t * E.d[2];
+    xmax = v > xmax ? v : xmax;
+    xmin = v < xmin ? v : xmin;
+  }
+  const double* mi = minv + 6 * s;
+  const R m00 = (R)mi[0], m01 = (R)mi[1], m02 = (R)mi[2], m11 = (R)mi[3], m12 = (R)mi[4], m22 = (R)mi[5];
+  R g[3] = {m00 * b[0] + m01 * b[1] + m02 * b[2], m01 * b[0] + m11 * b[1] + m12 * b[2],
+            m02 * b[0] + m12 * b[1] + m22 * b[2]};
+  const int seg = sseg[s];
+  const HydroParams& hp = segs[seg].hp;
+  const bool lim = limit < kLimitMaskBit0 ? limit != kLimitOff
+                                          : ((hp.limit_mask >> (limit - kLimitMaskBit0)) & 1) != 0;
+  if (lim) {
+    R dpos = R(0), dneg = R(0);
+    for (int e = 0; e < nf; ++e) {
+      const NbrEntry<R> E = list[64 * e];
+      const R D = g[0] * E.d[0] + g[1] * E.d[1] + g[2] * E.d[2];
+      dpos = D > dpos ? D : dpos;
+      dneg = D < dneg ? D : dneg;
+    }
+    R alpha = R(1);
+    if (dpos > R(0)) {
+      const R psi = quot(xmax - xi, dpos);
+      alpha = psi < alpha ? psi : alpha;
+    }
+    if (dneg < R(0)) {
+      const R psi = quot(xmin - xi, dneg);
+      alpha = psi < alpha ? psi : alpha;
+    }
+    g[0] *= alpha;
+    g[1] *= alpha;
+    g[2] *= alpha;
+  }
+  if (Xh) {
+    const R* u = U + 5 * s;
+    const R* gr = G + 15 * s;
+    const R ir = quot(R(1), u[0]);
+    const R v[3] = {u[1] * ir, u[2] * ir, u[3] * ir};
+    R divv = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) divv += (gr[3 * (1 + a) + a] - v[a] * gr[a]) * ir;
+    R rate = -(v[0] * g[0] + v[1] * g[1] + v[2] * g[2] + xi * divv);
+    if (hp.predictor_frame == 0) rate += (R)w[3 * s] * g[0] + (R)w[3 * s + 1] * g[1] + (R)w[3 * s + 2] * g[2];
+    const double dt = seg_dt(segs, dt_src, seg, 0.0);
+    Xh[s] = xi + (R)(0.5 * dt) * rate;
+  }
+  if (recx) recx[s] = XCell<R>{xi, {g[0], g[1], g[2]}};
 }
 
 template <typename R>
@@ -586,7 +734,9 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
                                                      const double* __restrict__ spos, const double* __restrict__ w,
                                                      double* __restrict__ posc, double* __restrict__ wc,
                                                      const SegStatus* dt_src, DevStatus* st, SegStatus* segst,
-                                                     bool drift_from_slots) {
+                                                     bool drift_from_slots, const double* __restrict__ Ss,
+                                                     const R* __restrict__ phiX, const float* __restrict__ machF,
+                                                     double* __restrict__ Sc, float* __restrict__ machc) {
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int seg = sseg[s];
@@ -595,15 +745,49 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
   cell_flux_sum(s, counts, soff, csr, phi, acc);
 #pragma unroll
   for (int q = 0; q < 5; ++q) Q[q] = Qs[5 * s + q] + acc[q];
-  // Floors at the cell centre after the step, with the time-n volume.
   const double V = geo[4 * s];
+  const double gamma = hp.gamma, g1 = gamma - 1.0;
+  // Entropy switch (Sec. 4.3): the cell's largest face Mach number decides
+  // whether its pressure follows the entropy (no shock) or the energy.
+  double Snew = 0.0;
+  float mx = 0.0f;
+  bool from_entropy = false;
+  if (Ss) {
+    const int nfc = (int)(counts[s] >> 32);
+    const int32_t* list = csr + sell_slot(soff, s, 0);
+    double accX = 0.0;
+    for (int e = 0; e < nfc; ++e) {
+      const int32_t cf = list[64 * e];
+      const int64_t fid = cf & 0x7fffffff;
+      accX += (cf < 0 ? 1.0 : -1.0) * (double)phiX[fid];
+      mx = fmaxf(mx, machF[fid]);
+    }
+    Snew = Ss[s] + accX;
+    if ((double)mx < hp.mach_threshold) {
+      const double m = Q[0];
+      const double P = (Snew / m) * pow(m / V, gamma);
+      Q[4] = P * V / g1 + 0.5 * (Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]) / m;
+      from_entropy = true;
+    }
+  }
+  // Floors at the cell centre after the step, with the volume of the mesh
+  // the fluxes used.
   double u[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) u[q] = Q[q] / V;
-  if (apply_floors(u, hp.gamma - 1.0, hp.rho_floor, hp.p_floor)) {
+  const bool floored = apply_floors(u, g1, hp.rho_floor, hp.p_floor);
+  if (floored) {
     atomicAdd(&segst[seg].floor_hits[3], 1ull);
 #pragma unroll
     for (int q = 0; q < 5; ++q) Q[q] = u[q] * V;
+  }
+  if (Ss) {
+    if (!from_entropy || floored) {
+      // The energy was integrated (or floored): the entropy follows the state.
+      const double ir = 1.0 / u[0];
+      const double P = g1 * (u[4] - 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * ir);
+      Snew = Q[0] * P / pow(u[0], gamma);
+    }
   }
   const int64_t c = perm[s];
   int bad = 0;
@@ -623,6 +807,11 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
     if (x >= hp.L[a]) x -= hp.L[a];
     posc[3 * c + a] = x;
     wc[3 * c + a] = wa;
+  }
+  if (Ss) {
+    Sc[c] = Snew;
+    if (machc) machc[c] = mx;
+    if (!isfinite(Snew)) bad = 1;
   }
   if (bad) seg_fail(st, segst, seg, F_NONFINITE, (int)s);
 }
@@ -686,7 +875,27 @@ __global__ void k_init_charges(const SegDesc* __restrict__ segs, const int32_t* 
   Q[5 * c + 4] = (P / (gamma - 1.0) + ke) * V;
 }
 
+// Entropy charges S = m P rho^-gamma (Sec. 4.3) of primitive states, in
+// caller order.
+__global__ void k_init_entropy(const SegDesc* __restrict__ segs, const int32_t* __restrict__ sseg, int64_t n,
+                               const double* prim, const int32_t* __restrict__ perm,
+                               const double* __restrict__ geo, double* S) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const double gamma = segs[sseg[s]].hp.gamma;
+  const int64_t c = perm[s];
+  const double rho = prim[5 * c], P = prim[5 * c + 4];
+  S[c] = rho * geo[4 * s] * P / pow(rho, gamma);
+}
+
 }  // namespace
+
+void launch_init_entropy(const SegDesc* segs, const int32_t* sseg, int64_t n, const double* prim_slots,
+                         const int32_t* perm, const double* geo, double* S_slots, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_init_entropy, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n,
+                     prim_slots, perm, geo, S_slots);
+}
 
 template <typename R>
 void launch_cell_state(const SegDesc* segs, const int32_t* sseg, int64_t n, const double* Q_slots,
@@ -727,13 +936,35 @@ void launch_predict(const SegDesc* segs, const int32_t* sseg, int64_t n, const R
 template <typename R>
 void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
                  const FluxCell<R>* rec, const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst,
-                 hipStream_t st) {
+                 hipStream_t st, const XCell<R>* recx, R* phiX, float* machF) {
   if (nf_host <= 0) return;
   // Enough resident blocks to fill the chip; each strides through its XCD's
   // part of the (device-counted) face list.
   const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(nf_host, kThreads), 4096);
-  hipLaunchKernelGGL(k_flux<R>, dim3(blocks), dim3(kThreads), 0, st, segs, nf_host, nf_dev, faces, rec, dt_src,
-                     dt_fixed, phi, segst);
+  if (recx)
+    hipLaunchKernelGGL((k_flux<R, true>), dim3(blocks), dim3(kThreads), 0, st, segs, nf_host, nf_dev, faces, rec,
+                       dt_src, dt_fixed, phi, segst, recx, phiX, machF);
+  else
+    hipLaunchKernelGGL((k_flux<R, false>), dim3(blocks), dim3(kThreads), 0, st, segs, nf_host, nf_dev, faces, rec,
+                       dt_src, dt_fixed, phi, segst, nullptr, nullptr, nullptr);
+}
+
+template <typename R>
+void launch_entropy_state(int64_t n, const int32_t* perm, const double* geo, const double* S_slots, double* Ss,
+                          R* X, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_entropy_state<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, n, perm, geo,
+                     S_slots, Ss, X);
+}
+
+template <typename R>
+void launch_entropy_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* X,
+                             const unsigned long long* counts, const unsigned long long* soff, const NbrEntry<R>* nbr,
+                             const double* minv, int limit, const R* U, const R* G, const double* w,
+                             const SegStatus* dt_src, R* Xh, XCell<R>* recx, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_entropy_gradient<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, X,
+                     counts, soff, nbr, minv, limit, U, G, w, dt_src, Xh, recx);
 }
 
 template <typename R>
@@ -741,11 +972,12 @@ void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const un
                    const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo,
                    const int32_t* perm, const double* Qs, double* Q_slots, const double* spos, const double* w,
                    double* pos_slots, double* w_slots, const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst,
-                   hipStream_t st, bool drift_from_slots) {
+                   hipStream_t st, bool drift_from_slots, const double* Ss, const R* phiX, const float* machF,
+                   double* S_slots, float* mach_slots) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_update<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, counts, soff,
                      csr, phi, geo, perm, Qs, Q_slots, spos, w, pos_slots, w_slots, dt_src, st_dev, segst,
-                     drift_from_slots);
+                     drift_from_slots, Ss, phiX, machF, S_slots, mach_slots);
 }
 
 template <typename R>
@@ -855,11 +1087,19 @@ void launch_copy_rows(const double* src, double* dst, int64_t n, int width, hipS
   template void launch_predict<R>(const SegDesc*, const int32_t*, int64_t, const R*, const R*, const double*,     \
                                   const SegStatus*, double, R*, SegStatus*, hipStream_t);                         \
   template void launch_flux<R>(const SegDesc*, int64_t, const unsigned long long*, const Face*,                    \
-                               const FluxCell<R>*, const SegStatus*, double, R*, SegStatus*, hipStream_t);        \
+                               const FluxCell<R>*, const SegStatus*, double, R*, SegStatus*, hipStream_t,         \
+                               const XCell<R>*, R*, float*);                                                      \
+  template void launch_entropy_state<R>(int64_t, const int32_t*, const double*, const double*, double*, R*,       \
+                                        hipStream_t);                                                             \
+  template void launch_entropy_gradient<R>(const SegDesc*, const int32_t*, int64_t, const R*,                     \
+                                           const unsigned long long*, const unsigned long long*,                  \
+                                           const NbrEntry<R>*, const double*, int, const R*, const R*,            \
+                                           const double*, const SegStatus*, R*, XCell<R>*, hipStream_t);          \
   template void launch_update<R>(const SegDesc*, const int32_t*, int64_t, const unsigned long long*,              \
                                  const unsigned long long*, const int32_t*, const R*, const double*,              \
                                  const int32_t*, const double*, double*, const double*, const double*, double*,   \
-                                 double*, const SegStatus*, DevStatus*, SegStatus*, hipStream_t, bool);           \
+                                 double*, const SegStatus*, DevStatus*, SegStatus*, hipStream_t, bool,            \
+                                 const double*, const R*, const float*, double*, float*);                         \
   template void launch_half_park<R>(const SegDesc*, const int32_t*, int64_t, const int32_t*, const R*,            \
                                     const double*, const SegStatus*, const double*, double*, R*, double*,         \
                                     hipStream_t);                                                                 \

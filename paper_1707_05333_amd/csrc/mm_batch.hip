@@ -196,6 +196,7 @@ mm_status mm_batch_admit(mm_batch* b, const mm_params* p, int64_t n, const doubl
   if (!params_ok(p, why)) return b->fail(MM_EINVAL, why);
   if (p->precision != b->precision) return b->fail(MM_EINVAL, "precision differs from the batch's");
   if (p->half_step_mesh) return b->fail(MM_EINVAL, "half_step_mesh is available for single simulations only");
+  if (p->mach_threshold != 0.0) return b->fail(MM_EINVAL, "the entropy switch is available for single simulations only");
   if (!(dt_max > 0.0)) return b->fail(MM_EINVAL, "dt_max must be positive");
   if (n < kMinPoints) return b->fail(MM_EINVAL, "n must be at least 3");
   if (n > b->E.ncap) return b->fail(MM_ECAPACITY, "n exceeds the batch's point capacity");

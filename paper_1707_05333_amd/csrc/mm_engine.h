@@ -54,6 +54,12 @@ struct Engine {
   // mesh is rebuilt.  Reserved only when init is asked for them.
   double* pos_half = nullptr;
   void* Uh_slots = nullptr;
+  // Entropy column (single simulations): X and its half-step value per
+  // cell, the face kernel's records, the face fluxes and Mach numbers, and
+  // the gathered entropy charges.
+  void *Xe = nullptr, *Xh = nullptr, *recx = nullptr, *phiX = nullptr;
+  float* machF = nullptr;
+  double* Ss = nullptr;
   // Segment table and status.
   SegDesc* segs = nullptr;
   SegStatus* segst = nullptr;
@@ -74,8 +80,9 @@ struct Engine {
   std::string err;
 
   // Reserves everything; returns MM_OK or MM_ENOMEM / MM_EHIP with err set.
+  // single: also reserve the half-step mesh and entropy buffers.
   mm_status init(int precision, int64_t ncap, int64_t slot_cap, int64_t fcap, int segcap, hipStream_t stream,
-                 bool half_step_buffers = false);
+                 bool single = false);
   void release();
 
   // Host staging of the segment table, safe to write once returned; then
@@ -92,8 +99,11 @@ struct Engine {
   // half_step: rebuild the mesh at r + w dt/2 after the predictor and take
   // the second gradient, the fluxes and the update on it (single segment,
   // n_slots == n, buffers reserved at init).
+  // S, mach (single segment, buffers reserved at init): the entropy
+  // charges in/out and each cell's largest face Mach number out (Sec. 4.3).
   void enqueue_step(double* pos, double* w, double* Q, int64_t n_slots, const int32_t* slot_seg, int64_t n,
-                    int64_t nbt, bool any_fresh, bool half_step = false);
+                    int64_t nbt, bool any_fresh, bool half_step = false, double* S = nullptr,
+                    float* mach = nullptr);
   // Waits for the stream and copies the status of the launch set and of
   // the first nseg segments to the host mirrors.
   mm_status readback();

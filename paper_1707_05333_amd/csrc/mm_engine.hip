@@ -82,6 +82,7 @@ HydroParams hydro_params(const mm_params& p) {
   h.predictor_frame = p.predictor_frame;
   h.riemann = p.riemann;
   h.pad = 0;
+  h.mach_threshold = p.mach_threshold;
   return h;
 }
 
@@ -98,6 +99,10 @@ bool params_ok(const mm_params* p, std::string& why) {
   if (p->predictor_frame != 0 && p->predictor_frame != 1) { why = "predictor_frame must be 0 or 1"; return false; }
   if (p->half_step_mesh != 0 && p->half_step_mesh != 1) { why = "half_step_mesh must be 0 or 1"; return false; }
   if (p->reserved != 0) { why = "reserved must be 0"; return false; }
+  if (!(p->mach_threshold >= 0.0 && std::isfinite(p->mach_threshold))) {
+    why = "mach_threshold must be finite and non-negative";
+    return false;
+  }
   return true;
 }
 
@@ -109,7 +114,7 @@ double dt_from_bits(unsigned long long bits) {
 }
 
 mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, int seg_cap, hipStream_t s,
-                       bool half_step_buffers) {
+                       bool single) {
   precision = prec;
   ncap = n_cap;
   slot_cap = s_cap;
@@ -151,9 +156,15 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
   ok &= hipMalloc(&phi, std::max<size_t>(5 * F * rs, 1)) == hipSuccess;
   ok &= dalloc(&w, 3 * N) == hipSuccess;
   ok &= dalloc(&Qs, 5 * N) == hipSuccess;
-  if (half_step_buffers) {
+  if (single) {
     ok &= dalloc(&pos_half, 3 * slot_cap) == hipSuccess;
     ok &= hipMalloc(&Uh_slots, std::max<size_t>(5 * slot_cap * rs, 1)) == hipSuccess;
+    ok &= hipMalloc(&Xe, std::max<size_t>(N * rs, 1)) == hipSuccess;
+    ok &= hipMalloc(&Xh, std::max<size_t>(N * rs, 1)) == hipSuccess;
+    ok &= hipMalloc(&recx, std::max<size_t>(N * 4 * rs, 1)) == hipSuccess;
+    ok &= hipMalloc(&phiX, std::max<size_t>(F * rs, 1)) == hipSuccess;
+    ok &= dalloc(&machF, F) == hipSuccess;
+    ok &= dalloc(&Ss, N) == hipSuccess;
   }
   ok &= dalloc(&segs, segcap) == hipSuccess;
   ok &= dalloc(&segst, segcap) == hipSuccess;
@@ -177,7 +188,7 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
 void Engine::release() {
   void* ptrs[] = {key, perm, sseg, deferred, spos, geo, rmax2, minv, bcount, boff, scan_tmp, counts, off, sw, soff,
                   stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, pos_half, Uh_slots,
-                  segs, segst, st};
+                  Xe, Xh, recx, phiX, machF, Ss, segs, segst, st};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   void* hptrs[] = {segs_host, segst_host, st_host};
@@ -226,15 +237,23 @@ namespace {
 
 template <typename R>
 void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n, bool any_fresh, bool half,
-                   int64_t nbt) {
+                   int64_t nbt, double* S_slots, float* mach_slots) {
+  static_assert(sizeof(XCell<R>) == 4 * sizeof(R), "entropy records are four values");
+  const bool ent = S_slots != nullptr;
+  R *Xe = (R*)E.Xe, *Xh = (R*)E.Xh;
+  XCell<R>* recx = (XCell<R>*)E.recx;
   const unsigned long long* nf_dev = &E.st->n_faces;
   R *U = (R*)E.U, *Uh = (R*)E.Uh, *phi = (R*)E.phi;
   FluxCell<R>* rec = (FluxCell<R>*)E.rec;
   if (any_fresh) launch_init_charges(E.segs, E.sseg, n, Q, E.perm, E.geo, Q, 1, E.stream);
   launch_cell_state<R>(E.segs, E.sseg, n, Q, E.perm, E.geo, E.Qs, U, E.w, E.st, E.segst, E.stream);
+  if (ent) launch_entropy_state<R>(n, E.perm, E.geo, S_slots, E.Ss, Xe, E.stream);
   E.mark(4);
-  launch_gradient<R>(E.segs, E.sseg, n, U, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv, kLimitMaskBit0, nullptr, E.w, E.segst,
-                     0.0, Uh, nullptr, nullptr, nullptr, E.segst, E.stream);
+  launch_gradient<R>(E.segs, E.sseg, n, U, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv, kLimitMaskBit0,
+                     ent ? (R*)E.G : nullptr, E.w, E.segst, 0.0, Uh, nullptr, nullptr, nullptr, E.segst, E.stream);
+  if (ent)
+    launch_entropy_gradient<R>(E.segs, E.sseg, n, Xe, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv,
+                               kLimitMaskBit0, U, (const R*)E.G, E.w, E.segst, Xh, nullptr, E.stream);
   if (half) {
     // Half-step geometry: park U_half and w in slot order, move the
     // generators by w dt/2, rebuild the mesh there and bring the parked
@@ -250,24 +269,31 @@ void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n
   E.mark(5);
   launch_gradient<R>(E.segs, E.sseg, n, Uh, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv, kLimitMaskBit1, nullptr, E.w, nullptr,
                      0.0, nullptr, rec, E.geo, E.spos, E.segst, E.stream);
+  if (ent)
+    launch_entropy_gradient<R>(E.segs, E.sseg, n, Xh, E.counts, E.soff, (const NbrEntry<R>*)E.nbr, E.minv,
+                               kLimitMaskBit1, nullptr, nullptr, nullptr, E.segst, nullptr, recx, E.stream);
   E.mark(6);
-  launch_flux<R>(E.segs, E.fcap, nf_dev, E.faces, rec, E.segst, 0.0, phi, E.segst, E.stream);
+  launch_flux<R>(E.segs, E.fcap, nf_dev, E.faces, rec, E.segst, 0.0, phi, E.segst, E.stream, ent ? recx : nullptr,
+                 (R*)E.phiX, E.machF);
   E.mark(7);
   launch_update<R>(E.segs, E.sseg, n, E.counts, E.soff, E.csr, phi, E.geo, E.perm, E.Qs, Q, E.spos, E.w, pos, w_slots, E.segst,
-                   E.st, E.segst, E.stream, half);
+                   E.st, E.segst, E.stream, half, ent ? E.Ss : nullptr, (const R*)E.phiX, E.machF, S_slots,
+                   mach_slots);
 }
 
 }  // namespace
 
 void Engine::enqueue_step(double* pos, double* w_slots, double* Q, int64_t n_slots, const int32_t* slot_seg,
-                          int64_t n_cells, int64_t n_buckets, bool any_fresh, bool half_step) {
-  const bool half = half_step && pos_half && Uh_slots && n_slots == n_cells && !slot_seg;
+                          int64_t n_cells, int64_t n_buckets, bool any_fresh, bool half_step, double* S,
+                          float* mach) {
+  const bool half = half_step && pos_half && Uh_slots && n_slots == n_cells && !slot_seg && !S;
+  if (!(Ss && n_slots == n_cells && !slot_seg)) S = nullptr, mach = nullptr;
   remeshed = half;
   reset_status();
   enqueue_tessellation(pos, n_slots, slot_seg, n_cells, n_buckets);
   mark(3);
-  if (precision == MM_MIXED) enqueue_hydro<float>(*this, pos, w_slots, Q, n_cells, any_fresh, half, n_buckets);
-  else enqueue_hydro<double>(*this, pos, w_slots, Q, n_cells, any_fresh, half, n_buckets);
+  if (precision == MM_MIXED) enqueue_hydro<float>(*this, pos, w_slots, Q, n_cells, any_fresh, half, n_buckets, S, mach);
+  else enqueue_hydro<double>(*this, pos, w_slots, Q, n_cells, any_fresh, half, n_buckets, S, mach);
   mark(8);
 }
 

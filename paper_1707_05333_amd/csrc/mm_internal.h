@@ -84,6 +84,7 @@ struct HydroParams {
   int predictor_frame;
   int riemann;      // kRiemannHllc or kRiemannHll (the MM_HLLC / MM_HLL values)
   int pad;
+  double mach_threshold;   // entropy switch (Sec. 4.3); 0: energy equation only
 };
 
 // One segment as the kernels see it.
@@ -263,16 +264,40 @@ void launch_predict(const SegDesc* segs, const int32_t* sseg, int64_t n, const R
                     const SegStatus* dt_src, double dt_fixed, R* U_half, SegStatus* segst, hipStream_t st);
 // nf_dev (device count, may be NULL) overrides nf_host, which then only
 // bounds the launch.
+// Entropy charges S = m P rho^-gamma of primitive states (slot order).
+void launch_init_entropy(const SegDesc* segs, const int32_t* sseg, int64_t n, const double* prim_slots,
+                         const int32_t* perm, const double* geo, double* S_slots, hipStream_t st);
+// Entropy column X = rho A (Sec. 4.3) of a cell for the face kernel: its
+// half-step value and limited gradient.
+template <typename R>
+struct XCell {
+  R X, g[3];
+};
+// X = S / V in internal order, with S (the caller's entropy charges, slot
+// order) gathered into Ss.
+template <typename R>
+void launch_entropy_state(int64_t n, const int32_t* perm, const double* geo, const double* S_slots, double* Ss,
+                          R* X, hipStream_t st);
+// Least-squares gradient of X with the S10 limiter (limit as in
+// launch_gradient).  With Xh: the half-step X from the predictor rate
+// -div(X v) (+ w . grad X), needing the time-n U, its gradient G and w.
+// With recx: the face kernel's records.
+template <typename R>
+void launch_entropy_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n, const R* X,
+                             const unsigned long long* counts, const unsigned long long* soff, const NbrEntry<R>* nbr,
+                             const double* minv, int limit, const R* U, const R* G, const double* w,
+                             const SegStatus* dt_src, R* Xh, XCell<R>* recx, hipStream_t st);
 template <typename R>
 void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
                  const FluxCell<R>* rec, const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst,
-                 hipStream_t st);
+                 hipStream_t st, const XCell<R>* recx = nullptr, R* phiX = nullptr, float* machF = nullptr);
 template <typename R>
 void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* counts,
                    const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo, const int32_t* perm, const double* Qs,
                    double* Q_slots, const double* spos, const double* w, double* pos_slots, double* w_slots,
                    const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st,
-                   bool drift_from_slots = false);
+                   bool drift_from_slots = false, const double* Ss = nullptr, const R* phiX = nullptr,
+                   const float* machF = nullptr, double* S_slots = nullptr, float* mach_slots = nullptr);
 // Half-step mesh: U_half and w of internal cell s go to slot perm[s], and
 // pos_half[slot] = wrap(pos[slot] + w dt/2) (single segment, slots = cells).
 template <typename R>

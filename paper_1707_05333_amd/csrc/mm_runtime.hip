@@ -330,8 +330,8 @@ mm_status mm_fluxes(mm_ctx* c, const void* U_half, const void* grad_half, const 
   return MM_OK;
 }
 
-mm_status mm_step(mm_ctx* c, int64_t n, double* pos, double* w, double* Q, double dt_max, mm_step_info* info) {
-  if (!c) return MM_EINVAL;
+static mm_status step_common(mm_ctx* c, int64_t n, double* pos, double* w, double* Q, double* S, float* mach,
+                             double dt_max, mm_step_info* info) {
   if (!pos || !w || !Q) return fail(c, MM_EINVAL, "pos, w or Q is NULL");
   if (mm_status r = check_n(c, n)) return r;
   if (!(dt_max > 0.0)) return fail(c, MM_EINVAL, "dt_max must be positive");
@@ -339,12 +339,35 @@ mm_status mm_step(mm_ctx* c, int64_t n, double* pos, double* w, double* Q, doubl
   c->grid = make_grid(c->p, n, c->E.rfac, 0);
   if (mm_status r = put_segment(c, dt_max)) return r;
   c->E.n = n;
-  c->E.enqueue_step(pos, w, Q, n, nullptr, n, c->grid.nbt, false, c->p.half_step_mesh != 0);
+  c->E.enqueue_step(pos, w, Q, n, nullptr, n, c->grid.nbt, false, c->p.half_step_mesh != 0, S, mach);
   if (mm_status r = readback(c)) return r;
   fill_info(c, info, dt_max);
   c->E.finish_timing();
   if (mm_status r = check_status(c)) return r;
   finish_mesh(c, n);
+  return MM_OK;
+}
+
+mm_status mm_step(mm_ctx* c, int64_t n, double* pos, double* w, double* Q, double dt_max, mm_step_info* info) {
+  if (!c) return MM_EINVAL;
+  if (c->p.mach_threshold > 0.0) return fail(c, MM_EINVAL, "mach_threshold > 0 needs mm_step_entropy");
+  return step_common(c, n, pos, w, Q, nullptr, nullptr, dt_max, info);
+}
+
+mm_status mm_step_entropy(mm_ctx* c, int64_t n, double* pos, double* w, double* Q, double* S, float* mach,
+                          double dt_max, mm_step_info* info) {
+  if (!c) return MM_EINVAL;
+  if (!S) return fail(c, MM_EINVAL, "S is NULL");
+  if (c->p.half_step_mesh) return fail(c, MM_EINVAL, "the entropy column is not combined with half_step_mesh");
+  return step_common(c, n, pos, w, Q, S, mach, dt_max, info);
+}
+
+mm_status mm_init_entropy(mm_ctx* c, const double* prim, double* S) {
+  if (!c) return MM_EINVAL;
+  if (mm_status r = need_mesh(c)) return r;
+  if (!prim || !S) return fail(c, MM_EINVAL, "prim or S is NULL");
+  launch_init_entropy(c->E.segs, c->E.sseg, c->E.n, prim, c->E.perm, c->E.geo, S, c->E.stream);
+  HIPCHECK(c, hipGetLastError());
   return MM_OK;
 }
 

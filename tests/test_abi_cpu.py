@@ -39,8 +39,9 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "mm.h"
 int main(void) {
-  printf("mm_params %zu %zu %zu %zu %zu\n", sizeof(mm_params), offsetof(mm_params, gamma),
-         offsetof(mm_params, precision), offsetof(mm_params, predictor_frame), offsetof(mm_params, half_step_mesh));
+  printf("mm_params %zu %zu %zu %zu %zu %zu\n", sizeof(mm_params), offsetof(mm_params, gamma),
+         offsetof(mm_params, precision), offsetof(mm_params, predictor_frame), offsetof(mm_params, half_step_mesh),
+         offsetof(mm_params, mach_threshold));
   printf("mm_step_info %zu %zu %zu\n", sizeof(mm_step_info), offsetof(mm_step_info, floor_hits),
          offsetof(mm_step_info, flags));
   printf("mm_mesh_view %zu %zu\n", sizeof(mm_mesh_view), offsetof(mm_mesh_view, faces));
@@ -60,7 +61,7 @@ int main(void) {
                for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
     P, S, V = M.Params, M.StepInfo, M.MeshView
     assert out["mm_params"] == [ctypes.sizeof(P), P.gamma.offset, P.precision.offset, P.predictor_frame.offset,
-                                P.half_step_mesh.offset]
+                                P.half_step_mesh.offset, P.mach_threshold.offset]
     assert out["mm_step_info"] == [ctypes.sizeof(S), S.floor_hits.offset, S.flags.offset]
     assert out["mm_mesh_view"] == [ctypes.sizeof(V), V.faces.offset]
     I, R, RR, SS = M.SimInfo, M.Request, M.RequestResult, M.ServeStats

@@ -1,0 +1,132 @@
+"""Entropy switch on the GPU (Sec. 4.3): X = rho A carried by the mass flux,
+face Mach numbers from the Riemann problems, the pressure of unshocked cells
+from the entropy.  Parity with the oracle element by element (charges,
+entropy charges, the switch decision of every cell), the threshold-zero
+identity with mm_step, a uniform entropic function kept to rounding, and
+the refusals (mm_step with a threshold, the half-step mesh, batches)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import dev, host, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _gpu_run(M, wl, nsteps, **over):
+    import torch
+    mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, **dict(wl.params, **over)))
+    pos = dev(wl.pos)
+    mm.tessellate(pos)
+    prim = dev(wl.prim)
+    Q, S = mm.init_charges(prim), mm.init_entropy(prim)
+    w = torch.empty_like(pos)
+    mach = torch.empty(wl.n, dtype=torch.float32, device=pos.device)
+    for _ in range(nsteps):
+        mm.step_entropy(pos, w, Q, S, mach)
+    out = host(pos), host(Q), host(S), host(mach)
+    mm.close()
+    return out
+
+
+def _orc_run(orc, wl, nsteps, **over):
+    p = orc.make_params(wl.box, **dict(wl.params, **over))
+    om = orc.tessellate(wl.pos, wl.box)
+    Q, S = orc.init_charges(om, p, wl.prim), orc.init_entropy(om, p, wl.prim)
+    x = wl.pos.copy()
+    for _ in range(nsteps):
+        x, Q, S, w, dt, cnt, mach = orc.step_entropy(x, Q, S, p)
+    return x, Q, S, mach
+
+
+@pytest.mark.parametrize("name", ["sod_strip", "gresho_16", "sod_paper_hll"])
+def test_entropy_step_parity(orc, name):
+    wl = {"sod_strip": lambda: W.c2_sod(shape=(64, 8, 8), box=(4.0, 0.5, 0.5)),
+          "gresho_16": lambda: W.gresho(16),
+          "sod_paper_hll": lambda: W.sod_paper(k=4, riemann="hll")}[name]()
+    print(f"[case] entropy parity {name} n={wl.n}", flush=True)
+    pg, Qg, Sg, mg = _gpu_run(__import__("paper_1707_05333_amd"), wl, 4, mach_threshold=1.1)
+    po, Qo, So, mo = _orc_run(orc, wl, 4, mach_threshold=1.1)
+    assert scaled_err(Qg, Qo) < TOL
+    assert np.abs(Sg - So).max() < TOL * np.abs(So).max()
+    assert np.abs(pg - po).max() < TOL
+    np.testing.assert_allclose(mg, mo, rtol=1e-6)
+    assert np.array_equal(mg < 1.1, mo < 1.1)
+
+
+def test_threshold_zero_matches_mm_step_bitwise():
+    import torch
+    import paper_1707_05333_amd as M
+    wl = W.c2_sod(shape=(64, 8, 8), box=(4.0, 0.5, 0.5))
+    print(f"[case] entropy threshold zero n={wl.n}", flush=True)
+    outs = []
+    for ent in (False, True):
+        mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, **wl.params))
+        pos = dev(wl.pos)
+        mm.tessellate(pos)
+        Q = mm.init_charges(dev(wl.prim))
+        S = mm.init_entropy(dev(wl.prim))
+        w = torch.empty_like(pos)
+        for _ in range(3):
+            (mm.step_entropy(pos, w, Q, S) if ent else mm.step(pos, w, Q))
+        outs.append((host(pos), host(Q)))
+        mm.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_uniform_entropic_function_is_kept():
+    import paper_1707_05333_amd as M
+    pos = W.jittered_lattice((24, 24, 24), (1, 1, 1), jitter=0.2, seed=3)
+    wl = W.uniform_state(pos, (1, 1, 1), rho=1.3, vel=(0.4, -0.2, 0.1), P=0.7)
+    print(f"[case] entropy uniform A n={wl.n}", flush=True)
+    spread = {}
+    for mth in (0.0, 1.1):
+        p, Q, S, mach = _gpu_run(M, wl, 10, mach_threshold=mth)
+        A = S / Q[:, 0]
+        spread[mth] = float(np.ptp(A) / A.mean())
+        assert mach.max() < 1.1
+    print("[entropy] A spread", spread, flush=True)
+    assert spread[1.1] < 1e-13 and spread[0.0] > 1e-7
+
+
+def test_refusals():
+    import torch
+    import paper_1707_05333_amd as M
+    wl = W.c1_uniform_random_velocity()
+    print(f"[case] entropy refusals n={wl.n}", flush=True)
+    mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, mach_threshold=1.1, **wl.params))
+    pos = dev(wl.pos)
+    mm.tessellate(pos)
+    Q = mm.init_charges(dev(wl.prim))
+    w = torch.empty_like(pos)
+    with pytest.raises(M.MMError) as e:
+        mm.step(pos, w, Q)
+    assert e.value.name == "MM_EINVAL"
+    mm.close()
+    mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, mach_threshold=1.1, half_step_mesh=1, **wl.params))
+    mm.tessellate(pos)
+    S = mm.init_entropy(dev(wl.prim))
+    with pytest.raises(M.MMError) as e:
+        mm.step_entropy(pos, w, Q, S)
+    assert e.value.name == "MM_EINVAL"
+    mm.close()
+    b = M.Batch(64 << 20, max_sims=2, precision="fp64")
+    with pytest.raises(M.MMError) as e:
+        b.admit(M.make_params(box=wl.box, mach_threshold=1.1, **wl.params), dev(wl.pos), dev(wl.prim))
+    assert e.value.name == "MM_EINVAL"
+    b.close()
+
+
+def test_mixed_precision_entropy_step():
+    # The float path of the entropy column (X, its gradients and face
+    # fluxes in float; charges in double) against the FP64 path.
+    import paper_1707_05333_amd as M
+    wl = W.c2_sod(shape=(64, 8, 8), box=(4.0, 0.5, 0.5))
+    print(f"[case] entropy mixed n={wl.n}", flush=True)
+    p64, Q64, S64, m64 = _gpu_run(M, wl, 5, mach_threshold=1.1)
+    pmx, Qmx, Smx, mmx = _gpu_run(M, wl, 5, mach_threshold=1.1, precision="mixed")
+    rho64, rhomx = Q64[:, 0], Qmx[:, 0]
+    assert np.abs(rhomx - rho64).sum() / np.abs(rho64).sum() < 1e-4
+    assert np.abs(Smx - S64).sum() / np.abs(S64).sum() < 1e-4
