@@ -171,7 +171,7 @@ __global__ void k_hash(const double* __restrict__ pos, int64_t n_slots, const in
     const int bx = bucket_coord(x, g.inv_hb[0], g.nb[0]);
     const int by = bucket_coord(y, g.inv_hb[1], g.nb[1]);
     const int bz = bucket_coord(z, g.inv_hb[2], g.nb[2]);
-    k += bx + g.nb[0] * (by + g.nb[1] * bz);
+    k += bucket_key(g.nb, bx, by, bz);
   } else {
     seg_fail(st, segst, seg, F_BADPOS, (int)i);
   }

@@ -255,7 +255,7 @@ __device__ inline StencilBucket stencil_bucket(const TessArgs& A, const GridPara
       kk[a] = t < 0 ? -1 : (t >= g.nb[a] ? 1 : 0);
       bb[a] = t - kk[a] * g.nb[a];
     }
-    const int64_t key = g.base + bb[0] + g.nb[0] * (bb[1] + g.nb[1] * bb[2]);
+    const int64_t key = g.base + bucket_key(g.nb, bb[0], bb[1], bb[2]);
     const unsigned long long b0 = A.boff[key];
     B.bst = (int)b0;
     B.cnt = (int)(A.boff[key + 1] - b0);
