@@ -32,7 +32,12 @@
 //           alternative (same item) uses the same wave-speed bounds.
 //   R-floor floors keep the velocity and pressure and raise the density, or
 //           keep density and velocity and raise the pressure (Sec. 4.1,
-//           floors paragraph; values are not given by the paper).
+//           floors paragraph; values are not given by the paper).  A face
+//           state whose reconstruction would need a floor is replaced by its
+//           cell's half-step state (first order on that side of the face):
+//           component-wise extrapolation across a large density jump can
+//           pair a small density with a large momentum, a velocity that no
+//           floor repairs.
 //   R-box   the starting cell is the box r_i +- L/2, the exact Voronoi cell
 //           of i's own periodic images (Sec. 3, the large box each cell is cut from).
 //   R-area  a face is kept iff its computed area is positive.  (A threshold
@@ -829,7 +834,8 @@ struct FaceSetup {
   double UL[5], UR[5];
   double n[3];   // unit normal from i toward the neighbour image
   double wt[3];  // face velocity
-  double rhoL0, rhoR0;   // reconstructed densities before the face floors
+  double rhoL0, rhoR0;   // densities of the face states (before any floor)
+  bool fbL, fbR;         // a side fell back to its cell's half-step state
   V3 fi, fj;             // face centroid minus each side's centroid
 };
 int setup_face(const Mesh& M, const Params& p, int64_t i, size_t e, const double* Uh, const double* Gh,
@@ -863,13 +869,22 @@ int setup_face(const Mesh& M, const Params& p, int64_t i, size_t e, const double
     S.UL[q] = Ui + dm_factor(p.theta, Uj - Ui, Di) * Di;
     S.UR[q] = Uj + dm_factor(p.theta, Ui - Uj, Dj) * Dj;
   }
-  S.rhoL0 = S.UL[0];
-  S.rhoR0 = S.UR[0];
   S.fi = fi;
   S.fj = fj;
+  // R-floor: a side whose reconstruction needs a floor takes its cell's
+  // half-step state, which the predictor has already floored.
   int hits = 0;
-  hits += apply_floors(S.UL, p) > 0;
-  hits += apply_floors(S.UR, p) > 0;
+  double t[5];
+  std::copy(S.UL, S.UL + 5, t);
+  S.fbL = apply_floors(t, p) > 0;
+  if (S.fbL) std::copy(Uh + 5 * i, Uh + 5 * i + 5, S.UL);
+  std::copy(S.UR, S.UR + 5, t);
+  S.fbR = apply_floors(t, p) > 0;
+  if (S.fbR) std::copy(Uh + 5 * (int64_t)j, Uh + 5 * (int64_t)j + 5, S.UR);
+  hits += S.fbL;
+  hits += S.fbR;
+  S.rhoL0 = S.UL[0];
+  S.rhoR0 = S.UR[0];
   return hits;
 }
 
@@ -1002,8 +1017,8 @@ int fluxes(const Mesh& M, const Params& p, const double* Uh, const double* Gh, c
         const double* gj = gXh + 3 * (int64_t)j;
         const double Di = gi[0] * S.fi.x + gi[1] * S.fi.y + gi[2] * S.fi.z;
         const double Dj = gj[0] * S.fj.x + gj[1] * S.fj.y + gj[2] * S.fj.z;
-        const double XL = Xh[i] + dm_factor(p.theta, Xh[j] - Xh[i], Di) * Di;
-        const double XR = Xh[j] + dm_factor(p.theta, Xh[i] - Xh[j], Dj) * Dj;
+        const double XL = S.fbL ? Xh[i] : Xh[i] + dm_factor(p.theta, Xh[j] - Xh[i], Di) * Di;
+        const double XR = S.fbR ? Xh[j] : Xh[j] + dm_factor(p.theta, Xh[i] - Xh[j], Dj) * Dj;
         Prim L = to_prim(S.UL, p.gamma), R = to_prim(S.UR, p.gamma);
         for (int a = 0; a < 3; ++a) {
           L.v[a] -= S.wt[a];

@@ -91,6 +91,17 @@ __device__ inline void state_rate(const T U[5], const T g[15], const T wv[3], T 
   }
 }
 
+// Pressure a face solver takes from a conserved state.  In FP32 the
+// difference E - rho v^2 / 2 resolves a pressure only down to about 6e-8 of
+// the kinetic energy density, so a state floored at a pressure below that
+// (cold gas moving fast) can come back slightly negative; the FP32 solver
+// raises it to the floor.  FP64 states pass through unchanged.
+template <typename T>
+__device__ inline T face_pressure(T P, T p_floor) {
+  if constexpr (sizeof(T) == 4) return P > p_floor ? P : p_floor;
+  return P;
+}
+
 // Euler flux along unit normal n of a face-frame state (rho, v, P).
 // ig1 = 1 / (gamma - 1).
 template <typename T>
@@ -111,7 +122,7 @@ __device__ inline void euler_flux(T rho, const T v[3], T P, const T n[3], T ig1,
 // |wt|^2/2 F_rho).  The reciprocal densities are formed once per side.
 template <typename T>
 __device__ inline void moving_flux(const T UL[5], const T UR[5], const T n[3], const T wt[3], T gamma, bool hll,
-                                   T F[5]) {
+                                   T p_floor, T F[5]) {
   const T g1 = gamma - T(1);
   const T ig1 = quot(T(1), g1);
   const T rL = UL[0], rR = UR[0];
@@ -122,8 +133,8 @@ __device__ inline void moving_flux(const T UL[5], const T UR[5], const T n[3], c
     vL[a] = UL[1 + a] * irL;
     vR[a] = UR[1 + a] * irR;
   }
-  const T PL = g1 * (UL[4] - T(0.5) * (UL[1] * vL[0] + UL[2] * vL[1] + UL[3] * vL[2]));
-  const T PR = g1 * (UR[4] - T(0.5) * (UR[1] * vR[0] + UR[2] * vR[1] + UR[3] * vR[2]));
+  const T PL = face_pressure(g1 * (UL[4] - T(0.5) * (UL[1] * vL[0] + UL[2] * vL[1] + UL[3] * vL[2])), p_floor);
+  const T PR = face_pressure(g1 * (UR[4] - T(0.5) * (UR[1] * vR[0] + UR[2] * vR[1] + UR[3] * vR[2])), p_floor);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     vL[a] -= wt[a];
@@ -184,7 +195,7 @@ __device__ inline void moving_flux(const T UL[5], const T UR[5], const T n[3], c
 // the face floors; AL, AR the entropic functions of the reconstruction.
 template <typename T>
 __device__ inline void entropy_flux(const T UL[5], const T UR[5], const T n[3], const T wt[3], T gamma, bool hll,
-                                    T AL, T AR, T& FX, float& mach) {
+                                    T p_floor, T AL, T AR, T& FX, float& mach) {
   const T g1 = gamma - T(1);
   const T rL = UL[0], rR = UR[0];
   const T irL = quot(T(1), rL), irR = quot(T(1), rR);
@@ -194,8 +205,8 @@ __device__ inline void entropy_flux(const T UL[5], const T UR[5], const T n[3], 
     vL[a] = UL[1 + a] * irL;
     vR[a] = UR[1 + a] * irR;
   }
-  const T PL = g1 * (UL[4] - T(0.5) * (UL[1] * vL[0] + UL[2] * vL[1] + UL[3] * vL[2]));
-  const T PR = g1 * (UR[4] - T(0.5) * (UR[1] * vR[0] + UR[2] * vR[1] + UR[3] * vR[2]));
+  const T PL = face_pressure(g1 * (UL[4] - T(0.5) * (UL[1] * vL[0] + UL[2] * vL[1] + UL[3] * vL[2])), p_floor);
+  const T PR = face_pressure(g1 * (UR[4] - T(0.5) * (UR[1] * vR[0] + UR[2] * vR[1] + UR[3] * vR[2])), p_floor);
   const T uL = (vL[0] - wt[0]) * n[0] + (vL[1] - wt[1]) * n[1] + (vL[2] - wt[2]) * n[2];
   const T uR = (vR[0] - wt[0]) * n[0] + (vR[1] - wt[1]) * n[1] + (vR[2] - wt[2]) * n[2];
   const T cL = sqrt(gamma * PL * irL), cR = sqrt(gamma * PR * irR);
@@ -576,12 +587,33 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
       UR[q] = uj + dm_limited(theta, ui - uj, Dj);
     }
     const R g1 = (R)(hp.gamma - 1.0);
-    const R rL0 = UL[0], rR0 = UR[0];   // before the face floors
-    int hit = apply_floors(UL, g1, (R)hp.rho_floor, (R)hp.p_floor);
-    hit += apply_floors(UR, g1, (R)hp.rho_floor, (R)hp.p_floor);
+    // A side whose reconstruction would need a floor takes its cell's
+    // half-step state (already floored): extrapolating each component
+    // across a large density jump can pair a small density with a large
+    // momentum, a velocity no floor repairs.
+    bool fbL, fbR;
+    {
+      R t[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) t[q] = UL[q];
+      fbL = apply_floors(t, g1, (R)hp.rho_floor, (R)hp.p_floor) != 0;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) t[q] = UR[q];
+      fbR = apply_floors(t, g1, (R)hp.rho_floor, (R)hp.p_floor) != 0;
+    }
+    if (fbL) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) UL[q] = A.U[q];
+    }
+    if (fbR) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) UR[q] = B.U[q];
+    }
+    const int hit = (int)fbL + (int)fbR;
     if (hit) atomicAdd(&segst[seg].floor_hits[2], (unsigned long long)hit);
+    const R rL0 = UL[0], rR0 = UR[0];
     R Fx[5];
-    moving_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, Fx);
+    moving_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, (R)hp.p_floor, Fx);
     const R scale = (R)(hp.dt * F.A);
 #pragma unroll
     for (int q = 0; q < 5; ++q) phi[5 * f + q] = scale * Fx[q];
@@ -589,11 +621,12 @@ __global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ s
       const XCell<R> XA = recx[F.i], XB = recx[F.j];
       const R Di = XA.g[0] * fi[0] + XA.g[1] * fi[1] + XA.g[2] * fi[2];
       const R Dj = XB.g[0] * fj[0] + XB.g[1] * fj[1] + XB.g[2] * fj[2];
-      const R XL = XA.X + dm_limited(theta, XB.X - XA.X, Di);
-      const R XR = XB.X + dm_limited(theta, XA.X - XB.X, Dj);
+      const R XL = fbL ? XA.X : XA.X + dm_limited(theta, XB.X - XA.X, Di);
+      const R XR = fbR ? XB.X : XB.X + dm_limited(theta, XA.X - XB.X, Dj);
       R FX;
       float mach;
-      entropy_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, quot(XL, rL0), quot(XR, rR0), FX, mach);
+      entropy_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, (R)hp.p_floor, quot(XL, rL0), quot(XR, rR0), FX,
+                   mach);
       phiX[f] = scale * FX;
       machF[f] = mach;
     }

@@ -36,6 +36,7 @@ namespace {
 #define MM_TESS_WAVES 1
 #endif
 constexpr int kWaves = MM_TESS_WAVES;   // cells (wavefronts) per workgroup
+constexpr int kShells = 512;            // distance shells of the second pass
 
 // 10.8 KB per wavefront, so 15 cells fit the 160 KB of LDS of a CU.  The
 // candidate list is only needed while cutting and the vertex copies only in
@@ -267,14 +268,33 @@ __device__ inline StencilBucket stencil_bucket(const TessArgs& A, const GridPara
   return B;
 }
 
+// Whether any of the nv vertices vl (relative to the generator) lies beyond
+// the bisector of image d (|d|^2 = d2) by more than a relative margin: an
+// image that fails it cannot cut the cell (nor any part of it the later
+// cuts leave), so it need not be gathered.  The margin keeps borderline
+// images for the exact test of the cutting loop.
+__device__ inline bool may_cut(const double4* vl, int nv, double dx, double dy, double dz, double d2) {
+  const double h = 0.5 * d2 * (1.0 - 1e-12);
+  bool out = false;
+  for (int t = 0; t < nv; ++t) {
+    const double4 v = vl[t];
+    out |= dx * v.x + dy * v.y + dz * v.z > h;
+  }
+  return out;
+}
+
 // Gathers the neighbour images with lo2 <= |d|^2 < hi2 from the stencil of
 // half-width `ring` into LDS (at most kCands of them); returns their number.
 // Each lane takes two buckets of the stencil at a time and the wave steps
 // through their points together, so the loads of 128 buckets are in flight
 // at once (two memory round trips for the usual 125-bucket stencil).  The
 // generator's own images are not gathered: the box planes stand for them.
+// With a vertex list (vl, nv) of the current cell, images that cannot cut it
+// are left out (a cell next to a much denser region then sees only the few
+// points that face it).
 __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const int s, const double r[3],
-                      const int b[3], const int ring, const double lo2, const double hi2) {
+                      const int b[3], const int ring, const double lo2, const double hi2,
+                      const double4* vl = nullptr, int nv = 0) {
   const int W = 2 * ring + 1, W3 = W * W * W;
   const WidthDiv D = width_div((unsigned)W);
   const int lane = __lane_id();
@@ -301,8 +321,12 @@ __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const 
       const double dx1 = (x1 + B1.sx) - r[0], dy1 = (y1 + B1.sy) - r[1], dz1 = (z1 + B1.sz) - r[2];
       const double d20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
       const double d21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
-      const bool keep0 = v0 && (d20 >= lo2) && (d20 < hi2);
-      const bool keep1 = v1 && (d21 >= lo2) && (d21 < hi2);
+      bool keep0 = v0 && (d20 >= lo2) && (d20 < hi2);
+      bool keep1 = v1 && (d21 >= lo2) && (d21 < hi2);
+      if (vl) {
+        if (keep0) keep0 = may_cut(vl, nv, dx0, dy0, dz0, d20);
+        if (keep1) keep1 = may_cut(vl, nv, dx1, dy1, dz1, d21);
+      }
       const unsigned long long mk0 = __ballot(keep0), mk1 = __ballot(keep1);
       if (keep0) {
         const int idx = nc + __popcll(mk0 & lanes_below());
@@ -616,6 +640,25 @@ __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const Cel
   return 0;
 }
 
+// The live vertices of the cell, compacted into vl; returns their number.
+__device__ int vertex_list(const CellRegs& C, double4* vl) {
+  const int lane = __lane_id();
+  const int n0 = __popcll(C.L0);
+  if ((C.L0 >> lane) & 1ull) vl[__popcll(C.L0 & lanes_below())] = make_double4(C.v0x, C.v0y, C.v0z, 0.0);
+  if ((C.L1 >> lane) & 1ull) vl[n0 + __popcll(C.L1 & lanes_below())] = make_double4(C.v1x, C.v1y, C.v1z, 0.0);
+  wave_sync();
+  return n0 + __popcll(C.L1);
+}
+
+// Points in the cell's own bucket.  Buckets are sized for the mean spacing,
+// so a bucket holding cnt > 4 points marks a region cnt/4 times denser,
+// whose first-candidate radius shrinks by cbrt(4/cnt); uniform inputs (a few
+// points per bucket) keep the grid's radius.
+__device__ inline unsigned own_count(const TessArgs& A, const GridParams& g, const int b[3]) {
+  const int64_t key = g.base + bucket_key(g.nb, b[0], b[1], b[2]);
+  return (unsigned)(A.boff[key + 1] - A.boff[key]);
+}
+
 __device__ void defer_cell(const TessArgs& A, int s, double rmax2) {
   if (__lane_id() == 0) {
     const int idx = atomicAdd(&A.st->n_deferred, 1);
@@ -633,7 +676,7 @@ __device__ void defer_cell(const TessArgs& A, int s, double rmax2) {
 //   slots, until twice the farthest vertex lies inside the shells done.  The
 //   first shell ends at twice the pass-1 farthest vertex, which bounds the
 //   true one (the pass-1 cell contains the true cell).
-__device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int pass) {
+__device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int pass, double4* vl = nullptr) {
   const int seg = A.sseg[s];
   const GridParams& g = A.segs[seg].g;   // read in place (wave-uniform loads), never copied
   const double r[3] = {A.spos[3 * (int64_t)s], A.spos[3 * (int64_t)s + 1], A.spos[3 * (int64_t)s + 2]};
@@ -647,13 +690,17 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
   }
   CellRegs C;
   init_box(S, g, C);
+  const unsigned cnt = uniform_i32((int)own_count(A, g, b));
+  const bool dense = cnt > 4u;
+  const double rloc = dense ? g.r_filter * cbrt(4.0 / (double)cnt) : g.r_filter;   // first-candidate radius
 
   if (pass == 1) {
+    const int ring = dense ? min(g.ring, ring_for(g, edge, rloc * rloc)) : g.ring;
     double reach = 1e300;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) reach = fmin(reach, g.ring * g.hb[a] + edge[a]);
-    const double hi2 = fmin(reach * reach, g.r_filter * g.r_filter);
-    const int nc = gather(S, A, g, s, r, b, g.ring, 0.0, hi2);
+    for (int a = 0; a < 3; ++a) reach = fmin(reach, ring * g.hb[a] + edge[a]);
+    const double hi2 = fmin(reach * reach, rloc * rloc);
+    const int nc = gather(S, A, g, s, r, b, ring, 0.0, hi2);
     if (nc > kCands) {
       if (__lane_id() == 0) atomicAdd(&A.st->n_overflow, 1);
       defer_cell(A, s, -1.0);
@@ -674,20 +721,21 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
     // a cell that still touched the starting box after the first pass does
     // not ask for a stencil as wide as the box at once.
     const double rm2 = A.rmax2[s];
-    const double rf2 = g.r_filter * g.r_filter;
+    const double rf2 = rloc * rloc;
     double lo2 = 0.0;
     double hi2 = rm2 > 0.0 ? fmin(4.0 * rm2 * (1.0 + 1e-9), 4.0 * rf2) : rf2;
     bool done = false;
-    for (int shell = 0; shell < 32 && !done; ++shell) {
+    for (int shell = 0; shell < kShells && !done; ++shell) {
       const int ring = ring_for(g, edge, hi2);
       if (ring > g.nb[0] || ring > g.nb[1] || ring > g.nb[2]) {
         fail_cell(A, s, seg, F_BOX);
         return;
       }
-      int nc = gather(S, A, g, s, r, b, ring, lo2, hi2);
+      const int nv = vl ? vertex_list(C, vl) : 0;
+      int nc = gather(S, A, g, s, r, b, ring, lo2, hi2, vl, nv);
       for (int tries = 0; nc > kCands && tries < 40; ++tries) {
         hi2 = lo2 + 0.5 * (hi2 - lo2);
-        nc = gather(S, A, g, s, r, b, ring, lo2, hi2);
+        nc = gather(S, A, g, s, r, b, ring, lo2, hi2, vl, nv);
       }
       if (nc > kCands) {
         fail_cell(A, s, seg, F_CANDS);
@@ -724,10 +772,11 @@ __global__ __launch_bounds__(64 * kWaves) void k_tess_pass1(TessArgs A) {
 
 __global__ __launch_bounds__(64 * kWaves) void k_tess_pass2(TessArgs A) {
   __shared__ TessLds lds[kWaves];
+  __shared__ double4 verts[kWaves][kVerts];   // the cell's live vertices, for pruning candidates
   const int w = threadIdx.x >> 6;
   const int nd = A.st->n_deferred;
   for (int64_t it = (int64_t)blockIdx.x * kWaves + w; it < nd; it += (int64_t)gridDim.x * kWaves)
-    tess_cell(lds[w], A, A.deferred[it], 2);
+    tess_cell(lds[w], A, A.deferred[it], 2, verts[w]);
 }
 
 }  // namespace

@@ -241,6 +241,90 @@ def sod_paper(k=14, seed=7, jitter=0.25, riemann="hllc", static_mesh=False) -> W
                     meta=dict(shape=(16 * k, k, k), t_end=2.0, left=(1.0, 0.0, 1.0), right=(0.25, 0.0, 0.1795)))
 
 
+def lane_emden(n=1.5, h=1e-4):
+    """Lane-Emden solution of index n by fourth-order Runge-Kutta from the
+    series start: returns (xi, theta, -xi^2 theta') sampled up to the first
+    zero xi_1 (the last sample is interpolated onto the zero)."""
+    def rhs(x, y):
+        th, dth = y
+        return np.array([dth, -max(th, 0.0) ** n - 2.0 * dth / x])
+    x = 1e-6
+    y = np.array([1.0 - x * x / 6.0, -x / 3.0])
+    xs, ths, ms = [0.0], [1.0], [0.0]
+    while True:
+        k1 = rhs(x, y); k2 = rhs(x + h / 2, y + h / 2 * k1)
+        k3 = rhs(x + h / 2, y + h / 2 * k2); k4 = rhs(x + h, y + h * k3)
+        yn = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+        if yn[0] <= 0.0:
+            f = y[0] / (y[0] - yn[0])
+            x1 = x + f * h
+            d1 = y[1] + f * (yn[1] - y[1])
+            xs.append(x1); ths.append(0.0); ms.append(-x1 * x1 * d1)
+            return np.array(xs), np.array(ths), np.array(ms)
+        x += h
+        y = yn
+        xs.append(x); ths.append(y[0]); ms.append(-x * x * y[1])
+
+
+def c5_polytropes(n_points=1 << 23, seed=5, m1=1.0, m2=0.7, r1=0.1, r2=0.08, sep=0.18, rho_bg=1e-6,
+                  inside_fraction=0.9) -> Workload:
+    """Two touching n = 1.5 polytropes in the periodic unit box (no
+    gravity: a workload of strongly non-uniform density).  G = 1; masses
+    m1, m2, radii r1, r2, centres sep apart along x with the centre of mass
+    at the box centre; P = K_k rho^(5/3) with K_k from the Lane-Emden
+    scaling; background rho_bg, P = K_1 rho_bg^(5/3), v = 0.  The stars
+    translate rigidly at -+(m_other / M) sqrt(M / sep) along y (a circular
+    binary's speeds).  inside_fraction of the points sample each star's mass
+    (in proportion to its mass), the rest are uniform outside both stars."""
+    rng = np.random.default_rng(seed)
+    xi, th, mxi = lane_emden(1.5)
+    xi1, mu1 = xi[-1], mxi[-1]
+    M = m1 + m2
+    vorb = math.sqrt(M / sep)
+    stars = []
+    for (m, R, cx, vy) in ((m1, r1, 0.5 - sep * m2 / M, -vorb * m2 / M),
+                           (m2, r2, 0.5 + sep * m1 / M, vorb * m1 / M)):
+        alpha = R / xi1
+        rho_c = m / (4.0 * math.pi * alpha ** 3 * mu1)
+        K = 4.0 * math.pi * alpha ** 2 * rho_c ** (1.0 / 3.0) / 2.5
+        stars.append(dict(m=m, R=R, c=np.array([cx, 0.5, 0.5]), vy=vy, alpha=alpha, rho_c=rho_c, K=K))
+    n_in = int(round(inside_fraction * n_points))
+    counts = [int(round(n_in * st["m"] / M)) for st in stars]
+    counts[1] = n_in - counts[0]
+    pos_parts, prim_parts = [], []
+    for st, k in zip(stars, counts):
+        # radius by inverting the mass profile, direction uniform
+        u = rng.uniform(0.0, mu1, size=k)
+        r = np.interp(u, mxi, xi) * st["alpha"]
+        d = rng.normal(size=(k, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        pos_parts.append(st["c"] + r[:, None] * d)
+        rho = st["rho_c"] * np.interp(r / st["alpha"], xi, th) ** 1.5
+        rho = np.maximum(rho, rho_bg)
+        pr = np.zeros((k, 5))
+        pr[:, 0] = rho
+        pr[:, 2] = st["vy"]
+        pr[:, 4] = st["K"] * rho ** (5.0 / 3.0)
+        prim_parts.append(pr)
+    n_out = n_points - n_in
+    out = np.empty((0, 3))
+    while out.shape[0] < n_out:
+        cand = rng.uniform(0.0, 1.0, size=(2 * (n_out - out.shape[0]) + 16, 3))
+        keep = np.ones(cand.shape[0], dtype=bool)
+        for st in stars:
+            keep &= np.linalg.norm(cand - st["c"], axis=1) > st["R"]
+        out = np.vstack([out, cand[keep]])
+    out = out[:n_out]
+    pbg = np.zeros((n_out, 5))
+    pbg[:, 0] = rho_bg
+    pbg[:, 4] = stars[0]["K"] * rho_bg ** (5.0 / 3.0)
+    pos = _wrap_inside(np.vstack(pos_parts + [out]), (1.0, 1.0, 1.0))
+    prim = np.vstack(prim_parts + [pbg])
+    return Workload("c5_polytropes", pos, prim, (1.0, 1.0, 1.0), _params(gamma=5.0 / 3.0), steps=20,
+                    meta=dict(stars=[{k: (v.tolist() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+                                     for st in stars], xi1=xi1, mu1=mu1))
+
+
 def poisson_arrivals(n, rate, seed=4) -> np.ndarray:
     """Arrival times (seconds, non-decreasing, first at 0) of n requests of a
     Poisson stream with the given rate (requests per second)."""
