@@ -59,3 +59,40 @@ def scaled_err(a, b):
     b = np.asarray(b, dtype=np.float64).reshape(b.shape[0], -1)
     scale = np.maximum(np.abs(b).max(axis=0), 1e-300)
     return float((np.abs(a - b).max(axis=0) / scale).max())
+
+
+def sampled_cells_match(orc, wl, ex, n_sample=3000, seed=0):
+    """Random cells of a large tessellation against the oracle, which builds
+    just those cells: volumes, centroids and every directed face."""
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(wl.n, n_sample, replace=False))
+    om = orc.tessellate(wl.pos, wl.box, subset=idx)
+    assert om.status == 0 and om.delta_min > 1e-12
+    V, c = host(ex.V), host(ex.centroid)
+    fi, fj, fc = host(ex.face_i), host(ex.face_j), host(ex.face_code)
+    fA, ff = host(ex.face_A), host(ex.face_f)
+    h = float(np.mean(om.V[idx]) ** (1 / 3))
+    np.testing.assert_allclose(V[idx], om.V[idx], rtol=1e-10)
+    assert np.abs(c[idx] - om.c[idx]).max() < 1e-10 * h
+    # directed GPU faces of the sampled cells: owner side as stored, the
+    # neighbour side with the opposite image and f moved by the image shift
+    sel = np.zeros(wl.n, bool)
+    sel[idx] = True
+    L = np.asarray(wl.box)
+    k = np.stack([fc % 3 - 1, (fc // 3) % 3 - 1, fc // 9 - 1], axis=1)
+    gpu = {}
+    for t in np.nonzero(sel[fi])[0]:
+        gpu[(int(fi[t]), int(fj[t]), int(fc[t]))] = (fA[t], ff[t])
+    for t in np.nonzero(sel[fj])[0]:
+        gpu[(int(fj[t]), int(fi[t]), 26 - int(fc[t]))] = (fA[t], ff[t] - k[t] * L)
+    own = om.face_owner()
+    ora = {(int(i), int(j), int(cc)): (a, f) for i, j, cc, a, f in zip(own, om.j, om.code, om.A, om.f) if sel[i]}
+    assert set(gpu) == set(ora), f"{len(set(gpu) ^ set(ora))} directed faces differ"
+    # Face centroids are compared at 1e-9 h: a vertex where four generators
+    # are nearly co-spherical is fixed by nearly parallel plane pairs, and
+    # both sides then carry rounding amplified by that conditioning (seen
+    # up to ~1.1e-10 h among 10^6 cells); areas and volumes stay at 1e-10.
+    for key, (a, f) in ora.items():
+        ga, gf = gpu[key]
+        assert abs(ga - a) <= 1e-10 * h * h
+        assert np.abs(gf - f).max() <= 1e-9 * h
