@@ -7,6 +7,8 @@
 // candidate stencil of a cell reads contiguous runs of positions.  Inside a
 // bucket points keep their caller order, which makes the internal order, and
 // every result downstream of it, independent of atomic scheduling.
+#include <algorithm>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -189,19 +191,114 @@ __global__ void k_scatter(const int32_t* __restrict__ key, int64_t n_slots, cons
   perm[slot] = (int32_t)i;
 }
 
-// Restores slot order inside each bucket (buckets hold a handful of points).
-__global__ void k_bucket_order(const unsigned long long* __restrict__ boff, int64_t nbt, int32_t* perm) {
+// Per bucket: a bucket of at most kDense points gets its slot order back
+// (insertion sort of a handful); a denser one records the size of its
+// sub-offset table (s^3 + 1), joins the list the block sort takes, and
+// lists its cells (sorted positions) for the tessellation's dense first
+// pass, with one atomic per bucket.
+// Buckets above kDenseMax points fail the call (their points stay where the
+// scatter put them and are read whole).
+__global__ void k_bucket_prep(const unsigned long long* __restrict__ boff, int64_t nbt, int32_t* perm,
+                              const int32_t* __restrict__ slot_seg, unsigned long long* __restrict__ sub_size_out,
+                              int32_t* __restrict__ dense, int32_t* __restrict__ dcells, DevStatus* st,
+                              SegStatus* segst) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbt) return;
   const int64_t lo = (int64_t)boff[b], hi = (int64_t)boff[b + 1];
-  for (int64_t a = lo + 1; a < hi; ++a) {
-    const int32_t v = perm[a];
-    int64_t c = a - 1;
-    while (c >= lo && perm[c] > v) {
-      perm[c + 1] = perm[c];
-      --c;
+  const int64_t cnt = hi - lo;
+  if (cnt <= kDense) {
+    sub_size_out[b] = 0;
+    for (int64_t a = lo + 1; a < hi; ++a) {
+      const int32_t v = perm[a];
+      int64_t c = a - 1;
+      while (c >= lo && perm[c] > v) {
+        perm[c + 1] = perm[c];
+        --c;
+      }
+      perm[c + 1] = v;
     }
-    perm[c + 1] = v;
+    return;
+  }
+  if (cnt > kDenseMax) {
+    sub_size_out[b] = 0;
+    seg_fail(st, segst, slot_seg ? slot_seg[perm[lo]] : 0, F_DENSE, (int)lo);
+    return;
+  }
+  const int s = sub_size((unsigned)cnt);
+  sub_size_out[b] = (unsigned long long)(s * s * s + 1);
+  dense[atomicAdd(&st->n_dense, 1)] = (int32_t)b;
+  const int c0 = atomicAdd(&st->n_dense_cells, (int)cnt);
+  for (int64_t i = 0; i < cnt; ++i) dcells[c0 + i] = (int32_t)(lo + i);
+}
+
+// Orders the points of each dense bucket by sub-bucket (x fastest), then by
+// slot, with a bitonic sort of (sub-bucket << 32 | slot) keys in LDS, and
+// writes the bucket's sub-bucket offsets: entry k counts its points in
+// sub-buckets below k (k = 0 .. s^3).  One block per bucket of the list.
+constexpr int kDenseThreads = 256;
+
+__global__ __launch_bounds__(kDenseThreads) void k_dense_order(
+    const int32_t* __restrict__ dense, const DevStatus* __restrict__ st, const unsigned long long* __restrict__ boff,
+    const unsigned long long* __restrict__ sbase, const double* __restrict__ pos,
+    const int32_t* __restrict__ slot_seg, const SegDesc* __restrict__ segs, int32_t* __restrict__ perm,
+    uint32_t* __restrict__ soffs) {
+  __shared__ unsigned long long kv[kDenseMax];
+  const int nd = st->n_dense;
+  const int t = threadIdx.x;
+  for (int it = blockIdx.x; it < nd; it += gridDim.x) {
+    const int64_t b = dense[it];
+    const int64_t lo = (int64_t)boff[b];
+    const int cnt = (int)((int64_t)boff[b + 1] - lo);
+    const int s = sub_size((unsigned)cnt);
+    int p2 = 1;
+    while (p2 < cnt) p2 <<= 1;
+    const int seg = slot_seg ? slot_seg[perm[lo]] : 0;
+    const GridParams& g = segs[seg].g;
+    for (int i = t; i < p2; i += kDenseThreads) {
+      unsigned long long k = ~0ull;
+      if (i < cnt) {
+        const int32_t q = perm[lo + i];
+        int sc[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double x = pos[3 * (int64_t)q + a];
+          sc[a] = sub_coord(x, g.inv_hb[a], bucket_coord(x, g.inv_hb[a], g.nb[a]), s);
+        }
+        k = ((unsigned long long)((sc[2] * s + sc[1]) * s + sc[0]) << 32) | (uint32_t)q;
+      }
+      kv[i] = k;
+    }
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = t; i < p2; i += kDenseThreads) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const unsigned long long a = kv[i], c = kv[ixj];
+            if (((i & k) == 0) == (a > c)) {
+              kv[i] = c;
+              kv[ixj] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = t; i < cnt; i += kDenseThreads) perm[lo + i] = (int32_t)(uint32_t)(kv[i] & 0xffffffffull);
+    const int ns = s * s * s;
+    uint32_t* so = soffs + sbase[b];
+    for (int k = t; k <= ns; k += kDenseThreads) {
+      // first position whose sub-bucket is k or more
+      const unsigned long long key = (unsigned long long)k << 32;
+      int l = 0, h = cnt;
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        if (kv[m] < key) l = m + 1;
+        else h = m;
+      }
+      so[k] = (uint32_t)l;
+    }
+    __syncthreads();
   }
 }
 
@@ -264,15 +361,23 @@ void launch_status_reset(DevStatus* s, SegStatus* segst, int nseg, hipStream_t s
 
 void launch_sort(const double* pos, int64_t n_slots, const int32_t* slot_seg, int64_t n, const SegDesc* segs,
                  int64_t nbt, unsigned long long* bcount, unsigned long long* boff, unsigned long long* scan_tmp,
-                 int32_t* key, int32_t* perm, int32_t* sseg, double* spos, DevStatus* st_dev, SegStatus* segst,
-                 hipStream_t st) {
+                 unsigned long long* sbase, uint32_t* soffs, int32_t* key, int32_t* perm, int32_t* sseg,
+                 double* spos, int32_t* dcells, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
   launch_fill_u64(bcount, 0ull, nbt, st);
+  launch_fill_i32(&st_dev->n_dense, 0, 2, st);   // n_dense and n_dense_cells
   hipLaunchKernelGGL(k_hash, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, pos, n_slots, slot_seg, segs, key,
                      bcount, st_dev, segst);
   scan_u64(bcount, boff, nbt, scan_tmp, st);
   launch_fill_u64(bcount, 0ull, nbt, st);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, key, n_slots, boff, bcount, perm);
-  hipLaunchKernelGGL(k_bucket_order, dim3(blocks_for(nbt, 256)), dim3(256), 0, st, boff, nbt, perm);
+  // bcount (the scatter's cursors) now takes the sub-table sizes and key
+  // (read by the scatter) the list of dense buckets.
+  hipLaunchKernelGGL(k_bucket_prep, dim3(blocks_for(nbt, 256)), dim3(256), 0, st, boff, nbt, perm, slot_seg, bcount,
+                     key, dcells, st_dev, segst);
+  scan_u64(bcount, sbase, nbt, scan_tmp, st);
+  const unsigned dense_blocks = (unsigned)std::min<int64_t>(std::max<int64_t>(nbt / kDense, 1), 2048);
+  hipLaunchKernelGGL(k_dense_order, dim3(dense_blocks), dim3(kDenseThreads), 0, st, key, st_dev, boff, sbase, pos,
+                     slot_seg, segs, perm, soffs);
   hipLaunchKernelGGL(k_gather_pos, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, perm, slot_seg, n, spos, sseg);
 }
 

@@ -37,6 +37,7 @@ namespace {
 #endif
 constexpr int kWaves = MM_TESS_WAVES;   // cells (wavefronts) per workgroup
 constexpr int kShells = 512;            // distance shells of the second pass
+constexpr int kShells1 = 3;             // extra shells a cell may take in the first pass
 
 // 10.8 KB per wavefront, so 15 cells fit the 160 KB of LDS of a CU.  The
 // candidate list is only needed while cutting and the vertex copies only in
@@ -68,12 +69,15 @@ struct TessArgs {
   const SegDesc* segs;
   const int32_t* sseg;
   const unsigned long long* boff;
+  const unsigned long long* sbase;   // sub-table base of each dense bucket
+  const uint32_t* soffs;             // sub-bucket offsets of the dense buckets
   StageNbr* stage_nb;
   StageGeo* stage_geo;
   unsigned long long* counts;
   double* geo;
   double* rmax2;
   int32_t* deferred;
+  int32_t* dcells;                   // cells for the dense first pass
   DevStatus* st;
   SegStatus* segst;
 };
@@ -243,7 +247,8 @@ __device__ inline unsigned div_width(unsigned o, const WidthDiv& d) {
 }
 
 __device__ inline StencilBucket stencil_bucket(const TessArgs& A, const GridParams& g, const int b[3], int ring,
-                                               int o, int W3, const WidthDiv& D) {
+                                               int o, int W3, const WidthDiv& D, int* bb_out = nullptr,
+                                               int64_t* key_out = nullptr) {
   StencilBucket B{0, 0, 13, 0.0, 0.0, 0.0};
   if (o < W3) {
     const unsigned W = D.W;
@@ -264,6 +269,12 @@ __device__ inline StencilBucket stencil_bucket(const TessArgs& A, const GridPara
     B.sx = kk[0] * g.L[0];
     B.sy = kk[1] * g.L[1];
     B.sz = kk[2] * g.L[2];
+    if (bb_out) {
+      bb_out[0] = bb[0];
+      bb_out[1] = bb[1];
+      bb_out[2] = bb[2];
+    }
+    if (key_out) *key_out = key;
   }
   return B;
 }
@@ -283,6 +294,166 @@ __device__ inline bool may_cut(const double4* vl, int nv, double dx, double dy, 
   return out;
 }
 
+// Whether a box (relative to the generator) may hold an image that cuts the
+// cell: a point cuts it only if it is closer to some vertex v than the
+// generator is, so the box must come within |v| of some v (vl[t].w holds
+// |v|^2).  The margins make the test looser than may_cut's, so no image
+// that may_cut keeps is lost with its box.
+__device__ inline bool box_may_cut(const double4* vl, int nv, const double lo[3], const double hi[3],
+                                   double slack) {
+  bool out = false;
+  for (int t = 0; t < nv; ++t) {
+    const double4 v = vl[t];
+    const double ex = fmax(0.0, fmax(lo[0] - v.x, v.x - hi[0]));
+    const double ey = fmax(0.0, fmax(lo[1] - v.y, v.y - hi[1]));
+    const double ez = fmax(0.0, fmax(lo[2] - v.z, v.z - hi[2]));
+    out |= ex * ex + ey * ey + ez * ez < v.w * (1.0 + 1e-9) + slack;
+  }
+  return out;
+}
+
+// Gather of one 128-bucket chunk of the stencil that holds dense buckets.
+// Each bucket contributes runs of consecutive points: a sparse bucket its
+// whole range, a dense one the part of each sub-bucket row (along x) that
+// meets the box around the query sphere; buckets that miss the box give
+// nothing.  The wave takes the runs 64 at a time, one per lane (the lane
+// finds the bucket of its run by a binary search over the buckets' run
+// prefix sums), and steps through their points together.  The test on each
+// point is the one of the uniform path, so the candidates are the same;
+// only the points read are fewer.  Returns the new candidate count.
+__device__ int gather_runs(TessLds& S, const TessArgs& A, const GridParams& g, const int s, const double r[3],
+                           const int b[3], const int ring, const int chunk, const int W3, const WidthDiv& D,
+                           const double lo2, const double hi2, const double4* vl, const int nv, int nc) {
+  const int lane = __lane_id();
+  // Half-width of the query box, with a margin far above the rounding of
+  // the distance test, so that every point the test keeps lies inside.
+  const double rq = sqrt(hi2) * (1.0 + 1e-9) + 1e-9 * fmin(g.hb[0], fmin(g.hb[1], g.hb[2]));
+  for (int half = 0; half < 2; ++half) {
+    int bb[3] = {0, 0, 0};
+    int64_t key = 0;
+    const StencilBucket B = stencil_bucket(A, g, b, ring, chunk + 64 * half + lane, W3, D, bb, &key);
+    int nr = 0, pack = 0, base = 0;
+    if (B.cnt > 0) {
+      const double sh[3] = {B.sx, B.sy, B.sz};
+      double qlo[3], qhi[3];
+      bool meet = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        qlo[a] = (r[a] - rq) - sh[a];
+        qhi[a] = (r[a] + rq) - sh[a];
+        // bucket bb holds the points with floor(x / hb) = bb (the last one
+        // also those rounding to nb)
+        const double tlo = qlo[a] * g.inv_hb[a], thi = qhi[a] * g.inv_hb[a];
+        if (thi < (double)bb[a] || (tlo >= (double)(bb[a] + 1) && bb[a] < g.nb[a] - 1)) meet = false;
+      }
+      if (meet && vl) {
+        // the bucket's box relative to the generator, widened a little
+        double blo[3], bhi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          blo[a] = (bb[a] * g.hb[a] + sh[a]) - r[a] - 1e-9 * g.hb[a];
+          bhi[a] = ((bb[a] + 1) * g.hb[a] + sh[a]) - r[a] + 1e-9 * g.hb[a];
+        }
+        meet = box_may_cut(vl, nv, blo, bhi, 1e-12 * hi2);
+      }
+      if (meet) {
+        if (B.cnt <= kDense || B.cnt > kDenseMax) {
+          nr = 1;
+        } else {
+          const int ss = sub_size((unsigned)B.cnt);
+          int l[3], m[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            l[a] = sub_coord(qlo[a], g.inv_hb[a], bb[a], ss);
+            m[a] = sub_coord(qhi[a], g.inv_hb[a], bb[a], ss) - l[a] + 1;
+          }
+          nr = m[1] * m[2];
+          pack = ss | l[0] << 5 | m[0] << 10 | l[1] << 15 | m[1] << 20 | l[2] << 25;
+          base = (int)A.sbase[key];
+        }
+      }
+    }
+    int total;
+    const int excl = wave_excl_scan_small<15>(nr, &total);
+    for (int t0 = 0; t0 < total; t0 += 64) {
+      const int t = t0 + lane;
+      // the last bucket whose runs start at or before t
+      int ow = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int e = __shfl(excl, ow + step, 64);
+        if (e <= t) ow += step;
+      }
+      const int e_o = __shfl(excl, ow, 64);
+      const int bst_o = __shfl(B.bst, ow, 64), cnt_o = __shfl(B.cnt, ow, 64), code_o = __shfl(B.code, ow, 64);
+      const int pack_o = __shfl(pack, ow, 64), base_o = __shfl(base, ow, 64);
+      // (shuffles stay outside the branches below: a lane reads another's
+      // register only while both are active)
+      int bx_o = 0, by_o = 0, bz_o = 0;
+      if (vl) {
+        bx_o = __shfl(bb[0], ow, 64);
+        by_o = __shfl(bb[1], ow, 64);
+        bz_o = __shfl(bb[2], ow, 64);
+      }
+      int kx, ky, kz;
+      decode(code_o, kx, ky, kz);
+      const double sx = kx * g.L[0], sy = ky * g.L[1], sz = kz * g.L[2];
+      int start = bst_o, count = t < total ? cnt_o : 0;
+      if (pack_o != 0 && t < total) {
+        const int ss = pack_o & 31, x0 = (pack_o >> 5) & 31, nx = (pack_o >> 10) & 31;
+        const int y0 = (pack_o >> 15) & 31, ny = (pack_o >> 20) & 31, z0 = (pack_o >> 25) & 31;
+        const int jr = t - e_o;
+        const int ry = y0 + jr % ny, rz = z0 + jr / ny;
+        bool take = true;
+        if (vl) {
+          // the row's box: sub-buckets x0 .. x0 + nx - 1 of row (ry, rz)
+          const double is = 1.0 / ss;
+          const double lo[3] = {(bx_o + x0 * is) * g.hb[0] + sx - r[0] - 1e-9 * g.hb[0],
+                                (by_o + ry * is) * g.hb[1] + sy - r[1] - 1e-9 * g.hb[1],
+                                (bz_o + rz * is) * g.hb[2] + sz - r[2] - 1e-9 * g.hb[2]};
+          const double hi[3] = {(bx_o + (x0 + nx) * is) * g.hb[0] + sx - r[0] + 1e-9 * g.hb[0],
+                                (by_o + (ry + 1) * is) * g.hb[1] + sy - r[1] + 1e-9 * g.hb[1],
+                                (bz_o + (rz + 1) * is) * g.hb[2] + sz - r[2] + 1e-9 * g.hb[2]};
+          take = box_may_cut(vl, nv, lo, hi, 1e-12 * hi2);
+        }
+        count = 0;
+        if (take) {
+          const int row = (rz * ss + ry) * ss + x0;
+          const uint32_t* so = A.soffs + base_o;
+          const int a0 = (int)so[row], a1 = (int)so[row + nx];
+          start = bst_o + a0;
+          count = a1 - a0;
+        }
+      }
+      const int maxc = (int)wave_umax32((unsigned)count);
+      for (int k = 0; k < maxc; ++k) {
+        const int j = start + k;
+        const bool v = k < count && j != s;
+        double x = 0, y = 0, z = 0;
+        if (v) {
+          x = A.spos[3 * (int64_t)j];
+          y = A.spos[3 * (int64_t)j + 1];
+          z = A.spos[3 * (int64_t)j + 2];
+        }
+        const double dx = (x + sx) - r[0], dy = (y + sy) - r[1], dz = (z + sz) - r[2];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        bool keep = v && (d2 >= lo2) && (d2 < hi2);
+        if (vl && keep) keep = may_cut(vl, nv, dx, dy, dz, d2);
+        const unsigned long long mk = __ballot(keep);
+        if (keep) {
+          const int idx = nc + __popcll(mk & lanes_below());
+          if (idx < kCands) {
+            S.cd[idx] = make_double4(dx, dy, dz, d2);
+            S.cjk[idx] = (j << 5) | code_o;
+          }
+        }
+        nc += __popcll(mk);
+      }
+    }
+  }
+  return nc;
+}
+
 // Gathers the neighbour images with lo2 <= |d|^2 < hi2 from the stencil of
 // half-width `ring` into LDS (at most kCands of them); returns their number.
 // Each lane takes two buckets of the stencil at a time and the wave steps
@@ -292,6 +463,10 @@ __device__ inline bool may_cut(const double4* vl, int nv, double dx, double dy, 
 // With a vertex list (vl, nv) of the current cell, images that cannot cut it
 // are left out (a cell next to a much denser region then sees only the few
 // points that face it).
+// Without RUNS (the first pass over all cells) a stencil chunk that holds a
+// dense bucket ends the gather with -1: the cell goes to the first pass for
+// cells near dense regions.
+template <bool RUNS>
 __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const int s, const double r[3],
                       const int b[3], const int ring, const double lo2, const double hi2,
                       const double4* vl = nullptr, int nv = 0) {
@@ -302,6 +477,13 @@ __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const 
   for (int chunk = 0; chunk < W3; chunk += 128) {
     const StencilBucket B0 = stencil_bucket(A, g, b, ring, chunk + lane, W3, D);
     const StencilBucket B1 = stencil_bucket(A, g, b, ring, chunk + 64 + lane, W3, D);
+    // With a vertex list every chunk takes the run path, whose boxes prune
+    // whole buckets and rows.
+    if (__ballot(B0.cnt > kDense || B1.cnt > kDense) || (RUNS && vl)) {
+      if constexpr (!RUNS) return -1;
+      nc = gather_runs(S, A, g, s, r, b, ring, chunk, W3, D, lo2, hi2, vl, nv, nc);
+      continue;
+    }
     const int maxc = (int)wave_umax32((unsigned)max(B0.cnt, B1.cnt));
     for (int k = 0; k < maxc; ++k) {
       const int j0 = B0.bst + k, j1 = B1.bst + k;
@@ -640,20 +822,28 @@ __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const Cel
   return 0;
 }
 
-// The live vertices of the cell, compacted into vl; returns their number.
+// The live vertices of the cell (relative to the generator, w = |v|^2),
+// compacted into vl; returns their number.
 __device__ int vertex_list(const CellRegs& C, double4* vl) {
   const int lane = __lane_id();
   const int n0 = __popcll(C.L0);
-  if ((C.L0 >> lane) & 1ull) vl[__popcll(C.L0 & lanes_below())] = make_double4(C.v0x, C.v0y, C.v0z, 0.0);
-  if ((C.L1 >> lane) & 1ull) vl[n0 + __popcll(C.L1 & lanes_below())] = make_double4(C.v1x, C.v1y, C.v1z, 0.0);
+  if ((C.L0 >> lane) & 1ull)
+    vl[__popcll(C.L0 & lanes_below())] =
+        make_double4(C.v0x, C.v0y, C.v0z, C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z);
+  if ((C.L1 >> lane) & 1ull)
+    vl[n0 + __popcll(C.L1 & lanes_below())] =
+        make_double4(C.v1x, C.v1y, C.v1z, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
   wave_sync();
   return n0 + __popcll(C.L1);
 }
 
 // Points in the cell's own bucket.  Buckets are sized for the mean spacing,
-// so a bucket holding cnt > 4 points marks a region cnt/4 times denser,
-// whose first-candidate radius shrinks by cbrt(4/cnt); uniform inputs (a few
-// points per bucket) keep the grid's radius.
+// so a bucket holding cnt > 4 points marks a denser region, whose
+// first-candidate radius shrinks: by cbrt(4/cnt) up to kDense points, and
+// for a bucket with a sub-grid by cbrt(ppb/cnt), the ratio of the local
+// spacing to the mean one, which keeps the expected number of candidates of
+// a uniform region.  Uniform inputs (a few points per bucket) keep the
+// grid's radius.
 __device__ inline unsigned own_count(const TessArgs& A, const GridParams& g, const int b[3]) {
   const int64_t key = g.base + bucket_key(g.nb, b[0], b[1], b[2]);
   return (unsigned)(A.boff[key + 1] - A.boff[key]);
@@ -667,16 +857,27 @@ __device__ void defer_cell(const TessArgs& A, int s, double rmax2) {
   }
 }
 
+// Hands a cell with a dense bucket in its stencil to the dense first pass.
+__device__ void defer_dense(const TessArgs& A, int s) {
+  if (__lane_id() == 0) A.dcells[atomicAdd(&A.st->n_dense_cells, 1)] = s;
+}
+
 // Builds the cell of internal generator s.
-// pass 1: candidates within the grid's filter radius; a cell whose
-//   candidates do not cover twice its farthest vertex (or overflow the
-//   candidate slots) is deferred.
-// pass 2: distance shells [lo, hi) processed in order, each gathered from a
-//   stencil wide enough for it and narrowed until it fits the candidate
-//   slots, until twice the farthest vertex lies inside the shells done.  The
-//   first shell ends at twice the pass-1 farthest vertex, which bounds the
-//   true one (the pass-1 cell contains the true cell).
-__device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int pass, double4* vl = nullptr) {
+// MODE 0 (first pass, every cell): candidates within the grid's filter
+//   radius; a cell whose candidates do not cover twice its farthest vertex
+//   (or overflow the candidate slots) is deferred to the shell pass, and a
+//   cell with a dense bucket in its own bucket or stencil goes to MODE 1.
+//   This kernel stays lean (uniform inputs finish here).
+// MODE 1 (first pass of the cells near dense regions): the same with the
+//   two-level gather, and a cell that falls short goes on with up to
+//   kShells1 more shells before it is deferred.
+// MODE 2 (shell pass): distance shells [lo, hi) processed in order, each
+//   gathered from a stencil wide enough for it and narrowed until it fits
+//   the candidate slots, until twice the farthest vertex lies inside the
+//   shells done.  The first shell ends at twice the farthest vertex found
+//   before, which bounds the true one (that cell contains the true cell).
+template <int MODE>
+__device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* vl = nullptr) {
   const int seg = A.sseg[s];
   const GridParams& g = A.segs[seg].g;   // read in place (wave-uniform loads), never copied
   const double r[3] = {A.spos[3 * (int64_t)s], A.spos[3 * (int64_t)s + 1], A.spos[3 * (int64_t)s + 2]};
@@ -692,15 +893,21 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
   init_box(S, g, C);
   const unsigned cnt = uniform_i32((int)own_count(A, g, b));
   const bool dense = cnt > 4u;
-  const double rloc = dense ? g.r_filter * cbrt(4.0 / (double)cnt) : g.r_filter;   // first-candidate radius
+  const double rloc = !dense ? g.r_filter
+                              : g.r_filter * cbrt((cnt > (unsigned)kDense ? g.ppb : 4.0) / (double)cnt);
 
-  if (pass == 1) {
+  if (MODE == 0 && cnt > (unsigned)kDense) return;   // listed for the dense first pass by the sort
+  if (MODE < 2) {
     const int ring = dense ? min(g.ring, ring_for(g, edge, rloc * rloc)) : g.ring;
     double reach = 1e300;
 #pragma unroll
     for (int a = 0; a < 3; ++a) reach = fmin(reach, ring * g.hb[a] + edge[a]);
-    const double hi2 = fmin(reach * reach, rloc * rloc);
-    const int nc = gather(S, A, g, s, r, b, ring, 0.0, hi2);
+    double hi2 = fmin(reach * reach, rloc * rloc);
+    const int nc = gather<MODE != 0>(S, A, g, s, r, b, ring, 0.0, hi2);
+    if (nc < 0) {
+      defer_dense(A, s);
+      return;
+    }
     if (nc > kCands) {
       if (__lane_id() == 0) atomicAdd(&A.st->n_overflow, 1);
       defer_cell(A, s, -1.0);
@@ -711,9 +918,30 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
       fail_cell(A, s, seg, bad);
       return;
     }
-    if (!(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12))) {
-      defer_cell(A, s, C.rmax2);
-      return;
+    // A cell whose candidates fell short of twice its farthest vertex goes
+    // on with a few more shells here (irregular inputs need them often);
+    // one that still falls short, or whose next shell overflows, is
+    // deferred with its farthest-vertex bound.
+    double lo2 = 0.0;
+    for (int shell = 0; !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)); ++shell) {
+      const double nhi2 = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
+      const int nring = ring_for(g, edge, nhi2);
+      if (MODE == 0 || shell == kShells1 || nring > g.nb[0] || nring > g.nb[1] || nring > g.nb[2]) {
+        defer_cell(A, s, C.rmax2);
+        return;
+      }
+      lo2 = hi2;
+      hi2 = nhi2;
+      const int nc2 = gather<true>(S, A, g, s, r, b, nring, lo2, hi2);
+      if (nc2 > kCands) {
+        defer_cell(A, s, C.rmax2);
+        return;
+      }
+      sort_candidates(S, nc2);
+      if (int bad = clip_candidates(S, nc2, C)) {
+        fail_cell(A, s, seg, bad);
+        return;
+      }
     }
   } else {
     // Shells [lo2, hi2) of growing radius.  Each next shell reaches twice
@@ -731,11 +959,14 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, const int 
         fail_cell(A, s, seg, F_BOX);
         return;
       }
-      const int nv = vl ? vertex_list(C, vl) : 0;
-      int nc = gather(S, A, g, s, r, b, ring, lo2, hi2, vl, nv);
+      // Buckets, sub-bucket rows and points that cannot cut the cell are
+      // left out (a cell next to a much denser region sees only the few
+      // points that face it).
+      const int nv = vertex_list(C, vl);
+      int nc = gather<true>(S, A, g, s, r, b, ring, lo2, hi2, vl, nv);
       for (int tries = 0; nc > kCands && tries < 40; ++tries) {
         hi2 = lo2 + 0.5 * (hi2 - lo2);
-        nc = gather(S, A, g, s, r, b, ring, lo2, hi2, vl, nv);
+        nc = gather<true>(S, A, g, s, r, b, ring, lo2, hi2, vl, nv);
       }
       if (nc > kCands) {
         fail_cell(A, s, seg, F_CANDS);
@@ -767,7 +998,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_tess_pass1(TessArgs A) {
   const int w = threadIdx.x >> 6;
   const int64_t s = xcd_block() * kWaves + w;
   if (s >= A.n) return;
-  tess_cell(lds[w], A, (int)s, 1);
+  tess_cell<0>(lds[w], A, (int)s);
+}
+
+// Three waves per SIMD fit without spills (the two-level gather and the
+// extra shells keep many values live).
+// The listed cells: those of the dense buckets (listed by the sort) and
+// those the first pass met a dense bucket for.
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_tess_pass1_dense(
+    TessArgs A) {
+  __shared__ TessLds lds[kWaves];
+  const int w = threadIdx.x >> 6;
+  const int nd = A.st->n_dense_cells;
+  for (int64_t it = (int64_t)blockIdx.x * kWaves + w; it < nd; it += (int64_t)gridDim.x * kWaves)
+    tess_cell<1>(lds[w], A, A.dcells[it]);
 }
 
 __global__ __launch_bounds__(64 * kWaves) void k_tess_pass2(TessArgs A) {
@@ -776,22 +1020,25 @@ __global__ __launch_bounds__(64 * kWaves) void k_tess_pass2(TessArgs A) {
   const int w = threadIdx.x >> 6;
   const int nd = A.st->n_deferred;
   for (int64_t it = (int64_t)blockIdx.x * kWaves + w; it < nd; it += (int64_t)gridDim.x * kWaves)
-    tess_cell(lds[w], A, A.deferred[it], 2, verts[w]);
+    tess_cell<2>(lds[w], A, A.deferred[it], verts[w]);
 }
 
 }  // namespace
 
 void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
-                       const unsigned long long* boff, StageNbr* stage_nb, StageGeo* stage_geo,
-                       unsigned long long* counts, double* geo, double* rmax2, int32_t* deferred, DevStatus* st_dev,
-                       SegStatus* segst, hipStream_t st) {
+                       const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
+                       StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
+                       double* rmax2, int32_t* deferred, int32_t* dcells, DevStatus* st_dev, SegStatus* segst,
+                       hipStream_t st) {
   if (n <= 0) return;
-  TessArgs A{spos, n, segs, sseg, boff, stage_nb, stage_geo, counts, geo, rmax2, deferred, st_dev, segst};
+  TessArgs A{spos,     n,   segs,  sseg,  boff,  sbase,    soffs,  stage_nb, stage_geo,
+             counts,   geo, rmax2, deferred, dcells, st_dev, segst};
   const unsigned blocks = (unsigned)((n + kWaves - 1) / kWaves);
   hipLaunchKernelGGL(k_tess_pass1, dim3(blocks), dim3(64 * kWaves), 0, st, A);
-  // The deferred count is known on the device only: enough blocks for a
-  // large share of deferred cells, each exits at once when there is none.
+  // The deferred counts are known on the device only: enough blocks for a
+  // large share of the cells, each exits at once when there is none.
   const unsigned blocks2 = (unsigned)std::min<int64_t>(blocks, 16384);
+  hipLaunchKernelGGL(k_tess_pass1_dense, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
   hipLaunchKernelGGL(k_tess_pass2, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
 }
 

@@ -37,9 +37,11 @@ struct Engine {
   hipStream_t stream = nullptr;
   int device = 0;
   // Sort and tessellation.
-  int32_t *key = nullptr, *perm = nullptr, *sseg = nullptr, *deferred = nullptr;
+  int32_t *key = nullptr, *perm = nullptr, *sseg = nullptr, *deferred = nullptr, *dcells = nullptr;
   double *spos = nullptr, *geo = nullptr, *rmax2 = nullptr, *minv = nullptr;
   unsigned long long *bcount = nullptr, *boff = nullptr, *scan_tmp = nullptr, *counts = nullptr, *off = nullptr;
+  unsigned long long* sbase = nullptr;   // sub-table base of each bucket (dense buckets)
+  uint32_t* soffs = nullptr;             // sub-bucket offsets of the dense buckets
   unsigned long long *sw = nullptr, *soff = nullptr;   // slice widths and offsets of the per-cell lists
   StageNbr* stage_nb = nullptr;
   StageGeo* stage_geo = nullptr;

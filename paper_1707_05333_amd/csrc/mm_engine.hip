@@ -20,9 +20,9 @@ hipError_t dalloc(T** p, size_t count) {
 
 int64_t engine_bytes_per_cell(int precision) {
   const int64_t r = precision == MM_MIXED ? 4 : 8;
-  const int64_t per_cell = 4 * 4                                       // key, perm, sseg, deferred
+  const int64_t per_cell = 4 * 5                                       // key, perm, sseg, deferred, dcells
                            + 8 * (3 + 4 + 1 + 6 + 1 + 1)               // spos, geo, rmax2, minv, counts, off
-                           + 16                                        // bucket count and offset
+                           + 16 + 8 + 4                                // bucket count, offset, sub-table base; sub-offsets
                            + (int64_t)kMaxFaces * (sizeof(StageNbr) + sizeof(StageGeo))
                            + kListPerCell * (4 + (r == 4 ? sizeof(NbrEntry<float>) : sizeof(NbrEntry<double>)))
                            + r * (5 + 15 + 5) + 8 * (3 + 5)            // U, G, Uh, w, Qs
@@ -61,6 +61,7 @@ GridParams make_grid(const mm_params& p, int64_t n, double rfac, int64_t base) {
   // (images beyond one box length are outside the scheme's premise).
   g.ring = std::min(g.ring, std::min(g.nb[0], std::min(g.nb[1], g.nb[2])));
   g.pad = 0;
+  g.ppb = (double)n / (double)g.nbt;
   g.base = base;
   return g;
 }
@@ -131,12 +132,15 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
   ok &= dalloc(&perm, N) == hipSuccess;
   ok &= dalloc(&sseg, N) == hipSuccess;
   ok &= dalloc(&deferred, N) == hipSuccess;
+  ok &= dalloc(&dcells, N) == hipSuccess;
   ok &= dalloc(&spos, 3 * N) == hipSuccess;
   ok &= dalloc(&geo, 4 * N) == hipSuccess;
   ok &= dalloc(&rmax2, N) == hipSuccess;
   ok &= dalloc(&minv, 6 * N) == hipSuccess;
   ok &= dalloc(&bcount, nbcap) == hipSuccess;
   ok &= dalloc(&boff, nbcap + 1) == hipSuccess;
+  ok &= dalloc(&sbase, nbcap + 1) == hipSuccess;
+  ok &= dalloc(&soffs, N) == hipSuccess;
   ok &= dalloc(&scan_tmp, scan_tmp_elems(std::max(N, nbcap))) == hipSuccess;
   ok &= dalloc(&counts, N) == hipSuccess;
   ok &= dalloc(&off, N + 1) == hipSuccess;
@@ -186,7 +190,7 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
 }
 
 void Engine::release() {
-  void* ptrs[] = {key, perm, sseg, deferred, spos, geo, rmax2, minv, bcount, boff, scan_tmp, counts, off, sw, soff,
+  void* ptrs[] = {key, perm, sseg, deferred, dcells, spos, geo, rmax2, minv, bcount, boff, sbase, soffs, scan_tmp, counts, off, sw, soff,
                   stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, pos_half, Uh_slots,
                   Xe, Xh, recx, phiX, machF, Ss, segs, segst, st};
   for (void* q : ptrs)
@@ -222,11 +226,11 @@ void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int3
                                   int64_t n_buckets) {
   nbt = n_buckets;
   mark(0);
-  launch_sort(pos, n_slots, slot_seg, n_cells, segs, n_buckets, bcount, boff, scan_tmp, key, perm, sseg, spos, st,
-              segst, stream);
+  launch_sort(pos, n_slots, slot_seg, n_cells, segs, n_buckets, bcount, boff, scan_tmp, sbase, soffs, key, perm,
+              sseg, spos, dcells, st, segst, stream);
   mark(1);
-  launch_tessellate(spos, n_cells, segs, sseg, boff, stage_nb, stage_geo, counts, geo, rmax2, deferred, st, segst,
-                    stream);
+  launch_tessellate(spos, n_cells, segs, sseg, boff, sbase, soffs, stage_nb, stage_geo, counts, geo, rmax2, deferred,
+                    dcells, st, segst, stream);
   mark(2);
   scan_u64(counts, off, n_cells, scan_tmp, stream);
   launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, sw, soff, scan_tmp, fcap,
@@ -348,6 +352,11 @@ mm_status Engine::check_flags(int flags, int bad_cell, std::string& msg) const {
   if (flags & F_VERTS) { msg = "a cell has more than 128 vertices: " + at; return MM_ECAPACITY; }
   if (flags & F_CANDS) {
     msg = "more than " + std::to_string(kCands) + " neighbour candidates in one distance shell of a cell: " + at;
+    return MM_ECAPACITY;
+  }
+  if (flags & F_DENSE) {
+    msg = "a grid bucket holds more than " + std::to_string(kDenseMax) +
+          " points (density contrast beyond the neighbour search's range): " + at;
     return MM_ECAPACITY;
   }
   if (flags & F_FACECAP) { msg = "more unique faces than the face capacity: " + at; return MM_ECAPACITY; }

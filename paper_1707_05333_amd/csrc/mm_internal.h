@@ -38,6 +38,7 @@ enum : int {
   F_WALK = 1 << 8,        // corrupted face cycle
   F_VOLUME = 1 << 9,      // non-positive cell volume
   F_BOX = 1 << 10,        // stencil wider than the periodic box allows
+  F_DENSE = 1 << 11,      // a grid bucket holds more than kDenseMax points
 };
 
 // Status of the whole launch set, read back once per call.
@@ -47,6 +48,8 @@ struct DevStatus {
   int max_faces;
   int bad_cell;                  // lowest internal cell index with a failure
   int n_overflow;                // of those, cells whose first-pass candidates overflowed
+  int n_dense;                   // buckets with a sub-grid (length of the sort's dense-bucket list)
+  int n_dense_cells;             // cells for the dense first pass (follows n_dense: cleared together)
   int pad;
   unsigned long long n_faces;    // unique faces (copy of the scan total)
   unsigned long long n_csr;      // directed faces (copy of the scan total)
@@ -71,6 +74,7 @@ struct GridParams {
   int ring;         // stencil half-width (in buckets) of the first pass
   int pad;
   double r_filter;  // first-pass candidate radius
+  double ppb;       // mean points per bucket
   int64_t base;     // first bucket of this grid in the shared bucket table
 };
 
@@ -158,6 +162,34 @@ inline __device__ int bucket_coord(double x, double inv_h, int nb) {
   return t >= 0.0 ? (t < (double)nb ? (int)t : nb - 1) : 0;
 }
 
+// Two-level grid.  Buckets are sized for the mean spacing; a bucket holding
+// more than kDense points (a region several times denser than the mean) is
+// split into s^3 sub-buckets, s the largest value in [2, kSubMax] with
+// 2 s^3 <= count, its points ordered sub-bucket by sub-bucket (x fastest,
+// then by slot).  Its s^3 + 1 sub-bucket offsets, relative to the bucket's
+// first point, sit in a shared table at the bucket's sub-table base.  A
+// query then reads only the sub-bucket rows that meet its sphere, so the
+// work per cell follows the local density.  kDenseMax bounds the points of
+// one bucket (they are sorted in LDS).
+constexpr int kDense = 8;
+constexpr int kSubMax = 16;
+constexpr int kDenseMax = 4096;
+
+inline __host__ __device__ int sub_size(unsigned cnt) {
+  int s = 2;
+  while (s < kSubMax && 2u * (unsigned)((s + 1) * (s + 1) * (s + 1)) <= cnt) ++s;
+  return s;
+}
+
+// Sub-bucket of a coordinate inside bucket b of an axis (b from
+// bucket_coord): monotone in x, clamped to [0, s - 1], so a query interval
+// [lo, hi] covers every point in it by the sub-buckets from
+// sub_coord(lo) to sub_coord(hi).
+inline __device__ int sub_coord(double x, double inv_h, int b, int s) {
+  const double t = floor((x * inv_h - (double)b) * (double)s);
+  return t >= 0.0 ? (t < (double)s ? (int)t : s - 1) : 0;
+}
+
 // Position of bucket (bx, by, bz) in the grid's table (before the grid's
 // base), and so in the cell order.  Buckets are numbered tile by tile
 // (tiles of kTile^3 buckets, row-major over tiles, x fastest; row-major
@@ -229,14 +261,15 @@ void launch_remesh_reset(DevStatus* s, hipStream_t st);
 // cell, the sorted positions and the bucket offsets of all nbt buckets.
 void launch_sort(const double* pos, int64_t n_slots, const int32_t* slot_seg, int64_t n, const SegDesc* segs,
                  int64_t nbt, unsigned long long* bcount, unsigned long long* boff, unsigned long long* scan_tmp,
-                 int32_t* key, int32_t* perm, int32_t* sseg, double* spos, DevStatus* st_dev, SegStatus* segst,
-                 hipStream_t st);
+                 unsigned long long* sbase, uint32_t* soffs, int32_t* key, int32_t* perm, int32_t* sseg,
+                 double* spos, int32_t* dcells, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
 // Tessellation: pass 1 over every cell, then the deferred cells.
 void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
-                       const unsigned long long* boff, StageNbr* stage_nb, StageGeo* stage_geo,
-                       unsigned long long* counts, double* geo, double* rmax2, int32_t* deferred, DevStatus* st_dev,
-                       SegStatus* segst, hipStream_t st);
+                       const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
+                       StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
+                       double* rmax2, int32_t* deferred, int32_t* dcells, DevStatus* st_dev, SegStatus* segst,
+                       hipStream_t st);
 
 // Per-cell lists (face ids with sign, neighbour entries) use a sliced ELL
 // layout: slices of 64 consecutive internal cells, each as wide as its
