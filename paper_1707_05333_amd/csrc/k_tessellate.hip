@@ -581,7 +581,7 @@ __device__ inline double farthest_bound(const CellRegs& C) {
   const int lane = __lane_id();
   double m2 = 0.0;
   if ((C.L0 >> lane) & 1ull) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
-  if ((C.L1 >> lane) & 1ull) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
+  if (C.L1 != 0ull && ((C.L1 >> lane) & 1ull)) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
   return wave_max_bound(m2);
 }
 
@@ -607,10 +607,15 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
       if (q.w >= 4.0 * C.rmax2) break;
     }
     const double h = 0.5 * q.w;
-    const bool live0 = (C.L0 >> lane) & 1ull, live1 = (C.L1 >> lane) & 1ull;
+    // Most cells keep every vertex in the first register (64 slots); the
+    // second register's work is skipped while it holds none (a
+    // wavefront-uniform test).
+    const bool two = C.L1 != 0ull;
+    const bool live0 = (C.L0 >> lane) & 1ull, live1 = two && ((C.L1 >> lane) & 1ull);
     const bool out0 = live0 && (q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h);
-    const bool out1 = live1 && (q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h);
-    const unsigned long long M0 = __ballot(out0), M1 = __ballot(out1);
+    bool out1 = false;
+    if (two) out1 = live1 && (q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h);
+    const unsigned long long M0 = __ballot(out0), M1 = two ? __ballot(out1) : 0ull;
     if ((M0 | M1) == 0ull) continue;
 
     // Plane slot for the new face: the next unused slot while there is one,
@@ -633,7 +638,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     const unsigned long long L0 = C.L0, L1 = C.L1;
     // Which slots survive the cut, as bytes every lane can look up.
     S.kept[lane] = (uint8_t)kept0;
-    S.kept[lane + 64] = (uint8_t)kept1;
+    if (two) S.kept[lane + 64] = (uint8_t)kept1;   // (no live triangle refers to these slots otherwise)
     wave_sync();
     auto boundary = [&](uint32_t T) -> int {
       const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
@@ -659,6 +664,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     int e = pre;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
+      if (sl == 1 && !two) break;
       const uint32_t T = sl ? C.t1 : C.t0;
       const int bm = sl ? bm1 : bm0;
       const int ta = T & 255, tb = (T >> 8) & 255, tc = (T >> 16) & 255;
@@ -698,7 +704,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     const bool nl0 = kept0 || new0;
     const bool nl1 = kept1 || new1;
     C.L0 = __ballot(nl0);
-    C.L1 = __ballot(nl1);
+    C.L1 = two || B > nf0 ? __ballot(nl1) : 0ull;
     stale = true;
     if (++since == 4) {
       C.rmax2 = farthest_bound(C);
