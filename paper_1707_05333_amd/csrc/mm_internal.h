@@ -120,20 +120,26 @@ struct Face {
   double f[3];      // area centroid minus r_i
 };
 
-// Everything the face kernel reads of one cell, in one aligned record so a
-// gather of a neighbour touches two or three cache lines: the half-step
-// state and its gradient (precision type), the mesh velocity, the centroid
-// minus the generator, and the generator.
+// Everything the face kernel reads of one cell, in one aligned record: the
+// half-step state and its gradient, the mesh velocity and the centroid
+// minus the generator, all in the precision type, and the generator in
+// FP64 (face normals are differences of nearby generators).  240 bytes in
+// FP64, 144 in mixed precision.
 template <typename R>
 struct __align__(16) FluxCell {
   R U[5];
   R G[15];
-  double w[3];
-  double c[3];
+  R w[3];      // mesh velocity
+  R c[3];      // centroid relative to the generator
   double r[3];
+  // A record stride of a whole number of cache lines puts the same word of
+  // every gathered record in the same cache bank; the mixed record is
+  // padded off the 128-byte multiple.
+  double pad[sizeof(R) == 4 ? 2 : 0];
 };
 
 static_assert(sizeof(StageNbr) == 8, "two staged entries per 16-byte load");
+static_assert(sizeof(FluxCell<float>) == 144 && sizeof(FluxCell<double>) == 240, "face kernel record sizes");
 
 // Per-cell neighbour entry used by the gradient kernel: neighbour index,
 // centroid displacement d = c_j + s - c_i and LSQ weight A / |d|^2, in the
