@@ -902,7 +902,13 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
   const double rloc = !dense ? g.r_filter
                               : g.r_filter * cbrt((cnt > (unsigned)kDense ? g.ppb : 4.0) / (double)cnt);
 
-  if (MODE == 0 && cnt > (unsigned)kDense) return;   // listed for the dense first pass by the sort
+  if (MODE == 0 && cnt > (unsigned)kDense) {
+    // Listed for the dense first pass by the sort, unless the bucket is
+    // beyond what the sort orders: then the call fails (the sort has
+    // flagged it) and the cell gets empty outputs here.
+    if (cnt > (unsigned)kDenseMax) fail_cell(A, s, seg, F_DENSE);
+    return;
+  }
   if (MODE < 2) {
     const int ring = dense ? min(g.ring, ring_for(g, edge, rloc * rloc)) : g.ring;
     double reach = 1e300;

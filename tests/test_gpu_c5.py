@@ -126,3 +126,37 @@ def test_c5_full_size_sampled_and_conservation(orc):
         print(f"step {k}: dt {info['dt']:.3e} floors {info['floor_hits']}", flush=True)
     assert bool(torch.isfinite(Q).all())
     assert abs(float(Q[:, 0].sum()) - m0) <= 1e-13 * m0
+
+
+def _cluster(n_in, n_out, width, seed, centre=0.5):
+    rng = np.random.default_rng(seed)
+    inner = centre + rng.normal(scale=width, size=(n_in, 3))
+    outer = rng.uniform(0.0, 1.0, size=(n_out, 3))
+    return np.ascontiguousarray(np.vstack([inner, outer]) % 1.0)
+
+
+def test_large_sub_grids_match_oracle(orc):
+    # A Gaussian cluster of 3000 points in a uniform background of 2000:
+    # the grid's central buckets hold up to ~2,000 points (sub-grids up to
+    # 10^3), every query crosses the boundary between the two levels.
+    import paper_1707_05333_amd as M
+    pos = _cluster(3000, 2000, 0.02, seed=12)
+    _case("cluster tessellation", n=pos.shape[0])
+    mm = M.MovingMesh(pos.shape[0], M.make_params(box=(1, 1, 1)))
+    info = mm.tessellate(dev(pos))
+    om = orc.tessellate(pos, (1, 1, 1), certificate=True)
+    assert om.status == 0 and om.delta_min > 1e-12
+    compare_mesh(mm, om)
+    assert info["n_faces"] * 2 == len(om.j)
+
+
+def test_bucket_beyond_sort_capacity_is_refused():
+    # 5000 points within ~1e-3 of one spot among 1000 spread ones: one grid
+    # bucket holds more points than the in-LDS sort of a bucket takes.
+    import paper_1707_05333_amd as M
+    pos = _cluster(5000, 1000, 3e-4, seed=13, centre=0.52)   # well inside one bucket
+    _case("bucket over capacity", n=pos.shape[0])
+    mm = M.MovingMesh(pos.shape[0], M.make_params(box=(1, 1, 1)))
+    with pytest.raises(M.MMError) as e:
+        mm.tessellate(dev(pos))
+    assert e.value.name == "MM_ECAPACITY" and "density contrast" in str(e.value)
