@@ -65,8 +65,8 @@ PEAK_VALU_WAVE_INSTR = 256 * 4 * 2.4e9 / 4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)   # the Sod configuration runs 50 steps
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--workload", choices=["sod", "blast"], default="sod")
     ap.add_argument("--no-cpu-baseline", action="store_true")

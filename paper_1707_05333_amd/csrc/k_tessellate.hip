@@ -963,7 +963,9 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
     const double rm2 = A.rmax2[s];
     const double rf2 = rloc * rloc;
     double lo2 = 0.0;
-    double hi2 = rm2 > 0.0 ? fmin(4.0 * rm2 * (1.0 + 1e-9), 4.0 * rf2) : rf2;
+    // The first shell holds about twice the first pass's expected
+    // candidates (a wider one overflowed and was halved, often twice).
+    double hi2 = rm2 > 0.0 ? fmin(4.0 * rm2 * (1.0 + 1e-9), 1.55 * rf2) : rf2;
     bool done = false;
     for (int shell = 0; shell < kShells && !done; ++shell) {
       const int ring = ring_for(g, edge, hi2);
@@ -973,12 +975,14 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
       }
       // Buckets, sub-bucket rows and points that cannot cut the cell are
       // left out (a cell next to a much denser region sees only the few
-      // points that face it).
-      const int nv = vertex_list(C, vl);
-      int nc = gather<true>(S, A, g, s, r, b, ring, lo2, hi2, vl, nv);
+      // points that face it).  The first shell starts from the box, which
+      // prunes nothing: it takes the plain gather.
+      const int nv = shell > 0 ? vertex_list(C, vl) : 0;
+      const double4* vlp = nv ? vl : nullptr;
+      int nc = gather<true>(S, A, g, s, r, b, ring, lo2, hi2, vlp, nv);
       for (int tries = 0; nc > kCands && tries < 40; ++tries) {
         hi2 = lo2 + 0.5 * (hi2 - lo2);
-        nc = gather<true>(S, A, g, s, r, b, ring, lo2, hi2, vl, nv);
+        nc = gather<true>(S, A, g, s, r, b, ring, lo2, hi2, vlp, nv);
       }
       if (nc > kCands) {
         fail_cell(A, s, seg, F_CANDS);
@@ -1026,7 +1030,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
     tess_cell<1>(lds[w], A, A.dcells[it]);
 }
 
-__global__ __launch_bounds__(64 * kWaves) void k_tess_pass2(TessArgs A) {
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_tess_pass2(TessArgs A) {
   __shared__ TessLds lds[kWaves];
   __shared__ double4 verts[kWaves][kVerts];   // the cell's live vertices, for pruning candidates
   const int w = threadIdx.x >> 6;
