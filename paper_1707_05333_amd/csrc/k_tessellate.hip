@@ -38,6 +38,7 @@ namespace {
 constexpr int kWaves = MM_TESS_WAVES;   // cells (wavefronts) per workgroup
 constexpr int kShells = 512;            // distance shells of the second pass
 constexpr int kShells1 = 3;             // extra shells a cell may take in the first pass
+constexpr int kFewCands = 8;            // below this many first candidates, a cell's region is thin
 
 // 10.8 KB per wavefront, so 15 cells fit the 160 KB of LDS of a CU.  The
 // candidate list is only needed while cutting and the vertex copies only in
@@ -871,12 +872,13 @@ __device__ void defer_dense(const TessArgs& A, int s) {
 // Builds the cell of internal generator s.
 // MODE 0 (first pass, every cell): candidates within the grid's filter
 //   radius; a cell whose candidates do not cover twice its farthest vertex
-//   (or overflow the candidate slots) is deferred to the shell pass, and a
-//   cell with a dense bucket in its own bucket or stencil goes to MODE 1.
+//   goes on with up to kShells1 more shells (when it found at least
+//   kFewCands candidates), and one that still falls short (or overflows the
+//   candidate slots) is deferred to the shell pass; a cell with a dense
+//   bucket in its own bucket or stencil goes to MODE 1.
 //   This kernel stays lean (uniform inputs finish here).
 // MODE 1 (first pass of the cells near dense regions): the same with the
-//   two-level gather, and a cell that falls short goes on with up to
-//   kShells1 more shells before it is deferred.
+//   two-level gather.
 // MODE 2 (shell pass): distance shells [lo, hi) processed in order, each
 //   gathered from a stencil wide enough for it and narrowed until it fits
 //   the candidate slots, until twice the farthest vertex lies inside the
@@ -938,13 +940,20 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
     for (int shell = 0; !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)); ++shell) {
       const double nhi2 = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
       const int nring = ring_for(g, edge, nhi2);
-      if (MODE == 0 || shell == kShells1 || nring > g.nb[0] || nring > g.nb[1] || nring > g.nb[2]) {
+      // (A thin region's cell, with few candidates found, needs wide shells
+      // that only the shell pass's pruning keeps cheap.)
+      if (shell == kShells1 || (MODE == 0 && nc < kFewCands) || nring > g.nb[0] || nring > g.nb[1] ||
+          nring > g.nb[2]) {
         defer_cell(A, s, C.rmax2);
         return;
       }
       lo2 = hi2;
       hi2 = nhi2;
-      const int nc2 = gather<true>(S, A, g, s, r, b, nring, lo2, hi2);
+      const int nc2 = gather<MODE != 0>(S, A, g, s, r, b, nring, lo2, hi2);
+      if (nc2 < 0) {
+        defer_dense(A, s);
+        return;
+      }
       if (nc2 > kCands) {
         defer_cell(A, s, C.rmax2);
         return;
