@@ -724,9 +724,11 @@ __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const Cel
   // The candidate list is dead now: its storage takes the vertex copies.
   wave_sync();
   S.vx[lane] = C.v0x; S.vy[lane] = C.v0y; S.vz[lane] = C.v0z;
-  S.vx[lane + 64] = C.v1x; S.vy[lane + 64] = C.v1y; S.vz[lane + 64] = C.v1z;
   S.tri[lane] = C.t0;
-  S.tri[lane + 64] = C.t1;
+  if (C.L1 != 0ull) {
+    S.vx[lane + 64] = C.v1x; S.vy[lane + 64] = C.v1y; S.vz[lane + 64] = C.v1z;
+    S.tri[lane + 64] = C.t1;
+  }
   S.first[lane] = kVerts;
   wave_sync();
   if (live0) {
@@ -755,7 +757,8 @@ __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const Cel
   if (valid) {
     const double4 P = S.pl[p];
     dl = sqrt(2.0 * P.w);
-    const double nx = P.x / dl, ny = P.y / dl, nz = P.z / dl;
+    const double idl = 1.0 / dl;
+    const double nx = P.x * idl, ny = P.y * idl, nz = P.z * idl;
     const int tstart = S.first[p];
     const double ox = S.vx[tstart], oy = S.vy[tstart], oz = S.vz[tstart];
     int t = tstart, it = 0;
@@ -777,18 +780,20 @@ __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const Cel
     } while (t != tstart && it < kVerts);
     walk_bad = (t != tstart);
     Af = as;
-    fx = ox + mx / (3.0 * as);
-    fy = oy + my / (3.0 * as);
-    fz = oz + mz / (3.0 * as);
+    const double i3a = 1.0 / (3.0 * as);
+    fx = ox + mx * i3a;
+    fy = oy + my * i3a;
+    fz = oz + mz * i3a;
   }
   if (__ballot(walk_bad)) return F_WALK;
   // A plane that only touches the cell gives no face (non-positive area).
   const bool keep = valid && Af > 0.0;
   const double vol = keep ? Af * dl / 6.0 : 0.0;
   const double V = wave_sum(vol);
-  const double cxr = wave_sum(0.75 * vol * fx) / V;
-  const double cyr = wave_sum(0.75 * vol * fy) / V;
-  const double czr = wave_sum(0.75 * vol * fz) / V;
+  const double iV = 1.0 / V;
+  const double cxr = wave_sum(keep ? 0.75 * vol * fx : 0.0) * iV;
+  const double cyr = wave_sum(keep ? 0.75 * vol * fy : 0.0) * iV;
+  const double czr = wave_sum(keep ? 0.75 * vol * fz : 0.0) * iV;
   if (!(V > 0.0)) return F_VOLUME;
 
   int j = s, code = 13;
