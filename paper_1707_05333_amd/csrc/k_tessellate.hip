@@ -538,22 +538,31 @@ __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const 
 // are rare (lattice symmetries), so the ranks are first taken by distance
 // alone and redone with the identities only when some distance repeats.
 __device__ void sort_candidates(TessLds& S, const int nc) {
-  bool tie = false;
-  for (int c = __lane_id(); c < nc; c += 64) {
-    const double key = S.cd[c].w;
-    int lt = 0, eq = 0;
+  // Rank by distance alone; with no repeated distance the ranks are a
+  // permutation, and a repeated one makes two candidates write the same
+  // slot, which the read-back shows.
+  int lt0 = 0, lt1 = 0;
+  const int c0 = __lane_id(), c1 = __lane_id() + 64;
+  if (nc <= 64) {
+    if (c0 < nc) {
+      const double k0 = S.cd[c0].w;
+      for (int m = 0; m < nc; ++m) lt0 += S.cd[m].w < k0;
+      S.order[lt0] = (uint8_t)c0;
+    }
+  } else {
+    const double k0 = S.cd[c0].w, k1 = c1 < nc ? S.cd[c1].w : 0.0;
     for (int m = 0; m < nc; ++m) {
       const double km = S.cd[m].w;
-      lt += km < key;
-      eq += km == key;
+      lt0 += km < k0;
+      lt1 += km < k1;
     }
-    tie |= eq > 1;
-    if (eq == 1) S.order[lt] = (uint8_t)c;
+    S.order[lt0] = (uint8_t)c0;
+    if (c1 < nc) S.order[lt1] = (uint8_t)c1;
   }
-  if (__ballot(tie) == 0ull) {
-    wave_sync();
-    return;
-  }
+  wave_sync();
+  const bool tie = (c0 < nc && S.order[lt0] != c0) || (c1 < nc && S.order[lt1] != c1);
+  if (__ballot(tie) == 0ull) return;
+  wave_sync();
   for (int c = __lane_id(); c < nc; c += 64) {
     const double key = S.cd[c].w;
     const int id = S.cjk[c];
