@@ -579,12 +579,6 @@ __device__ void sort_candidates(TessLds& S, const int nc) {
 // A value every lane holds equally (read from LDS at a uniform address),
 // moved to a scalar register so branches on it are uniform.
 __device__ inline int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ inline double uniform_f64(double x) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 // Squared distance bound of the farthest live vertex (float, rounded up).
 __device__ inline double farthest_bound(const CellRegs& C) {
@@ -606,15 +600,16 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
   bool stale = false;
   int since = 0;   // cuts since the bound was last recomputed
   for (int k = 0; k < nc; ++k) {
-    const int c = uniform_i32(S.order[k]);
-    const double4 ql = S.cd[c];
-    const double4 q = make_double4(uniform_f64(ql.x), uniform_f64(ql.y), uniform_f64(ql.z), uniform_f64(ql.w));
-    if (q.w >= 4.0 * C.rmax2) {   // farther images cannot cut the cell
+    // Every lane reads the same candidate (an LDS broadcast); it stays in
+    // vector registers, and the stop test is made uniform by a ballot.
+    const int c = S.order[k];
+    const double4 q = S.cd[c];
+    if (__ballot(q.w >= 4.0 * C.rmax2)) {   // farther images cannot cut the cell
       if (!stale) break;
       C.rmax2 = farthest_bound(C);
       stale = false;
       since = 0;
-      if (q.w >= 4.0 * C.rmax2) break;
+      if (__ballot(q.w >= 4.0 * C.rmax2)) break;
     }
     const double h = 0.5 * q.w;
     // Most cells keep every vertex in the first register (64 slots); the
