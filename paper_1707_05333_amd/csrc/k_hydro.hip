@@ -747,6 +747,9 @@ __device__ inline void cell_flux_sum(int64_t s, const unsigned long long* counts
   const int32_t* list = csr + sell_slot(soff, s, 0);   // entry e at list[64 e]
 #pragma unroll
   for (int q = 0; q < 5; ++q) acc[q] = 0.0;
+  // Unrolled so the loads of four entries are in flight together (the sum
+  // keeps its order).
+#pragma unroll 4
   for (int e = 0; e < nf; ++e) {
     const int32_t cf = list[64 * e];
     const int64_t fid = cf & 0x7fffffff;
@@ -789,6 +792,7 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
     const int nfc = (int)(counts[s] >> 32);
     const int32_t* list = csr + sell_slot(soff, s, 0);
     double accX = 0.0;
+#pragma unroll 4
     for (int e = 0; e < nfc; ++e) {
       const int32_t cf = list[64 * e];
       const int64_t fid = cf & 0x7fffffff;

@@ -120,16 +120,17 @@ __global__ __launch_bounds__(kMeshThreads) void k_build_mesh(
         const int want = 26 - code;
         const int nfj = (int)(counts[j] >> 32);
         const int4* row = reinterpret_cast<const int4*>(stage_nb + (int64_t)j * kMaxFaces);
+        // Eight entries per round, their loads issued together.
         int found_meta = -1;
-        for (int t = 0; t < nfj; t += 2) {
-          const int4 G = row[t >> 1];
-          if (G.x == (int)s && (G.y & 255) == want) {
-            found_meta = G.y;
-            break;
-          }
-          if (t + 1 < nfj && G.z == (int)s && (G.w & 255) == want) {
-            found_meta = G.w;
-            break;
+        for (int t = 0; t < nfj && found_meta < 0; t += 8) {
+          int4 G[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) G[u] = row[(t >> 1) + u];   // rows hold kMaxFaces entries: in bounds
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e0 = t + 2 * u;
+            if (found_meta < 0 && e0 < nfj && G[u].x == (int)s && (G[u].y & 255) == want) found_meta = G[u].y;
+            if (found_meta < 0 && e0 + 1 < nfj && G[u].z == (int)s && (G[u].w & 255) == want) found_meta = G[u].w;
           }
         }
         if (found_meta < 0 || !((found_meta >> 8) & 1)) {
