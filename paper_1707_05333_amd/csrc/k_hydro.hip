@@ -382,6 +382,10 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
   }
 #pragma unroll
   for (int k = 0; k < 15; ++k) b[k] = R(0);
+  // Two entries' loads in flight at once pay in FP64 (10% faster) but not
+  // with the smaller FP32 entries (10% slower).
+  constexpr int kUnroll = sizeof(R) == 8 ? 2 : 1;
+#pragma unroll kUnroll
   for (int e = 0; e < nf; ++e) {
     const NbrEntry<R> E = list[64 * e];
     const R dx = E.d[0], dy = E.d[1], dz = E.d[2], wg = E.wgt;
