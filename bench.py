@@ -592,7 +592,7 @@ def serving_object(M, torch, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
