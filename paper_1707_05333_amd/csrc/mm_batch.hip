@@ -309,7 +309,6 @@ mm_status mm_batch_step(mm_batch* b, mm_sim_info* info, int32_t info_cap, int32_
     if (info && out < info_cap) info[out++] = I;
   }
   if (n_info) *n_info = out;
-  if (!global_cap) E.adapt_filter();
   return global_cap ? b->fail(MM_ECAPACITY, "more unique faces than the batch's face capacity") : MM_OK;
 }
 

@@ -329,19 +329,6 @@ void Engine::finish_timing() {
   }
 }
 
-// The first-pass radius only changes how much work goes to the shell pass,
-// never the cells (clipping is always in order of distance, ties broken by
-// neighbour and image).  Narrow it when first-pass candidates overflowed
-// (dense regions), widen it when many cells were deferred for a too short
-// reach (sparse regions), narrow it slowly when none were.  The cap keeps
-// the candidates of a uniform region (about 4.2 rfac^3) well inside kCands.
-void Engine::adapt_filter() {
-  const double d = st_host->n_deferred, o = st_host->n_overflow, nn = (double)n;
-  if (o > 0.002 * nn) rfac = std::max(rfac * 0.9, 1.9);
-  else if (d > 0.02 * nn) rfac = std::min(rfac * 1.1, 2.4);
-  else if (d < 0.002 * nn) rfac = std::max(rfac * 0.98, 1.9);
-}
-
 mm_status Engine::check_flags(int flags, int bad_cell, std::string& msg) const {
   if (!flags) return MM_OK;
   char buf[256];

@@ -112,7 +112,6 @@ mm_status start_tessellation(mm_ctx* c, int64_t n, const double* pos, double dt_
 void finish_mesh(mm_ctx* c, int64_t n) {
   c->E.n = n;
   c->E.n_faces = (int64_t)c->E.st_host->n_faces;
-  c->E.adapt_filter();
   c->have_mesh = true;
 }
 
