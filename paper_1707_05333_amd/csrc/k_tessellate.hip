@@ -616,12 +616,14 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     // second register's work is skipped while it holds none (a
     // wavefront-uniform test).
     const bool two = C.L1 != 0ull;
-    const bool live0 = (C.L0 >> lane) & 1ull, live1 = two && ((C.L1 >> lane) & 1ull);
-    const bool out0 = live0 && (q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h);
-    bool out1 = false;
-    if (two) out1 = live1 && (q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h);
-    const unsigned long long M0 = __ballot(out0), M1 = two ? __ballot(out1) : 0ull;
+    // The test runs on every slot; the live masks (wavefront-uniform) keep
+    // the live ones.
+    const unsigned long long M0 = __ballot(q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h) & C.L0;
+    unsigned long long M1 = 0ull;
+    if (two) M1 = __ballot(q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h) & C.L1;
     if ((M0 | M1) == 0ull) continue;
+    const bool live0 = (C.L0 >> lane) & 1ull, live1 = two && ((C.L1 >> lane) & 1ull);
+    const bool out0 = (M0 >> lane) & 1ull, out1 = (M1 >> lane) & 1ull;
 
     // Plane slot for the new face: the next unused slot while there is one,
     // then the lowest slot no surviving vertex uses.
