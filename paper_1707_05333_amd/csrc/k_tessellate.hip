@@ -48,7 +48,7 @@ struct __align__(16) TessLds {
   double4 pl[kPlanes];                 // plane: d.x, d.y, d.z, h
   union {
     struct {
-      double4 cd[kCands];              // candidate image: d, |d|^2
+      double4 cd[kCands];              // candidate image: d, |d|^2 / 2
       int32_t cjk[kCands];             // candidate: j << 5 | image code
       uint8_t order[kCands];
     };
@@ -444,7 +444,7 @@ __device__ int gather_runs(TessLds& S, const TessArgs& A, const GridParams& g, c
         if (keep) {
           const int idx = nc + __popcll(mk & lanes_below());
           if (idx < kCands) {
-            S.cd[idx] = make_double4(dx, dy, dz, d2);
+            S.cd[idx] = make_double4(dx, dy, dz, 0.5 * d2);
             S.cjk[idx] = (j << 5) | code_o;
           }
         }
@@ -514,7 +514,7 @@ __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const 
       if (keep0) {
         const int idx = nc + __popcll(mk0 & lanes_below());
         if (idx < kCands) {
-          S.cd[idx] = make_double4(dx0, dy0, dz0, d20);
+          S.cd[idx] = make_double4(dx0, dy0, dz0, 0.5 * d20);
           S.cjk[idx] = (j0 << 5) | B0.code;
         }
       }
@@ -522,7 +522,7 @@ __device__ int gather(TessLds& S, const TessArgs& A, const GridParams& g, const 
       if (keep1) {
         const int idx = nc + n0 + __popcll(mk1 & lanes_below());
         if (idx < kCands) {
-          S.cd[idx] = make_double4(dx1, dy1, dz1, d21);
+          S.cd[idx] = make_double4(dx1, dy1, dz1, 0.5 * d21);
           S.cjk[idx] = (j1 << 5) | B1.code;
         }
       }
@@ -599,19 +599,21 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
   const int lane = __lane_id();
   bool stale = false;
   int since = 0;   // cuts since the bound was last recomputed
+  double lim = 2.0 * C.rmax2;   // a candidate with |d|^2 / 2 >= lim cannot cut
   for (int k = 0; k < nc; ++k) {
     // Every lane reads the same candidate (an LDS broadcast); it stays in
     // vector registers, and the stop test is made uniform by a ballot.
     const int c = S.order[k];
     const double4 q = S.cd[c];
-    if (__ballot(q.w >= 4.0 * C.rmax2)) {   // farther images cannot cut the cell
+    const double h = q.w;                 // |d|^2 / 2: the plane's offset
+    if (__ballot(h >= lim)) {   // farther images cannot cut the cell
       if (!stale) break;
       C.rmax2 = farthest_bound(C);
       stale = false;
       since = 0;
-      if (__ballot(q.w >= 4.0 * C.rmax2)) break;
+      lim = 2.0 * C.rmax2;
+      if (__ballot(h >= lim)) break;
     }
-    const double h = 0.5 * q.w;
     // Most cells keep every vertex in the first register (64 slots); the
     // second register's work is skipped while it holds none (a
     // wavefront-uniform test).
@@ -715,6 +717,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     stale = true;
     if (++since == 4) {
       C.rmax2 = farthest_bound(C);
+      lim = 2.0 * C.rmax2;
       stale = false;
       since = 0;
     }
