@@ -687,6 +687,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     // around the new face.  Boundary edge r goes to the free slot of rank r
     // (slots of the first register in lane order, then of the second), and
     // the lane holding that slot builds it in place.
+    const double4 qp = make_double4(q.x, q.y, q.z, h);
     const int r0 = __popcll(F0 & lanes_below());
     const int r1 = nf0 + __popcll(F1 & lanes_below());
     const bool new0 = ((F0 >> lane) & 1ull) && r0 < B;
@@ -695,7 +696,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
       const int xy = S.elist[r0];
       const int x = xy & 255, y = xy >> 8;
       C.t0 = (uint32_t)(x | (y << 8) | (p << 16));
-      intersect3(S.pl[x], S.pl[y], S.pl[p], C.v0x, C.v0y, C.v0z);
+      intersect3(S.pl[x], S.pl[y], qp, C.v0x, C.v0y, C.v0z);
       S.E[x * kPlanes + y] = (uint8_t)lane;
       S.E[y * kPlanes + p] = (uint8_t)lane;
       S.E[p * kPlanes + x] = (uint8_t)lane;
@@ -704,7 +705,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
       const int xy = S.elist[r1];
       const int x = xy & 255, y = xy >> 8;
       C.t1 = (uint32_t)(x | (y << 8) | (p << 16));
-      intersect3(S.pl[x], S.pl[y], S.pl[p], C.v1x, C.v1y, C.v1z);
+      intersect3(S.pl[x], S.pl[y], qp, C.v1x, C.v1y, C.v1z);
       S.E[x * kPlanes + y] = (uint8_t)(lane + 64);
       S.E[y * kPlanes + p] = (uint8_t)(lane + 64);
       S.E[p * kPlanes + x] = (uint8_t)(lane + 64);
