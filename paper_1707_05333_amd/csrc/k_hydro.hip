@@ -16,6 +16,14 @@ constexpr int kThreads = 256;
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Orders a wavefront's LDS accesses: everything before is visible to every
+// lane of the wavefront after.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // a / b: correctly rounded in double; in float (the mixed-precision state
 // arithmetic) through the hardware reciprocal, within about one ulp.
 template <typename T>
@@ -540,100 +548,128 @@ __device__ inline FaceParams face_params(const SegDesc* segs, const SegStatus* d
 // One thread per unique face (Sec. 4 items 1-5, Sec. 4.1 reconstruction):
 // phi = dt A F, F the lab-frame flux from the owner i toward j.  Each XCD
 // takes one contiguous eighth of the face list (faces are in owner order, so
-// the cells it gathers stay in its L2) and its blocks stride through it.
+// the cells it gathers stay in its L2) and its wavefronts stride through it.
 // With ENT the entropy column's face flux and the face's shock Mach number
 // are written as well (Sec. 4.3).
+// The owners of a wavefront's faces are a few consecutive cells, but its 64
+// neighbours are scattered: rather than each lane fetching its neighbour's
+// record alone (every load instruction then touches 64 cache lines), the
+// wavefront fetches the 64 records together, consecutive lanes taking
+// consecutive 16-byte pieces of one record, and hands them over in LDS.
+constexpr int kFluxThreads = 128;
+
 template <typename R, bool ENT>
-__global__ __launch_bounds__(kThreads) void k_flux(const SegDesc* __restrict__ segs, int64_t nf_host,
-                                                   const unsigned long long* __restrict__ nf_dev,
-                                                   const Face* __restrict__ faces,
-                                                   const FluxCell<R>* __restrict__ rec, const SegStatus* dt_src,
-                                                   double dt_fixed, R* __restrict__ phi, SegStatus* segst,
-                                                   const XCell<R>* __restrict__ recx, R* __restrict__ phiX,
-                                                   float* __restrict__ machF) {
+__global__ __launch_bounds__(kFluxThreads, sizeof(R) == 8 ? 6 : 8) void k_flux(const SegDesc* __restrict__ segs, int64_t nf_host,
+                                                       const unsigned long long* __restrict__ nf_dev,
+                                                       const Face* __restrict__ faces,
+                                                       const FluxCell<R>* __restrict__ rec, const SegStatus* dt_src,
+                                                       double dt_fixed, R* __restrict__ phi, SegStatus* segst,
+                                                       const XCell<R>* __restrict__ recx, R* __restrict__ phiX,
+                                                       float* __restrict__ machF) {
+  constexpr int kPieces = (int)(sizeof(FluxCell<R>) / sizeof(uint4));
+  static_assert(sizeof(FluxCell<R>) % sizeof(uint4) == 0, "records are whole 16-byte pieces");
+  __shared__ uint4 stage[kFluxThreads / 64][64 * kPieces];
+  const int lane = __lane_id();
+  uint4* const own = stage[threadIdx.x >> 6];
   const int64_t nf = nf_dev ? std::min<int64_t>((int64_t)*nf_dev, nf_host) : nf_host;
   const int64_t xcd = blockIdx.x % kXcds, kb = blockIdx.x / kXcds;
   const int64_t nbx = ((int64_t)gridDim.x - xcd + kXcds - 1) / kXcds;
   const int64_t lo = nf * xcd / kXcds, hi = nf * (xcd + 1) / kXcds;
-  for (int64_t f = lo + kb * blockDim.x + threadIdx.x; f < hi; f += nbx * blockDim.x) {
-    const Face F = faces[f];
-    const FluxCell<R> A = rec[F.i];
-    const FluxCell<R> B = rec[F.j];
-    const int seg = F.seg;
-    const FaceParams hp = face_params(segs, dt_src, dt_fixed, seg);
-    int kx, ky, kz;
-    decode(F.code, kx, ky, kz);
-    // Geometry in double: r_j + s - r_i, face centre and centroid offsets.
-    const double drx = (B.r[0] + kx * hp.L[0]) - A.r[0];
-    const double dry = (B.r[1] + ky * hp.L[1]) - A.r[1];
-    const double drz = (B.r[2] + kz * hp.L[2]) - A.r[2];
-    const double len = sqrt(drx * drx + dry * dry + drz * drz);
-    const double ilen = 1.0 / len;
-    const double nx = drx * ilen, ny = dry * ilen, nz = drz * ilen;
-    // Face velocity (Sec. 4 item 1): bisector's normal speed at the face
-    // centre plus the mean generator velocity.
-    const double sn = ((A.w[0] - B.w[0]) * (F.f[0] - 0.5 * drx) + (A.w[1] - B.w[1]) * (F.f[1] - 0.5 * dry) +
-                       (A.w[2] - B.w[2]) * (F.f[2] - 0.5 * drz)) * ilen;
-    const R wt[3] = {(R)(sn * nx + 0.5 * (A.w[0] + B.w[0])), (R)(sn * ny + 0.5 * (A.w[1] + B.w[1])),
-                     (R)(sn * nz + 0.5 * (A.w[2] + B.w[2]))};
-    const R nrm[3] = {(R)nx, (R)ny, (R)nz};
-    // f - c_i and f - (c_j + s), with f and c relative to the generators.
-    const R fi[3] = {(R)(F.f[0] - A.c[0]), (R)(F.f[1] - A.c[1]), (R)(F.f[2] - A.c[2])};
-    const R fj[3] = {(R)(F.f[0] - drx - B.c[0]), (R)(F.f[1] - dry - B.c[1]), (R)(F.f[2] - drz - B.c[2])};
-    const R theta = (R)hp.theta;
-    R UL[5], UR[5];
+  for (int64_t f0 = lo + kb * blockDim.x + (threadIdx.x & ~63); f0 < hi; f0 += nbx * blockDim.x) {
+    const int64_t f = f0 + lane;
+    const bool valid = f < hi;
+    Face F;
+    if (valid) F = faces[f];
+    const int jl = valid ? F.j : 0;   // a lane past the end fetches record 0 and ignores it
+    // Piece q = lane + 64 k of the wavefront's records is piece q % kPieces
+    // of the record of lane q / kPieces.
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const R ui = A.U[q], uj = B.U[q];
-      const R Di = A.G[3 * q] * fi[0] + A.G[3 * q + 1] * fi[1] + A.G[3 * q + 2] * fi[2];
-      const R Dj = B.G[3 * q] * fj[0] + B.G[3 * q + 1] * fj[1] + B.G[3 * q + 2] * fj[2];
-      UL[q] = ui + dm_limited(theta, uj - ui, Di);
-      UR[q] = uj + dm_limited(theta, ui - uj, Dj);
+    for (int k = 0; k < kPieces; ++k) {
+      const int q = lane + 64 * k;
+      const int j = __shfl(jl, q / kPieces);
+      own[q] = reinterpret_cast<const uint4*>(rec + j)[q % kPieces];
     }
-    const R g1 = (R)(hp.gamma - 1.0);
-    // A side whose reconstruction would need a floor takes its cell's
-    // half-step state (already floored): extrapolating each component
-    // across a large density jump can pair a small density with a large
-    // momentum, a velocity no floor repairs.
-    bool fbL, fbR;
-    {
-      R t[5];
-#pragma unroll
-      for (int q = 0; q < 5; ++q) t[q] = UL[q];
-      fbL = apply_floors(t, g1, (R)hp.rho_floor, (R)hp.p_floor) != 0;
-#pragma unroll
-      for (int q = 0; q < 5; ++q) t[q] = UR[q];
-      fbR = apply_floors(t, g1, (R)hp.rho_floor, (R)hp.p_floor) != 0;
+    wave_sync();
+    if (valid) {
+      const FluxCell<R> A = rec[F.i];
+      const FluxCell<R>& B = *reinterpret_cast<const FluxCell<R>*>(own + lane * kPieces);
+      const int seg = F.seg;
+      const FaceParams hp = face_params(segs, dt_src, dt_fixed, seg);
+      int kx, ky, kz;
+      decode(F.code, kx, ky, kz);
+      // Geometry in double: r_j + s - r_i, face centre and centroid offsets.
+      const double drx = (B.r[0] + kx * hp.L[0]) - A.r[0];
+      const double dry = (B.r[1] + ky * hp.L[1]) - A.r[1];
+      const double drz = (B.r[2] + kz * hp.L[2]) - A.r[2];
+      const double len = sqrt(drx * drx + dry * dry + drz * drz);
+      const double ilen = 1.0 / len;
+      const double nx = drx * ilen, ny = dry * ilen, nz = drz * ilen;
+      // Face velocity (Sec. 4 item 1): bisector's normal speed at the face
+      // centre plus the mean generator velocity.
+      const double sn = ((A.w[0] - B.w[0]) * (F.f[0] - 0.5 * drx) + (A.w[1] - B.w[1]) * (F.f[1] - 0.5 * dry) +
+                         (A.w[2] - B.w[2]) * (F.f[2] - 0.5 * drz)) * ilen;
+      const R wt[3] = {(R)(sn * nx + 0.5 * (A.w[0] + B.w[0])), (R)(sn * ny + 0.5 * (A.w[1] + B.w[1])),
+                       (R)(sn * nz + 0.5 * (A.w[2] + B.w[2]))};
+      const R nrm[3] = {(R)nx, (R)ny, (R)nz};
+      // f - c_i and f - (c_j + s), with f and c relative to the generators.
+      const R fi[3] = {(R)(F.f[0] - A.c[0]), (R)(F.f[1] - A.c[1]), (R)(F.f[2] - A.c[2])};
+      const R fj[3] = {(R)(F.f[0] - drx - B.c[0]), (R)(F.f[1] - dry - B.c[1]), (R)(F.f[2] - drz - B.c[2])};
+      const R theta = (R)hp.theta;
+      R UL[5], UR[5];
+  #pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const R ui = A.U[q], uj = B.U[q];
+        const R Di = A.G[3 * q] * fi[0] + A.G[3 * q + 1] * fi[1] + A.G[3 * q + 2] * fi[2];
+        const R Dj = B.G[3 * q] * fj[0] + B.G[3 * q + 1] * fj[1] + B.G[3 * q + 2] * fj[2];
+        UL[q] = ui + dm_limited(theta, uj - ui, Di);
+        UR[q] = uj + dm_limited(theta, ui - uj, Dj);
+      }
+      const R g1 = (R)(hp.gamma - 1.0);
+      // A side whose reconstruction would need a floor takes its cell's
+      // half-step state (already floored): extrapolating each component
+      // across a large density jump can pair a small density with a large
+      // momentum, a velocity no floor repairs.
+      bool fbL, fbR;
+      {
+        R t[5];
+  #pragma unroll
+        for (int q = 0; q < 5; ++q) t[q] = UL[q];
+        fbL = apply_floors(t, g1, (R)hp.rho_floor, (R)hp.p_floor) != 0;
+  #pragma unroll
+        for (int q = 0; q < 5; ++q) t[q] = UR[q];
+        fbR = apply_floors(t, g1, (R)hp.rho_floor, (R)hp.p_floor) != 0;
+      }
+      if (fbL) {
+  #pragma unroll
+        for (int q = 0; q < 5; ++q) UL[q] = A.U[q];
+      }
+      if (fbR) {
+  #pragma unroll
+        for (int q = 0; q < 5; ++q) UR[q] = B.U[q];
+      }
+      const int hit = (int)fbL + (int)fbR;
+      if (hit) atomicAdd(&segst[seg].floor_hits[2], (unsigned long long)hit);
+      const R rL0 = UL[0], rR0 = UR[0];
+      R Fx[5];
+      moving_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, (R)hp.p_floor, Fx);
+      const R scale = (R)(hp.dt * F.A);
+  #pragma unroll
+      for (int q = 0; q < 5; ++q) phi[5 * f + q] = scale * Fx[q];
+      if constexpr (ENT) {
+        const XCell<R> XA = recx[F.i], XB = recx[F.j];
+        const R Di = XA.g[0] * fi[0] + XA.g[1] * fi[1] + XA.g[2] * fi[2];
+        const R Dj = XB.g[0] * fj[0] + XB.g[1] * fj[1] + XB.g[2] * fj[2];
+        const R XL = fbL ? XA.X : XA.X + dm_limited(theta, XB.X - XA.X, Di);
+        const R XR = fbR ? XB.X : XB.X + dm_limited(theta, XA.X - XB.X, Dj);
+        R FX;
+        float mach;
+        entropy_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, (R)hp.p_floor, quot(XL, rL0), quot(XR, rR0), FX,
+                     mach);
+        phiX[f] = scale * FX;
+        machF[f] = mach;
+      }
     }
-    if (fbL) {
-#pragma unroll
-      for (int q = 0; q < 5; ++q) UL[q] = A.U[q];
-    }
-    if (fbR) {
-#pragma unroll
-      for (int q = 0; q < 5; ++q) UR[q] = B.U[q];
-    }
-    const int hit = (int)fbL + (int)fbR;
-    if (hit) atomicAdd(&segst[seg].floor_hits[2], (unsigned long long)hit);
-    const R rL0 = UL[0], rR0 = UR[0];
-    R Fx[5];
-    moving_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, (R)hp.p_floor, Fx);
-    const R scale = (R)(hp.dt * F.A);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) phi[5 * f + q] = scale * Fx[q];
-    if constexpr (ENT) {
-      const XCell<R> XA = recx[F.i], XB = recx[F.j];
-      const R Di = XA.g[0] * fi[0] + XA.g[1] * fi[1] + XA.g[2] * fi[2];
-      const R Dj = XB.g[0] * fj[0] + XB.g[1] * fj[1] + XB.g[2] * fj[2];
-      const R XL = fbL ? XA.X : XA.X + dm_limited(theta, XB.X - XA.X, Di);
-      const R XR = fbR ? XB.X : XB.X + dm_limited(theta, XA.X - XB.X, Dj);
-      R FX;
-      float mach;
-      entropy_flux(UL, UR, nrm, wt, (R)hp.gamma, hp.hll, (R)hp.p_floor, quot(XL, rL0), quot(XR, rR0), FX,
-                   mach);
-      phiX[f] = scale * FX;
-      machF[f] = mach;
-    }
+    wave_sync();   // every lane has read its record before the next pieces land
   }
 }
 
@@ -981,13 +1017,13 @@ void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long*
   if (nf_host <= 0) return;
   // Enough resident blocks to fill the chip; each strides through its XCD's
   // part of the (device-counted) face list.
-  const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(nf_host, kThreads), 4096);
+  const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(nf_host, kFluxThreads), 8192);
   if (recx)
-    hipLaunchKernelGGL((k_flux<R, true>), dim3(blocks), dim3(kThreads), 0, st, segs, nf_host, nf_dev, faces, rec,
-                       dt_src, dt_fixed, phi, segst, recx, phiX, machF);
+    hipLaunchKernelGGL((k_flux<R, true>), dim3(blocks), dim3(kFluxThreads), 0, st, segs, nf_host, nf_dev, faces,
+                       rec, dt_src, dt_fixed, phi, segst, recx, phiX, machF);
   else
-    hipLaunchKernelGGL((k_flux<R, false>), dim3(blocks), dim3(kThreads), 0, st, segs, nf_host, nf_dev, faces, rec,
-                       dt_src, dt_fixed, phi, segst, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_flux<R, false>), dim3(blocks), dim3(kFluxThreads), 0, st, segs, nf_host, nf_dev, faces,
+                       rec, dt_src, dt_fixed, phi, segst, nullptr, nullptr, nullptr);
 }
 
 template <typename R>
