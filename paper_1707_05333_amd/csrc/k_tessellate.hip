@@ -40,29 +40,31 @@ constexpr int kShells = 512;            // distance shells of the second pass
 constexpr int kShells1 = 3;             // extra shells a cell may take in the first pass
 constexpr int kFewCands = 8;            // below this many first candidates, a cell's region is thin
 
-// 10.8 KB per wavefront, so 15 cells fit the 160 KB of LDS of a CU.  The
-// candidate list is only needed while cutting and the vertex copies only in
-// the epilogue (while cutting, vertices live in registers and move between
-// lanes by permutes), so the two share storage.
+// 10 KB per wavefront, so 16 cells fit the 160 KB of LDS of a CU (as many
+// as the lean pass's registers allow).  The candidate list and the cut's
+// scratch are only needed while cutting and the vertex copies only in the
+// epilogue (while cutting, vertices and their triangles live in registers),
+// so the two share storage.
 struct __align__(16) TessLds {
   double4 pl[kPlanes];                 // plane: d.x, d.y, d.z, h
   union {
-    struct {
+    struct {                           // while the cell is cut
       double4 cd[kCands];              // candidate image: d, |d|^2 / 2
       int32_t cjk[kCands];             // candidate: j << 5 | image code
       uint8_t order[kCands];
+      uint16_t elist[kVerts];          // boundary edges of one cut: x | y << 8
+      uint8_t kept[kVerts];            // 1 for a live vertex slot that survives the current cut
     };
-    struct {
+    struct {                           // in the epilogue
       double vx[kVerts], vy[kVerts], vz[kVerts];
       int32_t first[kPlanes];
+      uint32_t tri[kVerts];            // a | b << 8 | c << 16
     };
   };
-  uint32_t tri[kVerts];                // a | b << 8 | c << 16
   int32_t pcand[kPlanes];              // neighbour of each plane slot (j << 5 | image code); -1 - k for box plane k
   uint8_t E[kPlanes * kPlanes];
-  uint16_t elist[kVerts];              // boundary edges of one cut: x | y << 8
-  uint8_t kept[kVerts];                // 1 for a live vertex slot that survives the current cut
 };
+static_assert(sizeof(TessLds) <= 10240, "16 cells per CU");
 
 struct TessArgs {
   const double* spos;

@@ -22,7 +22,7 @@ namespace mm {
 // ---------------------------------------------------------------------------
 constexpr int kPlanes = 64;
 constexpr int kVerts = 128;
-constexpr int kCands = 96;
+constexpr int kCands = 92;
 constexpr int kMaxFaces = kPlanes;   // staging slots per cell
 
 // Failure bits collected in DevStatus::flags and SegStatus::flags.
