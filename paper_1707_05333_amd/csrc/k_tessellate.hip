@@ -39,6 +39,10 @@ constexpr int kWaves = MM_TESS_WAVES;   // cells (wavefronts) per workgroup
 constexpr int kShells = 512;            // distance shells of the second pass
 constexpr int kShells1 = 3;             // extra shells a cell may take in the first pass
 constexpr int kFewCands = 8;            // below this many first candidates, a cell's region is thin
+// Live vertices the shell pass keeps for pruning candidates (a cell with
+// more, rare, gathers its shells unpruned); 13 KB of LDS per wavefront with
+// the cell, so the pass's 12 waves per CU (by registers) fit.
+constexpr int kPruneVerts = 96;
 
 // 10 KB per wavefront, so 16 cells fit the 160 KB of LDS of a CU (as many
 // as the lean pass's registers allow).  The candidate list and the cut's
@@ -847,10 +851,12 @@ __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const Cel
 }
 
 // The live vertices of the cell (relative to the generator, w = |v|^2),
-// compacted into vl; returns their number.
+// compacted into vl; returns their number, or 0 (no list) when there are
+// more than kPruneVerts.
 __device__ int vertex_list(const CellRegs& C, double4* vl) {
   const int lane = __lane_id();
-  const int n0 = __popcll(C.L0);
+  const int n0 = __popcll(C.L0), n = n0 + __popcll(C.L1);
+  if (n > kPruneVerts) return 0;
   if ((C.L0 >> lane) & 1ull)
     vl[__popcll(C.L0 & lanes_below())] =
         make_double4(C.v0x, C.v0y, C.v0z, C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z);
@@ -858,7 +864,7 @@ __device__ int vertex_list(const CellRegs& C, double4* vl) {
     vl[n0 + __popcll(C.L1 & lanes_below())] =
         make_double4(C.v1x, C.v1y, C.v1z, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
   wave_sync();
-  return n0 + __popcll(C.L1);
+  return n;
 }
 
 // Points in the cell's own bucket.  Buckets are sized for the mean spacing,
@@ -1058,7 +1064,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
 
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_tess_pass2(TessArgs A) {
   __shared__ TessLds lds[kWaves];
-  __shared__ double4 verts[kWaves][kVerts];   // the cell's live vertices, for pruning candidates
+  __shared__ double4 verts[kWaves][kPruneVerts];   // the cell's live vertices, for pruning candidates
   const int w = threadIdx.x >> 6;
   const int nd = A.st->n_deferred;
   for (int64_t it = (int64_t)blockIdx.x * kWaves + w; it < nd; it += (int64_t)gridDim.x * kWaves)
