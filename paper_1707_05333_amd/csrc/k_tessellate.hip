@@ -1053,7 +1053,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_tess_pass1(TessArgs A) {
 // extra shells keep many values live).
 // The listed cells: those of the dense buckets (listed by the sort) and
 // those the first pass met a dense bucket for.
-__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_tess_pass1_dense(
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_tess_pass1_dense(
     TessArgs A) {
   __shared__ TessLds lds[kWaves];
   const int w = threadIdx.x >> 6;
