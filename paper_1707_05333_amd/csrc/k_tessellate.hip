@@ -1049,8 +1049,8 @@ __global__ __launch_bounds__(64 * kWaves) void k_tess_pass1(TessArgs A) {
   tess_cell<0>(lds[w], A, (int)s);
 }
 
-// Three waves per SIMD fit without spills (the two-level gather and the
-// extra shells keep many values live).
+// Four waves per SIMD, with some values of the two-level gather and the
+// extra shells spilled (at three, without spills, it is slower).
 // The listed cells: those of the dense buckets (listed by the sort) and
 // those the first pass met a dense bucket for.
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_tess_pass1_dense(
