@@ -606,3 +606,124 @@ def test_roundness_correction_profile(orc):
     slope = np.diff(mags[mid]) / np.diff(ds[mid])
     np.testing.assert_allclose(slope, chi * cs / (0.2 * zeta * R), rtol=1e-9)
     assert np.abs(np.diff(mags)).max() < 0.1 * chi * cs   # no jump anywhere
+
+
+# ------------------------------------------------------- timestep, floors
+
+def test_cfl_timestep_closed_form_bcc(orc):
+    # Sec. 4.2, timestep: dt_i = eta_CFL R_i / (c_s + |v - w|) with R_i the
+    # radius of the sphere of the cell's volume.  On the exact BCC lattice
+    # every cell is a truncated octahedron of volume a^3/2 whose centroid is
+    # its generator (no roundness correction), so with a uniform state and
+    # eta = 0.5 the mesh moves at half the fluid speed and
+    # dt = 0.3 (3 a^3 / (8 pi))^(1/3) / (sqrt(gamma P / rho) + |v| / 2).
+    m_side, gamma, rho, P = 4, 1.4, 2.0, 3.0
+    v = np.array([0.3, -0.2, 0.5])
+    a = 1.0 / m_side
+    pos = W.bcc_lattice(m_side)
+    p = orc.make_params((1, 1, 1), gamma, cfl=0.3, eta=0.5, chi=1.0, zeta=0.25)
+    m = orc.tessellate(pos, (1, 1, 1), method="brute")
+    prim = np.tile(np.concatenate([[rho], v, [P]]), (m.n, 1))
+    Q = orc.init_charges(m, p, prim)
+    U, w, dti, dt, hits = orc.cell_state(m, p, Q)
+    assert hits == 0
+    np.testing.assert_allclose(w, np.tile(0.5 * v, (m.n, 1)), rtol=1e-14, atol=1e-16)
+    R = (3.0 * (a ** 3 / 2) / (4.0 * math.pi)) ** (1.0 / 3.0)
+    expect = 0.3 * R / (math.sqrt(gamma * P / rho) + 0.5 * np.linalg.norm(v))
+    np.testing.assert_allclose(dti, expect, rtol=1e-14)
+    assert abs(dt - expect) <= 1e-14 * expect
+
+
+@pytest.mark.parametrize("x1,ramp", [(1.72, 1.0), (1.3 + 2 * 0.25 * (3 / (4 * math.pi)) ** (1 / 3), 0.5)],
+                         ids=["ramp_full", "ramp_half"])
+def test_cfl_timestep_with_roundness_correction(orc, x1, ramp):
+    # Two generators on a line in a 2 x 1 x 1 box: both cells are unit-volume
+    # slabs whose centroids sit d = |x1 - 1.3| / 2 off their generators.  With
+    # eta = 1 the mesh velocity is v plus the roundness correction of size
+    # chi c_s ramp(d) (Sec. 4.2), so |v - w| = chi c_s ramp and
+    # dt = 0.3 R / (c_s (1 + chi ramp)) with R = (3 / (4 pi))^(1/3).
+    gamma, chi, zeta, rho, P = 5 / 3, 0.7, 0.25, 1.5, 0.8
+    p = orc.make_params((2, 1, 1), gamma, cfl=0.3, eta=1.0, chi=chi, zeta=zeta)
+    pos = np.array([[0.3, 0.5, 0.5], [x1, 0.5, 0.5]])
+    m = orc.tessellate(pos, (2, 1, 1), method="brute")
+    np.testing.assert_allclose(m.V, [1.0, 1.0], rtol=1e-14)
+    v = np.array([0.2, 0.1, -0.05])
+    prim = np.array([[rho, *v, P], [rho, *v, P]])
+    Q = orc.init_charges(m, p, prim)
+    U, w, dti, dt, hits = orc.cell_state(m, p, Q)
+    R = (3.0 / (4.0 * math.pi)) ** (1.0 / 3.0)
+    cs = math.sqrt(gamma * P / rho)
+    d = abs(x1 - 1.3) / 2
+    got_ramp = np.linalg.norm(w - v, axis=1) / (chi * cs)
+    np.testing.assert_allclose(got_ramp, ramp, rtol=1e-9)
+    assert abs(d - zeta * R) < 1e-12 or ramp == 1.0
+    expect = 0.3 * R / (cs * (1.0 + chi * ramp))
+    np.testing.assert_allclose(dti, expect, rtol=1e-12)
+
+
+def _three_slabs(orc, rho0):
+    """Three generators on a line in a 3 x 1 x 1 box: three unit slab cells.
+    Cell 0 has density rho0 and cells 1 and 2 densities 1 and 0.5, so the
+    unlimited least-squares density gradient of cell 0 is (1 - 0.5) / 2 along
+    x: its extrapolation to the face toward cell 2's image (half a spacing
+    behind it) is rho0 - 0.125."""
+    gamma = 1.4
+    p = orc.make_params((3, 1, 1), gamma, theta=0.0, limit_mask=0, rho_floor=1e-3, p_floor=1e-6)
+    pos = np.array([[0.5, 0.5, 0.5], [1.5, 0.5, 0.5], [2.5, 0.5, 0.5]])
+    m = orc.tessellate(pos, (3, 1, 1), method="brute")
+    prim = np.array([[rho0, 0.05, 0, 0, 0.5], [1.0, 0.1, 0, 0, 1.0], [0.5, -0.1, 0, 0, 0.3]])
+    Q = orc.init_charges(m, p, prim)
+    U = Q / m.V[:, None]
+    G = orc.gradient(m, p, U, limit=False)
+    return p, m, U, G
+
+
+def test_face_floor_fallback_takes_the_cells_half_step_state(orc):
+    # Sec. 4.1 floors (reading R-floor): a side whose reconstructed state would
+    # need a floor takes its own cell's half-step state, bitwise; the other
+    # side of the same face keeps its reconstruction.  Face states are formed
+    # from the half-step states and gradients passed in.
+    p, m, U, G = _three_slabs(orc, rho0=0.05)
+    np.testing.assert_allclose(G[0, 0], [0.25, 0, 0], atol=1e-14)
+    w = np.zeros((m.n, 3))
+    UL, UR, nrm, wt = orc.face_states(m, p, U, G, w)
+    own = m.face_owner()
+    # cell 0's face toward the image of cell 2 (behind it, along -x)
+    back = np.nonzero((own == 0) & (m.j == 2) & (nrm[:, 0] < -0.5))[0]
+    front = np.nonzero((own == 0) & (m.j == 1) & (nrm[:, 0] > 0.5))[0]
+    assert len(back) == 1 and len(front) == 1
+    b, f = back[0], front[0]
+    # the extrapolated density 0.05 - 0.125 < 0 needs a floor: the side is U_0
+    assert np.array_equal(UL[b], U[0])
+    assert not np.array_equal(UL[b], UR[b])
+    # the other side is cell 2's own reconstruction toward that face
+    np.testing.assert_allclose(UR[b], U[2] + G[2] @ np.array([0.5, 0, 0]), rtol=1e-14)
+    # the front face needs no floor: reconstructed on both sides
+    np.testing.assert_allclose(UL[f], U[0] + G[0] @ np.array([0.5, 0, 0]), rtol=1e-14)
+    # seen from cell 2, the same face has cell 0 on its right: U_0 again
+    back2 = np.nonzero((own == 2) & (m.j == 0) & (nrm[:, 0] > 0.5))[0]
+    assert len(back2) == 1 and np.array_equal(UR[back2[0]], U[0])
+    # with a higher density no floor is needed and the side is reconstructed
+    p2, m2, U2, G2 = _three_slabs(orc, rho0=0.5)
+    UL2, UR2, _, _ = orc.face_states(m2, p2, U2, G2, w)
+    np.testing.assert_allclose(UL2[b], U2[0] + G2[0] @ np.array([-0.5, 0, 0]), rtol=1e-14)
+
+
+def test_step_applies_fallback_to_the_half_step_state(orc):
+    # The whole step equals its parts: cell state, gradient, predictor,
+    # half-step gradient, face fluxes from the half-step states (where a
+    # face side falls back, to the half-step state of its cell) and the
+    # update with floors; the face floor fires here.
+    p, m, U, G = _three_slabs(orc, rho0=0.05)
+    pos = m.pos.copy()
+    Q = U * m.V[:, None]
+    U0, w, dti, dt, h0 = orc.cell_state(m, p, Q)
+    G0 = orc.gradient(m, p, U0, limit=False)
+    Uh, h1 = orc.predict(m, p, U0, G0, w, dt)
+    assert not np.allclose(Uh, U0)
+    Gh = orc.gradient(m, p, Uh, limit=False)
+    dQ, h2 = orc.fluxes(m, p, Uh, Gh, w, dt)
+    assert h2 > 0
+    x1, Q1, w1, dt1, cnt = orc.step(pos, Q, p, method="brute")
+    assert dt1 == dt and list(cnt[:3]) == [h0, h1, h2]
+    np.testing.assert_allclose(Q1, Q + dQ, rtol=1e-13, atol=1e-15)
