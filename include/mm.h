@@ -203,7 +203,14 @@ mm_status mm_fluxes(mm_ctx *ctx, const void *U_half, const void *grad_half, cons
  * pos: dev [n][3] in/out; w: dev [n][3] out (the mesh velocities used);
  * Q: dev [n][5] in/out; info: host out (may be NULL).  Waits for the
  * stream once, at the end.  MM_EINVAL when p.mach_threshold > 0 (use
- * mm_step_entropy). */
+ * mm_step_entropy).
+ * On any error pos and Q keep the values they had before the call (the
+ * results are copied out only once the step is known to have succeeded),
+ * so the caller can retry from them: after MM_ECAPACITY for the face
+ * capacity (mm_last_error names it), with a context created with a larger
+ * face_capacity; after MM_ENONFINITE (a start-of-step state that is not
+ * finite, or a step that produced one), with a smaller dt_max or repaired
+ * charges.  w may hold partial results after an error. */
 mm_status mm_step(mm_ctx *ctx, int64_t n, double *pos, double *w, double *Q, double dt_max,
                   mm_step_info *info);
 
@@ -222,7 +229,8 @@ mm_status mm_init_entropy(mm_ctx *ctx, const double *prim, double *S);
  * entropy charges (caller order); mach: dev [n] float out, each cell's
  * largest face Mach number (1 without compression), or NULL.  With
  * mach_threshold = 0 the charges Q are exactly those of mm_step.
- * Errors as mm_step, and MM_EINVAL with half_step_mesh = 1. */
+ * Errors as mm_step (S, like pos and Q, keeps its values on an error), and
+ * MM_EINVAL with half_step_mesh = 1. */
 mm_status mm_step_entropy(mm_ctx *ctx, int64_t n, double *pos, double *w, double *Q, double *S, float *mach,
                           double dt_max, mm_step_info *info);
 
@@ -302,8 +310,11 @@ mm_status mm_batch_admit(mm_batch *b, const mm_params *p, int64_t n, const doubl
  * launches.  info (host, may be NULL) receives up to info_cap reports, one
  * per simulation stepped, *n_info (may be NULL) their number.  Waits for
  * the stream once.  Returns MM_OK when the launches ran; errors of single
- * simulations are in their reports.  MM_ECAPACITY if a batch-wide capacity
- * was exceeded (then every stepped simulation reports it). */
+ * simulations are in their reports.  A simulation whose step fails keeps
+ * its positions and charges as they were before the step (a newly admitted
+ * one holds its first charges) and is parked; the others advance exactly
+ * as they would without it.  MM_ECAPACITY if a batch-wide capacity was
+ * exceeded (then no simulation advances and every stepped one reports it). */
 mm_status mm_batch_step(mm_batch *b, mm_sim_info *info, int32_t info_cap, int32_t *n_info);
 
 /* Copies a simulation's state out, in its caller order: pos [n][3],

@@ -799,6 +799,10 @@ __device__ inline void cell_flux_sum(int64_t s, const unsigned long long* counts
   }
 }
 
+// The charges, positions and entropy charges after the step, in internal
+// order: Qn may be Qs (each thread reads its own row before writing it).
+// Nothing in the caller's arrays changes here; k_commit copies the results
+// out once every failure of the step is known.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__ segs,
                                                      const int32_t* __restrict__ sseg, int64_t n,
@@ -806,13 +810,13 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
                                                      const unsigned long long* __restrict__ soff,
                                                      const int32_t* __restrict__ csr, const R* __restrict__ phi,
                                                      const double* __restrict__ geo, const int32_t* __restrict__ perm,
-                                                     const double* __restrict__ Qs, double* __restrict__ Qc,
+                                                     const double* Qs, double* Qn,
                                                      const double* __restrict__ spos, const double* __restrict__ w,
-                                                     double* __restrict__ posc, double* __restrict__ wc,
+                                                     const double* __restrict__ posc, double* __restrict__ pn,
                                                      const SegStatus* dt_src, DevStatus* st, SegStatus* segst,
-                                                     bool drift_from_slots, const double* __restrict__ Ss,
+                                                     bool drift_from_slots, double* Ss,
                                                      const R* __restrict__ phiX, const float* __restrict__ machF,
-                                                     double* __restrict__ Sc, float* __restrict__ machc) {
+                                                     float* __restrict__ machs) {
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int seg = sseg[s];
@@ -866,31 +870,59 @@ __global__ __launch_bounds__(kThreads) void k_update(const SegDesc* __restrict__
       Snew = Q[0] * P / pow(u[0], gamma);
     }
   }
-  const int64_t c = perm[s];
   int bad = 0;
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
-    Qc[5 * c + q] = Q[q];
+    Qn[5 * s + q] = Q[q];
     if (!isfinite(Q[q])) bad = 1;
   }
   // Drift by the full step with periodic wrap, from the start-of-step
   // position (the caller's slot when the mesh is a half-step one).
   const double dt = seg_dt(segs, dt_src, seg, 0.0);
+  const int64_t c = drift_from_slots ? perm[s] : 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const double wa = w[3 * s + a];
-    double x = (drift_from_slots ? posc[3 * c + a] : spos[3 * s + a]) + wa * dt;
+    double x = (drift_from_slots ? posc[3 * c + a] : spos[3 * s + a]) + w[3 * s + a] * dt;
     if (x < 0.0) x += hp.L[a];
     if (x >= hp.L[a]) x -= hp.L[a];
-    posc[3 * c + a] = x;
-    wc[3 * c + a] = wa;
+    pn[3 * s + a] = x;
   }
   if (Ss) {
-    Sc[c] = Snew;
-    if (machc) machc[c] = mx;
+    Ss[s] = Snew;
+    if (machs) machs[s] = mx;
     if (!isfinite(Snew)) bad = 1;
   }
   if (bad) seg_fail(st, segst, seg, F_NONFINITE, (int)s);
+}
+
+// Copies the step's results of every segment whose step raised no failure
+// into the caller's slot-order arrays (charges, positions, mesh velocities,
+// and with the entropy column its charges and Mach numbers).  A segment
+// with a failure keeps its state as it was before the step, and so does
+// every segment when the shared face capacity overflowed.
+__global__ __launch_bounds__(kThreads) void k_commit(const int32_t* __restrict__ sseg, int64_t n,
+                                                     const int32_t* __restrict__ perm, const DevStatus* __restrict__ st,
+                                                     const SegStatus* __restrict__ segst,
+                                                     const double* __restrict__ Qn, const double* __restrict__ pn,
+                                                     const double* __restrict__ w, const double* __restrict__ Ss,
+                                                     const float* __restrict__ machs, double* __restrict__ Qc,
+                                                     double* __restrict__ posc, double* __restrict__ wc,
+                                                     double* __restrict__ Sc, float* __restrict__ machc) {
+  const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  if (segst[sseg[s]].flags || (st->flags & F_FACECAP)) return;
+  const int64_t c = perm[s];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) Qc[5 * c + q] = Qn[5 * s + q];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    posc[3 * c + a] = pn[3 * s + a];
+    wc[3 * c + a] = w[3 * s + a];
+  }
+  if (Sc) {
+    Sc[c] = Ss[s];
+    if (machc) machc[c] = machs[s];
+  }
 }
 
 template <typename R>
@@ -1016,8 +1048,11 @@ void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long*
                  hipStream_t st, const XCell<R>* recx, R* phiX, float* machF) {
   if (nf_host <= 0) return;
   // Enough resident blocks to fill the chip; each strides through its XCD's
-  // part of the (device-counted) face list.
-  const unsigned blocks = (unsigned)std::min<int64_t>(blocks_for(nf_host, kFluxThreads), 8192);
+  // part of the (device-counted) face list.  The kernel splits the list into
+  // kXcds ranges by blockIdx.x % kXcds, so the grid is a whole multiple of
+  // kXcds blocks (at least one per range) or a range would be left undone.
+  const int64_t want = std::min<int64_t>(blocks_for(nf_host, kFluxThreads), 8192);
+  const unsigned blocks = (unsigned)((want + kXcds - 1) / kXcds * kXcds);
   if (recx)
     hipLaunchKernelGGL((k_flux<R, true>), dim3(blocks), dim3(kFluxThreads), 0, st, segs, nf_host, nf_dev, faces,
                        rec, dt_src, dt_fixed, phi, segst, recx, phiX, machF);
@@ -1047,14 +1082,22 @@ void launch_entropy_gradient(const SegDesc* segs, const int32_t* sseg, int64_t n
 template <typename R>
 void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* counts,
                    const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo,
-                   const int32_t* perm, const double* Qs, double* Q_slots, const double* spos, const double* w,
-                   double* pos_slots, double* w_slots, const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst,
-                   hipStream_t st, bool drift_from_slots, const double* Ss, const R* phiX, const float* machF,
-                   double* S_slots, float* mach_slots) {
+                   const int32_t* perm, double* Qs, const double* spos, const double* w, const double* pos_slots,
+                   double* pn, const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st,
+                   bool drift_from_slots, double* Ss, const R* phiX, const float* machF, float* machs) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_update<R>, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, segs, sseg, n, counts, soff,
-                     csr, phi, geo, perm, Qs, Q_slots, spos, w, pos_slots, w_slots, dt_src, st_dev, segst,
-                     drift_from_slots, Ss, phiX, machF, S_slots, mach_slots);
+                     csr, phi, geo, perm, Qs, Qs, spos, w, pos_slots, pn, dt_src, st_dev, segst, drift_from_slots, Ss,
+                     phiX, machF, machs);
+}
+
+void launch_commit(const int32_t* sseg, int64_t n, const int32_t* perm, const DevStatus* st_dev,
+                   const SegStatus* segst, const double* Qn, const double* pn, const double* w, const double* Ss,
+                   const float* machs, double* Q_slots, double* pos_slots, double* w_slots, double* S_slots,
+                   float* mach_slots, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_commit, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, sseg, n, perm, st_dev, segst, Qn, pn, w,
+                     Ss, machs, Q_slots, pos_slots, w_slots, S_slots, mach_slots);
 }
 
 template <typename R>
@@ -1174,9 +1217,9 @@ void launch_copy_rows(const double* src, double* dst, int64_t n, int width, hipS
                                            const double*, const SegStatus*, R*, XCell<R>*, hipStream_t);          \
   template void launch_update<R>(const SegDesc*, const int32_t*, int64_t, const unsigned long long*,              \
                                  const unsigned long long*, const int32_t*, const R*, const double*,              \
-                                 const int32_t*, const double*, double*, const double*, const double*, double*,   \
-                                 double*, const SegStatus*, DevStatus*, SegStatus*, hipStream_t, bool,            \
-                                 const double*, const R*, const float*, double*, float*);                         \
+                                 const int32_t*, double*, const double*, const double*, const double*, double*,   \
+                                 const SegStatus*, DevStatus*, SegStatus*, hipStream_t, bool, double*, const R*,  \
+                                 const float*, float*);                                                           \
   template void launch_half_park<R>(const SegDesc*, const int32_t*, int64_t, const int32_t*, const R*,            \
                                     const double*, const SegStatus*, const double*, double*, R*, double*,         \
                                     hipStream_t);                                                                 \

@@ -51,6 +51,7 @@ struct Engine {
   // State in internal order.
   void *U = nullptr, *G = nullptr, *Uh = nullptr, *rec = nullptr, *phi = nullptr;   // rec: FluxCell<R>[n]
   double *w = nullptr, *Qs = nullptr;
+  double* pn = nullptr;   // positions after the drift, before they are committed
   // Half-step mesh (single simulations): positions r + w dt/2 and the
   // half-step states and mesh velocities parked in slot order while the
   // mesh is rebuilt.  Reserved only when init is asked for them.
@@ -61,6 +62,7 @@ struct Engine {
   // the gathered entropy charges.
   void *Xe = nullptr, *Xh = nullptr, *recx = nullptr, *phiX = nullptr;
   float* machF = nullptr;
+  float* machs = nullptr;   // per cell, internal order
   double* Ss = nullptr;
   // Segment table and status.
   SegDesc* segs = nullptr;

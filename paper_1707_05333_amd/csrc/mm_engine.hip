@@ -25,7 +25,7 @@ int64_t engine_bytes_per_cell(int precision) {
                            + 16 + 8 + 4                                // bucket count, offset, sub-table base; sub-offsets
                            + (int64_t)kMaxFaces * (sizeof(StageNbr) + sizeof(StageGeo))
                            + kListPerCell * (4 + (r == 4 ? sizeof(NbrEntry<float>) : sizeof(NbrEntry<double>)))
-                           + r * (5 + 15 + 5) + 8 * (3 + 5)            // U, G, Uh, w, Qs
+                           + r * (5 + 15 + 5) + 8 * (3 + 5 + 3)        // U, G, Uh, w, Qs, pn
                            + (r == 4 ? sizeof(FluxCell<float>) : sizeof(FluxCell<double>));
   const int64_t per_face = sizeof(Face) + 5 * r;                       // face, phi
   return per_cell + kFacesPerCell * per_face;
@@ -160,6 +160,7 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
   ok &= hipMalloc(&phi, std::max<size_t>(5 * F * rs, 1)) == hipSuccess;
   ok &= dalloc(&w, 3 * N) == hipSuccess;
   ok &= dalloc(&Qs, 5 * N) == hipSuccess;
+  ok &= dalloc(&pn, 3 * N) == hipSuccess;
   if (single) {
     ok &= dalloc(&pos_half, 3 * slot_cap) == hipSuccess;
     ok &= hipMalloc(&Uh_slots, std::max<size_t>(5 * slot_cap * rs, 1)) == hipSuccess;
@@ -168,6 +169,7 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
     ok &= hipMalloc(&recx, std::max<size_t>(N * 4 * rs, 1)) == hipSuccess;
     ok &= hipMalloc(&phiX, std::max<size_t>(F * rs, 1)) == hipSuccess;
     ok &= dalloc(&machF, F) == hipSuccess;
+    ok &= dalloc(&machs, N) == hipSuccess;
     ok &= dalloc(&Ss, N) == hipSuccess;
   }
   ok &= dalloc(&segs, segcap) == hipSuccess;
@@ -191,8 +193,8 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
 
 void Engine::release() {
   void* ptrs[] = {key, perm, sseg, deferred, dcells, spos, geo, rmax2, minv, bcount, boff, sbase, soffs, scan_tmp, counts, off, sw, soff,
-                  stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, pos_half, Uh_slots,
-                  Xe, Xh, recx, phiX, machF, Ss, segs, segst, st};
+                  stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, pn, pos_half, Uh_slots,
+                  Xe, Xh, recx, phiX, machF, machs, Ss, segs, segst, st};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   void* hptrs[] = {segs_host, segst_host, st_host};
@@ -280,9 +282,12 @@ void enqueue_hydro(Engine& E, double* pos, double* w_slots, double* Q, int64_t n
   launch_flux<R>(E.segs, E.fcap, nf_dev, E.faces, rec, E.segst, 0.0, phi, E.segst, E.stream, ent ? recx : nullptr,
                  (R*)E.phiX, E.machF);
   E.mark(7);
-  launch_update<R>(E.segs, E.sseg, n, E.counts, E.soff, E.csr, phi, E.geo, E.perm, E.Qs, Q, E.spos, E.w, pos, w_slots, E.segst,
-                   E.st, E.segst, E.stream, half, ent ? E.Ss : nullptr, (const R*)E.phiX, E.machF, S_slots,
-                   mach_slots);
+  launch_update<R>(E.segs, E.sseg, n, E.counts, E.soff, E.csr, phi, E.geo, E.perm, E.Qs, E.spos, E.w, pos, E.pn,
+                   E.segst, E.st, E.segst, E.stream, half, ent ? E.Ss : nullptr, (const R*)E.phiX, E.machF, E.machs);
+  // Results reach the caller's arrays only for segments without a failure,
+  // so a failed step leaves the state it started from.
+  launch_commit(E.sseg, n, E.perm, E.st, E.segst, E.Qs, E.pn, E.w, ent ? E.Ss : nullptr, E.machs, Q, pos, w_slots,
+                ent ? S_slots : nullptr, mach_slots, E.stream);
 }
 
 }  // namespace

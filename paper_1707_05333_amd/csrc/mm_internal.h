@@ -346,13 +346,25 @@ template <typename R>
 void launch_flux(const SegDesc* segs, int64_t nf_host, const unsigned long long* nf_dev, const Face* faces,
                  const FluxCell<R>* rec, const SegStatus* dt_src, double dt_fixed, R* phi, SegStatus* segst,
                  hipStream_t st, const XCell<R>* recx = nullptr, R* phiX = nullptr, float* machF = nullptr);
+// Update of the charges with the floors after the step, and the drift
+// (internal order): Qs is overwritten with the new charges, pn receives the
+// new positions, Ss (entropy column, may be NULL) the new entropy charges
+// and machs each cell's largest face Mach number.  The caller's arrays are
+// untouched; launch_commit copies the results out.
 template <typename R>
 void launch_update(const SegDesc* segs, const int32_t* sseg, int64_t n, const unsigned long long* counts,
-                   const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo, const int32_t* perm, const double* Qs,
-                   double* Q_slots, const double* spos, const double* w, double* pos_slots, double* w_slots,
-                   const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st,
-                   bool drift_from_slots = false, const double* Ss = nullptr, const R* phiX = nullptr,
-                   const float* machF = nullptr, double* S_slots = nullptr, float* mach_slots = nullptr);
+                   const unsigned long long* soff, const int32_t* csr, const R* phi, const double* geo,
+                   const int32_t* perm, double* Qs, const double* spos, const double* w, const double* pos_slots,
+                   double* pn, const SegStatus* dt_src, DevStatus* st_dev, SegStatus* segst, hipStream_t st,
+                   bool drift_from_slots = false, double* Ss = nullptr, const R* phiX = nullptr,
+                   const float* machF = nullptr, float* machs = nullptr);
+// Copies the results of launch_update into the slot-order arrays of every
+// segment whose status holds no failure; a failed segment keeps its state
+// (all of them do after an overflow of the shared face capacity).
+void launch_commit(const int32_t* sseg, int64_t n, const int32_t* perm, const DevStatus* st_dev,
+                   const SegStatus* segst, const double* Qn, const double* pn, const double* w, const double* Ss,
+                   const float* machs, double* Q_slots, double* pos_slots, double* w_slots, double* S_slots,
+                   float* mach_slots, hipStream_t st);
 // Half-step mesh: U_half and w of internal cell s go to slot perm[s], and
 // pos_half[slot] = wrap(pos[slot] + w dt/2) (single segment, slots = cells).
 template <typename R>

@@ -53,12 +53,48 @@ def compare_mesh(mm, om, rtol=1e-10):
     return ex
 
 
-def scaled_err(a, b):
-    """Max |a - b| per column divided by the column's max |b| (or 1)."""
-    a = np.asarray(a, dtype=np.float64).reshape(a.shape[0], -1)
-    b = np.asarray(b, dtype=np.float64).reshape(b.shape[0], -1)
-    scale = np.maximum(np.abs(b).max(axis=0), 1e-300)
-    return float((np.abs(a - b).max(axis=0) / scale).max())
+def state_scale(Q, gamma):
+    """Per-cell rounding scale of each column of charges Q [n][5] (or of
+    densities U, the same formula): |m| for the mass, m (|v| + c_s) for the
+    momenta and |E| for the energy, c_s^2 = gamma (gamma - 1)(E - |p|^2/2m)/m.
+    A cell at rest in a uniform region has zero momentum up to the rounding
+    of its face sums, which are of the order m c_s."""
+    Q = np.asarray(Q, dtype=np.float64)
+    m = np.abs(Q[:, 0])
+    p2 = (Q[:, 1:4] ** 2).sum(axis=1)
+    e_int = np.maximum(Q[:, 4] - 0.5 * p2 / np.where(m > 0, m, 1.0), 0.0)
+    cs = np.sqrt(gamma * (gamma - 1.0) * e_int / np.where(m > 0, m, 1.0))
+    v = np.sqrt(p2) / np.where(m > 0, m, 1.0)
+    out = np.empty_like(Q)
+    out[:, 0] = m
+    out[:, 1:4] = (m * (v + cs))[:, None]
+    out[:, 4] = np.abs(Q[:, 4])
+    return out
+
+
+def neighbour_max(om, S):
+    """Elementwise max of S [n][k] over each cell and its neighbours in the
+    oracle mesh om."""
+    S = np.asarray(S, dtype=np.float64).reshape(om.n, -1)
+    out = S.copy()
+    np.maximum.at(out, om.face_owner(), S[om.j])
+    return out
+
+
+def local_err(a, b, om, phys=None):
+    """Largest |a - b| over all elements, each divided by its own scale:
+    the largest |b| of that column over the cell and its neighbours in the
+    oracle mesh om, raised to the cell's physical rounding scale phys
+    [n][k] (same columns) where one is given.  Unlike a per-column maximum,
+    a low-density cell's error is measured against its own neighbourhood."""
+    n = om.n
+    a = np.asarray(a, dtype=np.float64).reshape(n, -1)
+    b = np.asarray(b, dtype=np.float64).reshape(n, -1)
+    S = np.abs(b)
+    if phys is not None:
+        S = np.maximum(S, np.asarray(phys, dtype=np.float64).reshape(n, -1))
+    S = np.maximum(neighbour_max(om, S), 1e-300)
+    return float((np.abs(a - b) / S).max())
 
 
 def sampled_cells_match(orc, wl, ex, n_sample=3000, seed=0):

@@ -3,11 +3,13 @@ background a million times thinner: cell sizes differ ~20x in length):
 
 * 20K points: the whole tessellation against the oracle (topology bit-exact,
   geometry within 1e-10 of the cell scale), two FP64 steps against the
-  oracle element by element (states within 1e-10 of each column's scale
-  and every cell's mass within 1e-10 of the largest start-of-step mass
-  among it and its neighbours, the scale of the mass its faces move; the floor and
-  fall-back counters equal), and three mixed steps: finite, mass conserved
-  to rounding, density within 1e-4 (L1, mass-weighted) of the oracle.
+  oracle element by element (every charge within 1e-10 of its own scale:
+  the largest value of its column over the cell and its neighbours, and at
+  least m, m(|v| + c_s), |E| of those cells, so a background cell a million
+  times thinner than a star's core is measured against its own
+  neighbourhood; the floor and fall-back counters equal), and three mixed
+  steps: finite, mass conserved to rounding, density within 1e-4 (L1,
+  mass-weighted) of the oracle.
 * 8,388,608 points (the workload's full size, in the benchmark's launch
   configuration): 3000 sampled cells against the oracle, the volumes tile
   the box, and two mixed steps conserve mass to rounding.
@@ -16,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import compare_mesh, dev, host, sampled_cells_match, scaled_err
+from gpu_common import compare_mesh, dev, host, local_err, sampled_cells_match, state_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -51,15 +53,9 @@ def _oracle_run(orc, wl, nsteps):
     pos, Q = wl.pos.copy(), Q0.copy()
     out = []
     for _ in range(nsteps):
-        # the largest mass among each cell and its neighbours at the start
-        # of the step: a face moves a share of its upwind cell's mass, so a
-        # cell's new mass carries rounding on that scale
-        om = orc.tessellate(pos, wl.box)
-        own = om.face_owner()
-        mscale = Q[:, 0].copy()
-        np.maximum.at(mscale, own, Q[om.j, 0])
+        om = orc.tessellate(pos, wl.box)   # the step's mesh: each cell's neighbourhood
         pos, Q, w, dt, cnt = orc.step(pos, Q, p)
-        out.append((pos.copy(), Q.copy(), dt, list(cnt), mscale))
+        out.append((pos.copy(), Q.copy(), dt, list(cnt), om))
     return Q0, out
 
 
@@ -72,14 +68,14 @@ def test_c5_small_fp64_steps_match_oracle(orc, c5_small):
     mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, precision="fp64", **wl.params))
     pos, Q = dev(wl.pos), dev(Q0)
     w = torch.empty_like(pos)
-    for k, (po, Qo, dto, cnt, mscale) in enumerate(ref):
+    for k, (po, Qo, dto, cnt, om) in enumerate(ref):
         info = mm.step(pos, w, Q)
         assert abs(info["dt"] - dto) <= TOL * dto, f"step {k}"
         assert info["floor_hits"] == cnt, f"step {k}"
         assert cnt[2] > 0   # faces at the stars' edges fell back to first order
-        Qg = host(Q)
-        assert scaled_err(Qg, Qo) < TOL, f"step {k}"
-        assert np.all(np.abs(Qg[:, 0] - Qo[:, 0]) <= TOL * mscale), f"step {k}"
+        err = local_err(host(Q), Qo, om, state_scale(Qo, wl.params["gamma"]))
+        print(f"[step {k}] max element error {err:.3e}", flush=True)
+        assert err < TOL, f"step {k}"
         assert np.abs(host(pos) - po).max() < TOL, f"step {k}"
 
 

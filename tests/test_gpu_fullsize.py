@@ -1,14 +1,15 @@
 """GPU checks at the workloads' full sizes, in the launch configuration the
 benchmark uses: sampled cells against the oracle (which builds just those
-cells), properties that hold at any size, the Sod tube against the exact
-Riemann solution, and the mixed-precision error against FP64."""
+cells), whole FP64 steps against the oracle element by element, properties
+that hold at any size, the Sod tube against the exact Riemann solution, and
+the mixed-precision error against the FP64 oracle."""
 import math
 
 import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import dev, host, sampled_cells_match as _sampled_cells_match
+from gpu_common import dev, host, local_err, sampled_cells_match as _sampled_cells_match, state_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +30,41 @@ def test_full_size_tessellation_sampled(orc, name):
     assert abs(V.sum() / np.prod(wl.box) - 1) < 1e-12
     assert info["max_faces_cell"] <= 64
     _sampled_cells_match(orc, wl, ex)
+
+
+@pytest.mark.parametrize("name,steps", [("sod_256x64x64", 2), ("blast_128^3", 1)])
+def test_full_size_fp64_steps_match_oracle(orc, name, steps):
+    # Whole FP64 steps of the full workloads (1,048,576 and 2,097,152 cells)
+    # against the oracle's steps: every charge within 1e-10 of its own
+    # scale (the largest value of its column over the cell and its
+    # neighbours, at least m, m(|v| + c_s), |E|), positions within 1e-10,
+    # the timestep and the floor counters equal.
+    import paper_1707_05333_amd as M
+    import torch
+    wl = W.c2_sod() if name.startswith("sod") else W.c3_point_blast()
+    _case("full-size fp64 steps vs oracle", name=name, n=wl.n, steps=steps)
+    p = orc.make_params(wl.box, **wl.params)
+    om = orc.tessellate(wl.pos, wl.box)
+    Q0 = orc.init_charges(om, p, wl.prim)
+    if wl.energy_cells is not None:
+        Q0[wl.energy_cells, 4] += wl.energy_amount
+    del om
+    mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, precision="fp64", **wl.params))
+    pos_g, Q_g = dev(wl.pos), dev(Q0)
+    w_g = torch.empty_like(pos_g)
+    pos_o, Q_o = wl.pos.copy(), Q0
+    for k in range(steps):
+        info = mm.step(pos_g, w_g, Q_g)
+        start = pos_o
+        pos_o, Q_o, w_o, dt_o, cnt = orc.step(pos_o, Q_o, p)
+        print(f"[step {k}] dt {info['dt']:.6e} oracle {dt_o:.6e}", flush=True)
+        assert abs(info["dt"] - dt_o) <= 1e-10 * dt_o
+        assert info["floor_hits"] == list(cnt)
+    om = orc.tessellate(start, wl.box)
+    err = local_err(host(Q_g), Q_o, om, state_scale(Q_o, wl.params["gamma"]))
+    print(f"[parity] max element error {err:.3e}", flush=True)
+    assert err < 1e-10
+    assert np.abs(host(pos_g) - pos_o).max() < 1e-10
 
 
 def test_full_size_closed_cells_and_conservation():
@@ -104,30 +140,41 @@ def test_sod_full_resolution_against_exact_solution(orc):
     assert np.median(rho[behind]) > 0.24 and np.median(rho[ahead]) < 0.14
 
 
-def test_mixed_precision_blast_error():
-    # FP32 gradients, predictor and fluxes with FP64 geometry and sums
-    # against the FP64 path on the point blast (64^3, 40 steps): relative
-    # L1 density error <= 1e-4; mass is conserved by both.
+def test_mixed_precision_blast_error(orc):
+    # FP32 gradients, predictor and fluxes with FP64 geometry and sums on the
+    # point blast (64^3, 40 steps), against the FP64 oracle's run of the
+    # same steps: relative L1 density error <= 1e-4, and the mass, momentum
+    # and energy drifts of both stay at rounding.  The FP64 GPU path is run
+    # beside it and must sit on the oracle.
     import paper_1707_05333_amd as M
     import torch
     wl = W.c3_point_blast(n_side=64)
-    _case("mixed vs fp64", n=wl.n)
+    nsteps = 40
+    _case("mixed vs fp64 oracle", n=wl.n, steps=nsteps)
+    p = orc.make_params(wl.box, **wl.params)
+    om = orc.tessellate(wl.pos, wl.box)
+    Q0 = orc.init_charges(om, p, wl.prim)
+    Q0[wl.energy_cells, 4] += wl.energy_amount
+    pos_o, Q_o = wl.pos.copy(), Q0.copy()
+    for _ in range(nsteps):
+        pos_o, Q_o, _, _, cnt = orc.step(pos_o, Q_o, p)
+    r_o = Q_o[:, 0] / orc.tessellate(pos_o, wl.box).V
     out = {}
     for prec in ("fp64", "mixed"):
         mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, precision=prec, **wl.params))
-        pos = dev(wl.pos)
-        mm.tessellate(pos)
-        Q = mm.init_charges(dev(wl.prim))
-        Q[torch.from_numpy(wl.energy_cells).cuda(), 4] += wl.energy_amount
-        M0 = float(Q[:, 0].sum())
+        pos, Q = dev(wl.pos), dev(Q0)
         w = torch.empty_like(pos)
-        for _ in range(40):
+        for _ in range(nsteps):
             mm.step(pos, w, Q)
         mm.tessellate(pos)
-        V = mm.mesh_export().V
-        out[prec] = (host(Q[:, 0] / V), abs(float(Q[:, 0].sum()) - M0) / M0)
-    r64, r32 = out["fp64"][0], out["mixed"][0]
-    l1 = np.abs(r32 - r64).sum() / np.abs(r64).sum()
-    print(f"[mixed] L1(rho) = {l1:.3e}, mass drift fp64 {out['fp64'][1]:.2e} mixed {out['mixed'][1]:.2e}")
-    assert l1 < 1e-4
-    assert out["fp64"][1] < 1e-13 and out["mixed"][1] < 1e-12
+        V = host(mm.mesh_export().V)
+        Qh = host(Q)
+        drift = np.abs(Qh.sum(axis=0) - Q0.sum(axis=0)) / np.abs(Qh).sum(axis=0)
+        out[prec] = (Qh[:, 0] / V, drift)
+    l1 = {k: float(np.abs(v[0] - r_o).sum() / np.abs(r_o).sum()) for k, v in out.items()}
+    print(f"[mixed] L1(rho) vs oracle: mixed {l1['mixed']:.3e}, fp64 {l1['fp64']:.3e}; "
+          f"drift (m, p, E) mixed {out['mixed'][1]}, fp64 {out['fp64'][1]}", flush=True)
+    assert l1["fp64"] < 1e-10
+    assert l1["mixed"] < 1e-4
+    for prec in ("fp64", "mixed"):
+        assert out[prec][1][0] < 1e-12 and out[prec][1][4] < 1e-12
