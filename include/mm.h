@@ -234,7 +234,32 @@ mm_status mm_init_entropy(mm_ctx *ctx, const double *prim, double *S);
 mm_status mm_step_entropy(mm_ctx *ctx, int64_t n, double *pos, double *w, double *Q, double *S, float *mach,
                           double dt_max, mm_step_info *info);
 
-/* Message for the last error on this context (static storage of the context). */
+/* Largest n of mm_step_static. */
+#define MM_STATIC_MAX_POINTS 8192
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): mm_step
+ * without a context.  It runs the same kernels as mm_step with the context
+ * of parameters p (a one-simulation context of MM_STATIC_MAX_POINTS points
+ * and 12 faces per point) carved from a fixed device array of 64 MiB that
+ * the library holds on each GPU it runs on until the process ends; the call
+ * allocates no device or pinned memory and creates no events.  pos, w, Q,
+ * dt_max and info as for mm_step (caller-owned device arrays, caller order;
+ * on an error pos and Q keep their values); hip_stream is a hipStream_t
+ * (NULL: the null stream) on the current device.  Every call on a device
+ * shares that device's array and overwrites what the last call left there,
+ * so calls that overlap on one device (from several host threads, or on
+ * several streams without ordering between them) race and must be
+ * serialised by the caller.  Waits for the stream once, at its end.
+ * Errors: MM_EINVAL (n outside [1, MM_STATIC_MAX_POINTS], bad parameters,
+ * half_step_mesh = 1 or mach_threshold > 0), then those of mm_step; the
+ * message is mm_last_error(NULL) on the calling thread. */
+mm_status mm_step_static(const mm_params *p, int64_t n, double *pos, double *w, double *Q, double dt_max,
+                         mm_step_info *info, void *hip_stream);
+
+/* Message for the last error on this context (static storage of the context);
+ * with ctx NULL, of the last failed mm_create or mm_step_static on the
+ * calling thread. */
 const char *mm_last_error(const mm_ctx *ctx);
 
 /* Library version string. */

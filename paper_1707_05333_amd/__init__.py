@@ -160,6 +160,7 @@ SIGNATURES = {
     "mm_predict": (_i32, [_vp, _vp, _vp, _vp, _d, _vp]),
     "mm_fluxes": (_i32, [_vp, _vp, _vp, _vp, _d, _vp]),
     "mm_step": (_i32, [_vp, _i64, _vp, _vp, _vp, _d, ctypes.POINTER(StepInfo)]),
+    "mm_step_static": (_i32, [ctypes.POINTER(Params), _i64, _vp, _vp, _vp, _d, ctypes.POINTER(StepInfo), _vp]),
     "mm_last_error": (ctypes.c_char_p, [_vp]),
     "mm_version": (ctypes.c_char_p, []),
     "mm_set_stage_timing": (_i32, [_vp, _i32]),
@@ -515,6 +516,26 @@ class Batch:
         results = [dict(admitted=res[k].admitted, finished=res[k].finished, status=res[k].status,
                         steps=res[k].steps, t=res[k].t) for k in range(n_req)]
         return results, stats.as_dict()
+
+
+STATIC_MAX_POINTS = 8192   # MM_STATIC_MAX_POINTS of include/mm.h
+
+
+def step_static(params: Params, pos, w, Q, dt_max=math.inf, stream=None) -> dict:
+    """mm_step_static: one whole step in place on pos, w (output) and Q with
+    no context, for callers that cannot allocate device memory (n at most
+    STATIC_MAX_POINTS; calls on one device must not overlap)."""
+    import torch
+    L = load_library()
+    n = int(pos.shape[0])
+    s = stream if stream is not None else torch.cuda.current_stream()
+    info = StepInfo()
+    rc = L.mm_step_static(ctypes.byref(params), n, _ptr(pos, torch.float64, (n, 3), "pos"),
+                          _ptr(w, torch.float64, (n, 3), "w"), _ptr(Q, torch.float64, (n, 5), "Q"),
+                          float(dt_max), ctypes.byref(info), ctypes.c_void_p(s.cuda_stream))
+    if rc != 0:
+        raise MMError(rc, L.mm_last_error(None).decode())
+    return info.as_dict()
 
 
 def version() -> str:

@@ -93,7 +93,17 @@ struct Engine {
   // single: also reserve the half-step mesh and entropy buffers.
   mm_status init(int precision, int64_t ncap, int64_t slot_cap, int64_t fcap, int segcap, hipStream_t stream,
                  bool single = false);
+  // The same buffers (one segment, no half-step mesh or entropy column)
+  // carved from the given device arena, with the given host memory as the
+  // status mirrors: nothing is allocated, and no events exist (no stage
+  // timing).  MM_ECAPACITY when they do not fit.
+  mm_status init_arena(int precision, int64_t ncap, int64_t fcap, void* arena, size_t bytes, SegDesc* seg_host,
+                       SegStatus* seg_status_host, DevStatus* status_host, hipStream_t stream);
+  // Bytes init_arena needs (its alignment included).
+  static size_t arena_bytes(int precision, int64_t ncap, int64_t fcap);
+  void set_capacity(int precision, int64_t ncap, int64_t slot_cap, int64_t fcap, int segcap);
   void release();
+  bool arena_mode = false;
 
   // Host staging of the segment table, safe to write once returned; then
   // upload(nseg) copies the first nseg descriptors (stream-ordered).
@@ -125,7 +135,7 @@ struct Engine {
     return code;
   }
   void mark(int k) {
-    if (timing) (void)hipEventRecord(ev[k], stream);
+    if (timing && !arena_mode) (void)hipEventRecord(ev[k], stream);
   }
 };
 

@@ -11,9 +11,36 @@ namespace mm {
 
 namespace {
 
-template <typename T>
-hipError_t dalloc(T** p, size_t count) {
-  return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+// Hands out the engine's device buffers: from hipMalloc, or carved from one
+// arena by a bump pointer (256-byte aligned, no allocation), or only counted
+// (no base: the bytes an arena must hold).
+struct Reserver {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool arena = false, ok = true;
+  template <typename T>
+  void operator()(T** p, size_t count) {
+    bytes((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+  }
+  void bytes(void** p, size_t b) {
+    b = std::max<size_t>(b, 1);
+    if (!arena) {
+      ok &= hipMalloc(p, b) == hipSuccess;
+      return;
+    }
+    const size_t at = (used + 255) & ~size_t(255);
+    used = at + b;
+    if (!base || used > cap) {
+      *p = nullptr;
+      ok &= base == nullptr;   // counting only
+      return;
+    }
+    *p = base + at;
+  }
+};
+
+__global__ void k_put_segment(SegDesc d, SegDesc* dst) {
+  if (threadIdx.x == 0) *dst = d;
 }
 
 }  // namespace
@@ -114,8 +141,63 @@ double dt_from_bits(unsigned long long bits) {
   return d;
 }
 
-mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, int seg_cap, hipStream_t s,
-                       bool single) {
+// Every device buffer of the engine, in one list for both ways of
+// reserving them.
+template <typename Res>
+void reserve_buffers(Engine& E, Res& R, bool single) {
+  const int64_t N = E.ncap, F = E.fcap, slot_cap = E.slot_cap, nbcap = E.nbcap, sell_cap = E.sell_cap;
+  const int precision = E.precision, segcap = E.segcap;
+  const size_t rs = precision == MM_MIXED ? sizeof(float) : sizeof(double);
+  R(&E.key, slot_cap);
+  R(&E.perm, N);
+  R(&E.sseg, N);
+  R(&E.deferred, N);
+  R(&E.dcells, N);
+  R(&E.spos, 3 * N);
+  R(&E.geo, 4 * N);
+  R(&E.rmax2, N);
+  R(&E.minv, 6 * N);
+  R(&E.bcount, nbcap);
+  R(&E.boff, nbcap + 1);
+  R(&E.sbase, nbcap + 1);
+  R(&E.soffs, N);
+  R(&E.scan_tmp, scan_tmp_elems(std::max(N, nbcap)));
+  R(&E.counts, N);
+  R(&E.off, N + 1);
+  R(&E.sw, (N + 63) / 64 + 1);
+  R(&E.soff, (N + 63) / 64 + 2);
+  R(&E.stage_nb, (size_t)N * kMaxFaces);
+  R(&E.stage_geo, (size_t)N * kMaxFaces);
+  R(&E.faces, F);
+  R(&E.csr, sell_cap);
+  R.bytes(&E.nbr, sell_cap * (precision == MM_MIXED ? sizeof(NbrEntry<float>)
+                                                                            : sizeof(NbrEntry<double>)));
+  R.bytes(&E.U, 5 * N * rs);
+  R.bytes(&E.G, 15 * N * rs);
+  R.bytes(&E.Uh, 5 * N * rs);
+  R.bytes(&E.rec, N * (precision == MM_MIXED ? sizeof(FluxCell<float>)
+                                                                       : sizeof(FluxCell<double>)));
+  R.bytes(&E.phi, 5 * F * rs);
+  R(&E.w, 3 * N);
+  R(&E.Qs, 5 * N);
+  R(&E.pn, 3 * N);
+  if (single) {
+    R(&E.pos_half, 3 * slot_cap);
+    R.bytes(&E.Uh_slots, 5 * slot_cap * rs);
+    R.bytes(&E.Xe, N * rs);
+    R.bytes(&E.Xh, N * rs);
+    R.bytes(&E.recx, N * 4 * rs);
+    R.bytes(&E.phiX, F * rs);
+    R(&E.machF, F);
+    R(&E.machs, N);
+    R(&E.Ss, N);
+  }
+  R(&E.segs, segcap);
+  R(&E.segst, segcap);
+  R(&E.st, 1);
+}
+
+void Engine::set_capacity(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, int seg_cap) {
   precision = prec;
   ncap = n_cap;
   slot_cap = s_cap;
@@ -123,58 +205,44 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
   segcap = seg_cap;
   nbcap = ncap + 8ll * segcap;
   sell_cap = kListPerCell * ((ncap + 63) / 64) * 64;   // whole slices of 64 cells
+}
+
+size_t Engine::arena_bytes(int prec, int64_t n_cap, int64_t f_cap) {
+  Engine E;
+  E.set_capacity(prec, n_cap, n_cap, f_cap, 1);
+  Reserver R;
+  R.arena = true;   // no base: counts the bytes
+  reserve_buffers(E, R, false);
+  return R.used;
+}
+
+mm_status Engine::init_arena(int prec, int64_t n_cap, int64_t f_cap, void* arena, size_t bytes, SegDesc* seg_host,
+                             SegStatus* seg_status_host, DevStatus* status_host, hipStream_t s) {
+  *this = Engine();
+  set_capacity(prec, n_cap, n_cap, f_cap, 1);
+  stream = s;
+  arena_mode = true;
+  if (hipGetDevice(&device) != hipSuccess) return fail(MM_EHIP, "hipGetDevice failed");
+  Reserver R;
+  R.arena = true;
+  R.base = (char*)arena;
+  R.cap = bytes;
+  reserve_buffers(*this, R, false);
+  if (!R.ok || !arena) return fail(MM_ECAPACITY, "the buffers do not fit the arena");
+  segs_host = seg_host;
+  segst_host = seg_status_host;
+  st_host = status_host;
+  return MM_OK;
+}
+
+mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, int seg_cap, hipStream_t s,
+                       bool single) {
+  set_capacity(prec, n_cap, s_cap, f_cap, seg_cap);
   stream = s;
   if (hipGetDevice(&device) != hipSuccess) return fail(MM_EHIP, "hipGetDevice failed");
-  const int64_t N = ncap, F = fcap;
-  const size_t rs = precision == MM_MIXED ? sizeof(float) : sizeof(double);
-  bool ok = true;
-  ok &= dalloc(&key, slot_cap) == hipSuccess;
-  ok &= dalloc(&perm, N) == hipSuccess;
-  ok &= dalloc(&sseg, N) == hipSuccess;
-  ok &= dalloc(&deferred, N) == hipSuccess;
-  ok &= dalloc(&dcells, N) == hipSuccess;
-  ok &= dalloc(&spos, 3 * N) == hipSuccess;
-  ok &= dalloc(&geo, 4 * N) == hipSuccess;
-  ok &= dalloc(&rmax2, N) == hipSuccess;
-  ok &= dalloc(&minv, 6 * N) == hipSuccess;
-  ok &= dalloc(&bcount, nbcap) == hipSuccess;
-  ok &= dalloc(&boff, nbcap + 1) == hipSuccess;
-  ok &= dalloc(&sbase, nbcap + 1) == hipSuccess;
-  ok &= dalloc(&soffs, N) == hipSuccess;
-  ok &= dalloc(&scan_tmp, scan_tmp_elems(std::max(N, nbcap))) == hipSuccess;
-  ok &= dalloc(&counts, N) == hipSuccess;
-  ok &= dalloc(&off, N + 1) == hipSuccess;
-  ok &= dalloc(&sw, (N + 63) / 64 + 1) == hipSuccess;
-  ok &= dalloc(&soff, (N + 63) / 64 + 2) == hipSuccess;
-  ok &= dalloc(&stage_nb, (size_t)N * kMaxFaces) == hipSuccess;
-  ok &= dalloc(&stage_geo, (size_t)N * kMaxFaces) == hipSuccess;
-  ok &= dalloc(&faces, F) == hipSuccess;
-  ok &= dalloc(&csr, sell_cap) == hipSuccess;
-  ok &= hipMalloc(&nbr, std::max<size_t>(sell_cap * (precision == MM_MIXED ? sizeof(NbrEntry<float>)
-                                                                            : sizeof(NbrEntry<double>)), 1)) == hipSuccess;
-  ok &= hipMalloc(&U, std::max<size_t>(5 * N * rs, 1)) == hipSuccess;
-  ok &= hipMalloc(&G, std::max<size_t>(15 * N * rs, 1)) == hipSuccess;
-  ok &= hipMalloc(&Uh, std::max<size_t>(5 * N * rs, 1)) == hipSuccess;
-  ok &= hipMalloc(&rec, std::max<size_t>(N * (precision == MM_MIXED ? sizeof(FluxCell<float>)
-                                                                       : sizeof(FluxCell<double>)), 1)) == hipSuccess;
-  ok &= hipMalloc(&phi, std::max<size_t>(5 * F * rs, 1)) == hipSuccess;
-  ok &= dalloc(&w, 3 * N) == hipSuccess;
-  ok &= dalloc(&Qs, 5 * N) == hipSuccess;
-  ok &= dalloc(&pn, 3 * N) == hipSuccess;
-  if (single) {
-    ok &= dalloc(&pos_half, 3 * slot_cap) == hipSuccess;
-    ok &= hipMalloc(&Uh_slots, std::max<size_t>(5 * slot_cap * rs, 1)) == hipSuccess;
-    ok &= hipMalloc(&Xe, std::max<size_t>(N * rs, 1)) == hipSuccess;
-    ok &= hipMalloc(&Xh, std::max<size_t>(N * rs, 1)) == hipSuccess;
-    ok &= hipMalloc(&recx, std::max<size_t>(N * 4 * rs, 1)) == hipSuccess;
-    ok &= hipMalloc(&phiX, std::max<size_t>(F * rs, 1)) == hipSuccess;
-    ok &= dalloc(&machF, F) == hipSuccess;
-    ok &= dalloc(&machs, N) == hipSuccess;
-    ok &= dalloc(&Ss, N) == hipSuccess;
-  }
-  ok &= dalloc(&segs, segcap) == hipSuccess;
-  ok &= dalloc(&segst, segcap) == hipSuccess;
-  ok &= dalloc(&st, 1) == hipSuccess;
+  Reserver R;
+  reserve_buffers(*this, R, single);
+  bool ok = R.ok;
   ok &= hipHostMalloc((void**)&segs_host, sizeof(SegDesc) * segcap, hipHostMallocDefault) == hipSuccess;
   ok &= hipHostMalloc((void**)&segst_host, sizeof(SegStatus) * segcap, hipHostMallocDefault) == hipSuccess;
   ok &= hipHostMalloc((void**)&st_host, sizeof(DevStatus), hipHostMallocDefault) == hipSuccess;
@@ -192,6 +260,10 @@ mm_status Engine::init(int prec, int64_t n_cap, int64_t s_cap, int64_t f_cap, in
 }
 
 void Engine::release() {
+  if (arena_mode) {   // nothing of its own: the arena and the host mirrors belong to the caller
+    *this = Engine();
+    return;
+  }
   void* ptrs[] = {key, perm, sseg, deferred, dcells, spos, geo, rmax2, minv, bcount, boff, sbase, soffs, scan_tmp, counts, off, sw, soff,
                   stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, pn, pos_half, Uh_slots,
                   Xe, Xh, recx, phiX, machF, machs, Ss, segs, segst, st};
@@ -210,6 +282,14 @@ mm_status Engine::upload(int k) {
   if (k < 0 || k > segcap) return fail(MM_EINVAL, "segment count beyond capacity");
   nseg = k;
   if (k == 0) return MM_OK;
+  if (arena_mode) {
+    // Each descriptor travels as a kernel argument (copied at the launch):
+    // no staging memory, and the host copy is free again at once.
+    for (int q = 0; q < k; ++q) hipLaunchKernelGGL(k_put_segment, dim3(1), dim3(64), 0, stream, segs_host[q], segs + q);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MM_EHIP, std::string("segment upload: ") + hipGetErrorString(e));
+    return MM_OK;
+  }
   const hipError_t e = hipMemcpyAsync(segs, segs_host, sizeof(SegDesc) * k, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return fail(MM_EHIP, std::string("segment upload: ") + hipGetErrorString(e));
   (void)hipEventRecord(upload_done, stream);
@@ -218,7 +298,7 @@ mm_status Engine::upload(int k) {
 
 SegDesc* Engine::staging() {
   // The staging buffer may be rewritten only once the last upload has run.
-  (void)hipEventSynchronize(upload_done);
+  if (!arena_mode) (void)hipEventSynchronize(upload_done);
   return segs_host;
 }
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -368,6 +369,80 @@ mm_status mm_init_entropy(mm_ctx* c, const double* prim, double* S) {
   launch_init_entropy(c->E.segs, c->E.sseg, c->E.n, prim, c->E.perm, c->E.geo, S, c->E.stream);
   HIPCHECK(c, hipGetLastError());
   return MM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free step.  Its buffers live in one file-scope device array
+// per GPU, of fixed size; host code reaches that array only through the
+// device address hipGetSymbolAddress gives for the current device (the
+// array's name is a host-side stand-in, not a device address).
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr int64_t kStaticPoints = MM_STATIC_MAX_POINTS;
+constexpr int64_t kStaticFaces = kFacesPerCell * kStaticPoints;
+constexpr size_t kScratchBytes = 64ull << 20;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_static_mu;
+void* g_scratch_dev[kMaxDevices];          // device address of scratch, per device (set once)
+mm_ctx g_static_ctx[kMaxDevices];          // one context per device, carved from its scratch
+SegDesc g_static_seg[kMaxDevices];         // host mirrors of the one segment and its status
+SegStatus g_static_segst[kMaxDevices];
+DevStatus g_static_st[kMaxDevices];
+
+mm_status static_fail(mm_status code, const std::string& msg) {
+  g_create_err = msg;
+  return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_step_static(const mm_params* p, int64_t n, double* pos, double* w, double* Q, double dt_max,
+                         mm_step_info* info, void* hip_stream) {
+  if (!p) return static_fail(MM_EINVAL, "p is NULL");
+  std::string why;
+  if (!params_ok(p, why)) return static_fail(MM_EINVAL, why);
+  if (p->half_step_mesh) return static_fail(MM_EINVAL, "mm_step_static does not take half_step_mesh = 1");
+  if (p->mach_threshold > 0.0) return static_fail(MM_EINVAL, "mm_step_static does not take the entropy switch");
+  if (n < 1 || n > kStaticPoints)
+    return static_fail(MM_EINVAL, "n must be in [1, MM_STATIC_MAX_POINTS = " + std::to_string(kStaticPoints) + "]");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return static_fail(MM_EHIP, "no usable current device");
+  {
+    // Once per device, with that device current: the device address of its
+    // copy of the scratch array.
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_scratch_dev[dev]) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr)
+        return static_fail(MM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      const size_t need = std::max(Engine::arena_bytes(MM_FP64, kStaticPoints, kStaticFaces),
+                                   Engine::arena_bytes(MM_MIXED, kStaticPoints, kStaticFaces));
+      if (need > kScratchBytes) return static_fail(MM_ECAPACITY, "scratch array smaller than its buffers");
+      g_scratch_dev[dev] = ptr;
+    }
+  }
+  // The context is carved anew each call (pointer arithmetic only), so each
+  // call may bring its own parameters, precision and stream.
+  mm_ctx* c = &g_static_ctx[dev];
+  c->p = *p;
+  c->have_mesh = false;
+  if (mm_status r = c->E.init_arena(p->precision, kStaticPoints, kStaticFaces, g_scratch_dev[dev], kScratchBytes,
+                                    &g_static_seg[dev], &g_static_segst[dev], &g_static_st[dev],
+                                    (hipStream_t)hip_stream))
+    return static_fail(r, c->E.err);
+  const mm_status r = step_common(c, n, pos, w, Q, nullptr, nullptr, dt_max, info);
+  if (r != MM_OK) g_create_err = c->err;
+  return r;
 }
 
 mm_status mm_set_stage_timing(mm_ctx* c, int32_t enable) {

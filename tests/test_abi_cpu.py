@@ -169,3 +169,17 @@ def test_workloads_are_seeded_and_inside_the_box():
         assert np.all(wl.prim[:, 0] > 0) and np.all(wl.prim[:, 4] > 0)
     hot = W.c3_point_blast(n_side=16)
     assert len(hot.energy_cells) == 32 and abs(hot.energy_amount * 32 - 1.0) < 1e-15
+
+
+def test_static_step_validates_on_host():
+    # The allocation-free step refuses bad arguments before touching a device.
+    import ctypes
+    import paper_1707_05333_amd as M
+    L = M.load_library()
+    info = M.StepInfo()
+    assert L.mm_step_static(None, 10, None, None, None, 1.0, ctypes.byref(info), None) == -1
+    p = M.make_params()
+    assert L.mm_step_static(ctypes.byref(p), 0, None, None, None, 1.0, ctypes.byref(info), None) == -1
+    assert b"MM_STATIC_MAX_POINTS" in L.mm_last_error(None)
+    assert L.mm_step_static(ctypes.byref(p), M.STATIC_MAX_POINTS + 1, None, None, None, 1.0,
+                            ctypes.byref(info), None) == -1
