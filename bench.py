@@ -14,10 +14,15 @@ Also reported on the same line:
                summary when it was taken on the current kernel source; its
                "issue" member puts the counted VALU instructions per cell over
                the same duration against the VALU issue peak;
-  flux_kernel  the face kernel against the HBM peak (algorithmic bytes);
+  stage_ms     mean per-step stage times from HIP events (stage_ms_median:
+               their medians over the timed steps);
+  hbm_copy_gbs achievable HBM bandwidth of a 512 MiB device copy;
+  flux_kernel  the face kernel against the HBM peak (algorithmic bytes), and
+               against the measured copy bandwidth;
   mixed        the point blast (128^3, 100 steps) in mixed precision against
                the FP64 path: cell-updates/s of both, relative L1 density
-               error, conservation drift;
+               error, conservation drift; with the CPU baseline also its
+               error against the FP64 oracle on a 64^3 blast (vs_oracle);
   gresho       the Gresho-Chan vortex to t = 2 at 32^2, 64^2, 128^2: L1 of the
                tangential speed and its rate of convergence;
   sod_paper    the paper's Sod tube to t = 2, moving and static mesh, HLLC and
@@ -40,6 +45,7 @@ import json
 import math
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -83,6 +89,8 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=8.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle sample (whole steps)")
+    ap.add_argument("--only-polytropes", action="store_true",
+                    help="run only the two-polytrope object (for profiling its kernels)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 512 MiB device copy (for counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -119,7 +127,75 @@ def cpu_baseline(args):
     dt = time.perf_counter() - t0
     what = "Sod tube 256x64x64 (1,048,576 cells)" if args.workload == "sod" else "blast 64^3"
     return {"value": wl.n * steps / dt, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{steps} whole oracle steps of the {what}", "seconds": dt}
+            "sample": f"{steps} whole oracle steps of the {what}", "seconds": dt, "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count()}
+
+
+def mixed_vs_oracle(M, torch, n_side=64, steps=10):
+    """The mixed-precision path against the FP64 oracle on the point blast
+    (n_side^3 points, `steps` steps): relative L1 density error and the
+    mass, momentum and energy drift of both.  Runs the oracle, so it belongs
+    to the CPU-baseline leg."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    wl = W.c3_point_blast(n_side=n_side)
+    p = oracle.make_params(wl.box, **wl.params)
+    m = oracle.tessellate(wl.pos, wl.box)
+    Q0 = oracle.init_charges(m, p, wl.prim)
+    Q0[wl.energy_cells, 4] += wl.energy_amount
+    m.free()
+    pos_o, Q_o = wl.pos.copy(), Q0.copy()
+    for _ in range(steps):
+        pos_o, Q_o, *_ = oracle.step(pos_o, Q_o, p)
+    r_o = Q_o[:, 0] / oracle.tessellate(pos_o, wl.box).V
+    mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, precision="mixed", **wl.params))
+    pos, Q = torch.from_numpy(wl.pos.copy()).cuda(), torch.from_numpy(Q0.copy()).cuda()
+    w = torch.empty_like(pos)
+    for _ in range(steps):
+        mm.step(pos, w, Q)
+    mm.tessellate(pos)
+    r_g = Q[:, 0].cpu().numpy() / mm.mesh_export().V.cpu().numpy()
+    Qg = Q.cpu().numpy()
+    mm.close()
+
+    def drift(Qe):
+        return {"mass": float(abs(Qe[:, 0].sum() - Q0[:, 0].sum()) / Q0[:, 0].sum()),
+                "momentum": float(np.linalg.norm(Qe[:, 1:4].sum(0) - Q0[:, 1:4].sum(0))
+                                  / max(np.linalg.norm(Qe[:, 1:4], axis=1).sum(), 1e-300)),
+                "energy": float(abs(Qe[:, 4].sum() - Q0[:, 4].sum()) / Q0[:, 4].sum())}
+
+    return {"workload": f"blast_{n_side}^3", "steps": steps,
+            "l1_rho_rel_vs_oracle": float(np.abs(r_g - r_o).sum() / np.abs(r_o).sum()),
+            "drift_mixed": drift(Qg), "drift_oracle": drift(Q_o)}
+
+
+def hbm_copy_gbs(torch, mib=512, reps=10):
+    """Achievable HBM bandwidth: a device-to-device copy of `mib` MiB, timed
+    with events over `reps` copies; read plus written bytes per second."""
+    a = torch.empty(mib << 17, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    return 2 * (mib << 20) / sec / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def tess_traffic(n_launch_cells):
@@ -173,19 +249,20 @@ def run_single(M, torch, wl, precision, steps, warmup, timing=True):
     for _ in range(warmup):
         mm.step(pos, w, Q)
     mm.set_stage_timing(timing)
-    stage_tot, faces_tot = {k: 0.0 for k in M.STAGE_NAMES}, 0
+    per_step, faces_tot = [], 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         info = mm.step(pos, w, Q)
         if timing:
-            for k, v in mm.stage_ms().items():
-                stage_tot[k] += v
+            per_step.append(mm.stage_ms())
         faces_tot += info["n_faces"]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     mm.set_stage_timing(False)
-    stage_ms = {k: v / max(steps, 1) for k, v in stage_tot.items()}
+    stage_ms = {k: sum(s[k] for s in per_step) / max(len(per_step), 1) for k in M.STAGE_NAMES}
+    run_single.median = {k: statistics.median([s[k] for s in per_step]) if per_step else 0.0
+                         for k in M.STAGE_NAMES}
     return elapsed, stage_ms, faces_tot / max(steps, 1), (mm, pos, Q, w)
 
 
@@ -599,14 +676,20 @@ def main():
     import paper_1707_05333_amd as M
 
     torch.cuda.set_device(0)
+    if args.only_polytropes:
+        print(json.dumps({"polytropes": polytropes_object(M, torch, args)}))
+        return
     wl = make_workload(args.workload)
     n = wl.n
     log(f"workload {args.workload} n={n} precision={args.precision}")
     elapsed, stage_ms, faces, (mm, *_rest) = run_single(M, torch, wl, args.precision, args.steps, args.warmup)
     mm.close()
+    stage_median = dict(run_single.median)
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
     ms_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
+    copy_gbs = hbm_copy_gbs(torch)
+    log(f"device copy {copy_gbs:.0f} GB/s")
 
     if args.copy_calibration:
         a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
@@ -652,9 +735,12 @@ def main():
                    "faces_per_step": faces},
         "roofline": roofline,
         "stage_ms": stage_ms,
+        "stage_ms_median": stage_median,
+        "hbm_copy_gbs": copy_gbs,
         "flux_kernel": {"bound": "hbm", "achieved": flux_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": flux_gbs / PEAK_HBM_GBS, "algorithmic_bytes": flux_bytes,
-                        "launch_ms": stage_ms["flux"]},
+                        "frac": flux_gbs / PEAK_HBM_GBS, "frac_of_copy": flux_gbs / copy_gbs,
+                        "algorithmic_bytes": flux_bytes, "launch_ms": stage_ms["flux"],
+                        "launch_ms_median": stage_median["flux"]},
     }
     if not args.no_mixed:
         out["mixed"] = mixed_object(M, torch, args)
@@ -680,6 +766,11 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args)
         log(f"cpu baseline {out['cpu_baseline']['seconds']:.1f} s")
+        if "mixed" in out:
+            # the oracle's run of a smaller blast is the FP64 reference of the
+            # mixed path (the oracle runs only in this leg)
+            out["mixed"]["vs_oracle"] = mixed_vs_oracle(M, torch)
+            log(f"mixed vs oracle: L1 {out['mixed']['vs_oracle']['l1_rho_rel_vs_oracle']:.2e}")
     print(json.dumps(out))
 
 

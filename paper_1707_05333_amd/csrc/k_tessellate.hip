@@ -39,6 +39,7 @@ constexpr int kWaves = MM_TESS_WAVES;   // cells (wavefronts) per workgroup
 constexpr int kShells = 512;            // distance shells of the second pass
 constexpr int kShells1 = 3;             // extra shells a cell may take in the first pass
 constexpr int kFewCands = 8;            // below this many first candidates, a cell's region is thin
+constexpr int kThinRing = 8;            // widest stencil of a thin region's first gather
 // Live vertices the shell pass keeps for pruning candidates (a cell with
 // more, rare, gathers its shells unpruned); 13 KB of LDS per wavefront with
 // the cell, so the pass's 12 waves per CU (by registers) fit.
@@ -319,6 +320,82 @@ __device__ inline bool box_may_cut(const double4* vl, int nv, const double lo[3]
   return out;
 }
 
+// The same two tests with the roles of lanes turned round, for when few
+// lanes ask (the sparse stencils of a thin region): each asking lane's box
+// or image is broadcast in turn and every lane tests the vertex it holds
+// (vertex k in lane k, vertex k + 64 in the second register).  Each
+// (box or image, vertex) pair is the same comparison as above, so the
+// answers are the same; only the work follows the number of asking lanes
+// instead of the number of vertices.
+struct LaneVerts {
+  double4 a, b;   // vertices lane and lane + 64 (w = -1: none)
+  bool two;       // some lane holds a second vertex
+};
+
+__device__ inline LaneVerts lane_verts(const double4* vl, int nv) {
+  const int lane = __lane_id();
+  LaneVerts V;
+  const double4 none = make_double4(0.0, 0.0, 0.0, -1.0);
+  V.a = lane < nv ? vl[lane] : none;
+  V.b = lane + 64 < nv ? vl[lane + 64] : none;
+  V.two = nv > 64;
+  return V;
+}
+
+__device__ inline double readlane_d(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ inline bool vert_near_box(const double4 v, const double lo[3], const double hi[3], double slack) {
+  const double ex = fmax(0.0, fmax(lo[0] - v.x, v.x - hi[0]));
+  const double ey = fmax(0.0, fmax(lo[1] - v.y, v.y - hi[1]));
+  const double ez = fmax(0.0, fmax(lo[2] - v.z, v.z - hi[2]));
+  return ex * ex + ey * ey + ez * ez < v.w * (1.0 + 1e-9) + slack;
+}
+
+// box_may_cut for every lane with `ask` set (false for the others); called
+// by the whole wavefront.
+__device__ inline bool boxes_may_cut(bool ask, const double4* vl, int nv, const LaneVerts& V, const double lo[3],
+                                     const double hi[3], double slack) {
+  const unsigned long long m = __ballot(ask);
+  if (m == 0ull) return false;
+  if (3 * __popcll(m) >= nv) return ask && box_may_cut(vl, nv, lo, hi, slack);
+  const int lane = __lane_id();
+  bool res = false;
+  for (unsigned long long r = m; r; r &= r - 1ull) {
+    const int l = __builtin_ctzll(r);
+    const double blo[3] = {readlane_d(lo[0], l), readlane_d(lo[1], l), readlane_d(lo[2], l)};
+    const double bhi[3] = {readlane_d(hi[0], l), readlane_d(hi[1], l), readlane_d(hi[2], l)};
+    bool t = vert_near_box(V.a, blo, bhi, slack);
+    if (V.two) t |= vert_near_box(V.b, blo, bhi, slack);
+    if (__ballot(t) != 0ull && lane == l) res = true;
+  }
+  return res;
+}
+
+// may_cut for every lane with `ask` set (false for the others); called by
+// the whole wavefront.
+__device__ inline bool images_may_cut(bool ask, const double4* vl, int nv, const LaneVerts& V, double dx, double dy,
+                                      double dz, double d2) {
+  const unsigned long long m = __ballot(ask);
+  if (m == 0ull) return false;
+  if (4 * __popcll(m) >= nv) return ask && may_cut(vl, nv, dx, dy, dz, d2);
+  const int lane = __lane_id();
+  bool res = false;
+  for (unsigned long long r = m; r; r &= r - 1ull) {
+    const int l = __builtin_ctzll(r);
+    const double x = readlane_d(dx, l), y = readlane_d(dy, l), z = readlane_d(dz, l);
+    const double h = 0.5 * readlane_d(d2, l) * (1.0 - 1e-12);
+    bool t = x * V.a.x + y * V.a.y + z * V.a.z > h;
+    if (V.two) t |= x * V.b.x + y * V.b.y + z * V.b.z > h;
+    if (__ballot(t) != 0ull && lane == l) res = true;
+  }
+  return res;
+}
+
 // Gather of one 128-bucket chunk of the stencil that holds dense buckets.
 // Each bucket contributes runs of consecutive points: a sparse bucket its
 // whole range, a dense one the part of each sub-bucket row (along x) that
@@ -335,15 +412,20 @@ __device__ int gather_runs(TessLds& S, const TessArgs& A, const GridParams& g, c
   // Half-width of the query box, with a margin far above the rounding of
   // the distance test, so that every point the test keeps lies inside.
   const double rq = sqrt(hi2) * (1.0 + 1e-9) + 1e-9 * fmin(g.hb[0], fmin(g.hb[1], g.hb[2]));
+  LaneVerts V{};
+  if (vl) V = lane_verts(vl, nv);
   for (int half = 0; half < 2; ++half) {
     int bb[3] = {0, 0, 0};
     int64_t key = 0;
     const StencilBucket B = stencil_bucket(A, g, b, ring, chunk + 64 * half + lane, W3, D, bb, &key);
     int nr = 0, pack = 0, base = 0;
+    const double sh[3] = {B.sx, B.sy, B.sz};
+    double qlo[3] = {0.0, 0.0, 0.0}, qhi[3] = {0.0, 0.0, 0.0};
+    bool meet = false;
+    // the bucket's box relative to the generator, widened a little
+    double blo[3] = {0.0, 0.0, 0.0}, bhi[3] = {0.0, 0.0, 0.0};
     if (B.cnt > 0) {
-      const double sh[3] = {B.sx, B.sy, B.sz};
-      double qlo[3], qhi[3];
-      bool meet = true;
+      meet = true;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         qlo[a] = (r[a] - rq) - sh[a];
@@ -354,15 +436,15 @@ __device__ int gather_runs(TessLds& S, const TessArgs& A, const GridParams& g, c
         if (thi < (double)bb[a] || (tlo >= (double)(bb[a] + 1) && bb[a] < g.nb[a] - 1)) meet = false;
       }
       if (meet && vl) {
-        // the bucket's box relative to the generator, widened a little
-        double blo[3], bhi[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           blo[a] = (bb[a] * g.hb[a] + sh[a]) - r[a] - 1e-9 * g.hb[a];
           bhi[a] = ((bb[a] + 1) * g.hb[a] + sh[a]) - r[a] + 1e-9 * g.hb[a];
         }
-        meet = box_may_cut(vl, nv, blo, bhi, 1e-12 * hi2);
       }
+    }
+    if (vl) meet = boxes_may_cut(meet, vl, nv, V, blo, bhi, 1e-12 * hi2);
+    if (B.cnt > 0) {
       if (meet) {
         if (B.cnt <= kDense || B.cnt > kDenseMax) {
           nr = 1;
@@ -406,28 +488,32 @@ __device__ int gather_runs(TessLds& S, const TessArgs& A, const GridParams& g, c
       decode(code_o, kx, ky, kz);
       const double sx = kx * g.L[0], sy = ky * g.L[1], sz = kz * g.L[2];
       int start = bst_o, count = t < total ? cnt_o : 0;
-      if (pack_o != 0 && t < total) {
-        const int ss = pack_o & 31, x0 = (pack_o >> 5) & 31, nx = (pack_o >> 10) & 31;
-        const int y0 = (pack_o >> 15) & 31, ny = (pack_o >> 20) & 31, z0 = (pack_o >> 25) & 31;
-        const int jr = t - e_o;
-        const int ry = y0 + jr % ny, rz = z0 + jr / ny;
-        bool take = true;
-        if (vl) {
-          // the row's box: sub-buckets x0 .. x0 + nx - 1 of row (ry, rz)
+      const bool row = pack_o != 0 && t < total;
+      const int ss = pack_o & 31, x0 = (pack_o >> 5) & 31, nx = (pack_o >> 10) & 31;
+      const int y0 = (pack_o >> 15) & 31, ny = (pack_o >> 20) & 31, z0 = (pack_o >> 25) & 31;
+      const int jr = t - e_o;
+      const int ry = row ? y0 + jr % ny : 0, rz = row ? z0 + jr / ny : 0;
+      bool take = row;
+      if (vl) {
+        // the row's box: sub-buckets x0 .. x0 + nx - 1 of row (ry, rz)
+        double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+        if (row) {
           const double is = 1.0 / ss;
-          const double lo[3] = {(bx_o + x0 * is) * g.hb[0] + sx - r[0] - 1e-9 * g.hb[0],
-                                (by_o + ry * is) * g.hb[1] + sy - r[1] - 1e-9 * g.hb[1],
-                                (bz_o + rz * is) * g.hb[2] + sz - r[2] - 1e-9 * g.hb[2]};
-          const double hi[3] = {(bx_o + (x0 + nx) * is) * g.hb[0] + sx - r[0] + 1e-9 * g.hb[0],
-                                (by_o + (ry + 1) * is) * g.hb[1] + sy - r[1] + 1e-9 * g.hb[1],
-                                (bz_o + (rz + 1) * is) * g.hb[2] + sz - r[2] + 1e-9 * g.hb[2]};
-          take = box_may_cut(vl, nv, lo, hi, 1e-12 * hi2);
+          lo[0] = (bx_o + x0 * is) * g.hb[0] + sx - r[0] - 1e-9 * g.hb[0];
+          lo[1] = (by_o + ry * is) * g.hb[1] + sy - r[1] - 1e-9 * g.hb[1];
+          lo[2] = (bz_o + rz * is) * g.hb[2] + sz - r[2] - 1e-9 * g.hb[2];
+          hi[0] = (bx_o + (x0 + nx) * is) * g.hb[0] + sx - r[0] + 1e-9 * g.hb[0];
+          hi[1] = (by_o + (ry + 1) * is) * g.hb[1] + sy - r[1] + 1e-9 * g.hb[1];
+          hi[2] = (bz_o + (rz + 1) * is) * g.hb[2] + sz - r[2] + 1e-9 * g.hb[2];
         }
+        take = boxes_may_cut(row, vl, nv, V, lo, hi, 1e-12 * hi2);
+      }
+      if (row) {
         count = 0;
         if (take) {
-          const int row = (rz * ss + ry) * ss + x0;
+          const int ri = (rz * ss + ry) * ss + x0;
           const uint32_t* so = A.soffs + base_o;
-          const int a0 = (int)so[row], a1 = (int)so[row + nx];
+          const int a0 = (int)so[ri], a1 = (int)so[ri + nx];
           start = bst_o + a0;
           count = a1 - a0;
         }
@@ -445,7 +531,7 @@ __device__ int gather_runs(TessLds& S, const TessArgs& A, const GridParams& g, c
         const double dx = (x + sx) - r[0], dy = (y + sy) - r[1], dz = (z + sz) - r[2];
         const double d2 = dx * dx + dy * dy + dz * dz;
         bool keep = v && (d2 >= lo2) && (d2 < hi2);
-        if (vl && keep) keep = may_cut(vl, nv, dx, dy, dz, d2);
+        if (vl) keep = images_may_cut(keep, vl, nv, V, dx, dy, dz, d2);
         const unsigned long long mk = __ballot(keep);
         if (keep) {
           const int idx = nc + __popcll(mk & lanes_below());
@@ -940,10 +1026,31 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
 #pragma unroll
     for (int a = 0; a < 3; ++a) reach = fmin(reach, ring * g.hb[a] + edge[a]);
     double hi2 = fmin(reach * reach, rloc * rloc);
-    const int nc = gather<MODE != 0>(S, A, g, s, r, b, ring, 0.0, hi2);
+    int nc = gather<MODE != 0>(S, A, g, s, r, b, ring, 0.0, hi2);
     if (nc < 0) {
       defer_dense(A, s);
       return;
+    }
+    if (MODE == 0 && nc < kFewCands) {
+      // A thin region: the first radius, sized for the mean spacing, holds
+      // few neighbours.  It grows, in one wider gather, to the radius that
+      // holds as many neighbours as the first radius holds on average at
+      // the mean density (the count found gives the local density), when
+      // that stencil stays narrow enough; otherwise the cell goes to the
+      // shell pass as before.
+      const double mean_cands = 4.18879020478639 * (g.r_filter * g.r_filter * g.r_filter) * g.ppb /
+                                (g.hb[0] * g.hb[1] * g.hb[2]);   // (4 pi / 3) r^3 times the mean density
+      const double rt = g.r_filter * cbrt(mean_cands / (double)max(nc, 1));
+      const double nhi2 = rt * rt;
+      const int nring = ring_for(g, edge, nhi2);
+      if (nhi2 > hi2 && nring <= kThinRing && nring <= g.nb[0] && nring <= g.nb[1] && nring <= g.nb[2]) {
+        nc = gather<false>(S, A, g, s, r, b, nring, 0.0, nhi2);
+        if (nc < 0) {
+          defer_dense(A, s);
+          return;
+        }
+        hi2 = nhi2;
+      }
     }
     if (nc > kCands) {
       if (__lane_id() == 0) atomicAdd(&A.st->n_overflow, 1);
