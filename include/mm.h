@@ -106,7 +106,9 @@ typedef struct {
   int64_t floor_hits[4];     /* floors fired: [0] cell states at the start, [1] half-step states,
                                 [2] face states, [3] charges after the update (Sec. 4.1) */
   int32_t flags;             /* internal failure bits (0 when the step succeeded) */
-  int32_t reserved;
+  int32_t rebuilt_cells;     /* cells the two-cells-per-wavefront first pass handed to the one-cell
+                                first pass (too many candidates, faces or vertices for its slots, a
+                                thin region, or more than one distance shell) */
 } mm_step_info;
 
 /* Device views of the current tessellation, in the library's internal
@@ -146,7 +148,7 @@ mm_status mm_set_params(mm_ctx *ctx, const mm_params *p);
  * pos: dev [n][3], each coordinate in [0, L).  Keeps the mesh in the
  * context for mm_mesh_view/mm_mesh_export/mm_init_charges/mm_cell_state/
  * mm_gradients/mm_predict/mm_fluxes.  info (host, may be NULL) receives
- * n_faces, max_faces_cell and deferred_cells.  Waits for the stream.
+ * n_faces, max_faces_cell, deferred_cells and rebuilt_cells.  Waits for the stream.
  * Errors: MM_EINVAL (bad n or positions), MM_ECAPACITY, MM_EDEGENERATE. */
 mm_status mm_tessellate(mm_ctx *ctx, int64_t n, const double *pos, mm_step_info *info);
 

@@ -60,12 +60,13 @@ class StepInfo(ctypes.Structure):
         ("deferred_cells", ctypes.c_int32),
         ("floor_hits", ctypes.c_int64 * 4),
         ("flags", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("rebuilt_cells", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return dict(dt=self.dt, dt_cfl=self.dt_cfl, n_faces=self.n_faces, max_faces_cell=self.max_faces_cell,
-                    deferred_cells=self.deferred_cells, floor_hits=list(self.floor_hits), flags=self.flags)
+                    deferred_cells=self.deferred_cells, rebuilt_cells=self.rebuilt_cells,
+                    floor_hits=list(self.floor_hits), flags=self.flags)
 
 
 class MeshView(ctypes.Structure):

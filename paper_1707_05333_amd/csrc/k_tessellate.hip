@@ -1,7 +1,9 @@
-// Periodic Voronoi tessellation by half-space clipping, one wavefront per
-// cell (Sec. 3 of the paper: start from a box around the generator, cut it by
-// the bisector plane of each neighbour in order of distance, and stop once
-// the next neighbour is farther than twice the farthest vertex).
+// Periodic Voronoi tessellation by half-space clipping (Sec. 3 of the paper:
+// start from a box around the generator, cut it by the bisector plane of each
+// neighbour in order of distance, and stop once the next neighbour is farther
+// than twice the farthest vertex).  The first pass builds two cells per
+// wavefront, one per half (the cells of uniform regions, most of them); the
+// cells it hands on, and those of the later passes, get a wavefront each.
 //
 // Cell representation (all in the wavefront's LDS slice).  A convex cell is
 // stored by its dual: every face is a plane slot (normal d = r_j + s - r_i
@@ -86,6 +88,7 @@ struct TessArgs {
   double* rmax2;
   int32_t* deferred;
   int32_t* dcells;                   // cells for the dense first pass
+  int32_t* redo;                     // cells the two-cell first pass hands to the one-cell one
   DevStatus* st;
   SegStatus* segst;
 };
@@ -979,13 +982,12 @@ __device__ void defer_dense(const TessArgs& A, int s) {
 }
 
 // Builds the cell of internal generator s.
-// MODE 0 (first pass, every cell): candidates within the grid's filter
-//   radius; a cell whose candidates do not cover twice its farthest vertex
-//   goes on with up to kShells1 more shells (when it found at least
-//   kFewCands candidates), and one that still falls short (or overflows the
-//   candidate slots) is deferred to the shell pass; a cell with a dense
-//   bucket in its own bucket or stencil goes to MODE 1.
-//   This kernel stays lean (uniform inputs finish here).
+// MODE 0 (first pass of the cells the two-cell pass hands on): candidates
+//   within the grid's filter radius; a cell whose candidates do not cover
+//   twice its farthest vertex goes on with up to kShells1 more shells (when
+//   it found at least kFewCands candidates), and one that still falls short
+//   (or overflows the candidate slots) is deferred to the shell pass; a cell
+//   with a dense bucket in its own bucket or stencil goes to MODE 1.
 // MODE 1 (first pass of the cells near dense regions): the same with the
 //   two-level gather.
 // MODE 2 (shell pass): distance shells [lo, hi) processed in order, each
@@ -1148,14 +1150,6 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
   if (int bad = finish_cell(S, A, s, C)) fail_cell(A, s, seg, bad);
 }
 
-__global__ __launch_bounds__(64 * kWaves) void k_tess_pass1(TessArgs A) {
-  __shared__ TessLds lds[kWaves];
-  const int w = threadIdx.x >> 6;
-  const int64_t s = xcd_block() * kWaves + w;
-  if (s >= A.n) return;
-  tess_cell<0>(lds[w], A, (int)s);
-}
-
 // Four waves per SIMD, with some values of the two-level gather and the
 // extra shells spilled (at three, without spills, it is slower).
 // The listed cells: those of the dense buckets (listed by the sort) and
@@ -1178,24 +1172,648 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
     tess_cell<2>(lds[w], A, A.deferred[it], verts[w]);
 }
 
+// ---------------------------------------------------------------------------
+// The lean first pass with two cells per wavefront.
+//
+// One wavefront builds one cell above, and most of the work of a cut (the
+// plane slot, the cap's boundary, the new vertices of the fan) occupies a
+// few lanes while the others wait.  Here each half of the wavefront (32
+// lanes) builds its own cell with the same steps, so one instruction serves
+// two cells.  A half holds 64 vertex slots (two per lane), 40 plane slots
+// and 48 candidates, 5 KB of LDS per cell, so 32 cells fit a CU (twice the
+// one-cell pass): the usual cell of the uniform inputs (about 16 faces, 28
+// vertices, 29 candidates) fits with room to spare.  A cell that needs
+// more, more than one distance shell, or the two-level grid (a thin region
+// or a dense bucket nearby) is handed to the one-cell pass, which builds it
+// as before.  Values that are uniform per cell are uniform per half here:
+// held in each lane of the half, and the half's 32 bits of every ballot are
+// its masks.
+// ---------------------------------------------------------------------------
+constexpr int kPlanesP = 40;
+constexpr int kVertsP = 64;
+constexpr int kCandsP = 48;
+
+struct __align__(16) PairLds {
+  double4 pl[kPlanesP];
+  union {
+    struct {                           // while the cell is cut
+      double4 cd[kCandsP];
+      int32_t cjk[kCandsP];
+      uint8_t order[kCandsP];
+      uint16_t elist[kVertsP];
+      uint8_t kept[kVertsP];
+    };
+    struct {                           // in the epilogue
+      double vx[kVertsP], vy[kVertsP], vz[kVertsP];
+      int32_t first[kPlanesP];
+      uint32_t tri[kVertsP];
+    };
+  };
+  int32_t pcand[kPlanesP];
+  uint8_t E[kPlanesP * kPlanesP];
+};
+static_assert(sizeof(PairLds) <= 5120, "32 cells per CU");
+
+__device__ __forceinline__ int hlane() { return __lane_id() & 31; }
+// The 32 bits of a wavefront mask that belong to this lane's half.
+__device__ __forceinline__ unsigned hbits(unsigned long long m) { return (unsigned)(m >> (__lane_id() & 32)); }
+__device__ __forceinline__ unsigned hbelow() { return (1u << hlane()) - 1u; }
+
+template <int BITS>
+__device__ __forceinline__ int half_excl_scan_small(int x, int* total) {
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) {
+    const unsigned m = hbits(__ballot((x >> b) & 1));
+    pre += __popc(m & hbelow()) << b;
+    tot += __popc(m) << b;
+  }
+  *total = tot;
+  return pre;
+}
+
+// Reductions over each half: within rows of 16 by quad permutes and row
+// rotations, then row 0 into row 1 and row 2 into row 3; lanes 31 and 63
+// end with the two halves' results.
+#define MM_DPP_REDUCE_HALF(OP, x)                                                   \
+  do {                                                                              \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));  \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));  \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xF, 0xF, false)); \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xF, 0xF, false)); \
+    x = OP(x, (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false)); \
+  } while (0)
+
+__device__ __forceinline__ unsigned half_pick(unsigned x) {
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)x, 31);
+  const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)x, 63);
+  return (__lane_id() & 32) ? b : a;
+}
+
+__device__ __forceinline__ unsigned half_umax32(unsigned x) {
+  MM_DPP_REDUCE_HALF(op_max, x);
+  return half_pick(x);
+}
+
+__device__ __forceinline__ unsigned long long half_or(unsigned long long v) {
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  MM_DPP_REDUCE_HALF(op_or, lo);
+  MM_DPP_REDUCE_HALF(op_or, hi);
+  return ((unsigned long long)half_pick(hi) << 32) | half_pick(lo);
+}
+
+// Upper bound of the half's largest non-negative finite value (as
+// wave_max_bound).
+__device__ __forceinline__ double half_max_bound(double x) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(x) >> 32) + 1u;
+  return __longlong_as_double((long long)((unsigned long long)half_umax32(hi) << 32));
+}
+
+// Butterfly sum within each half: every lane of a half ends with the
+// bitwise-same result.
+__device__ __forceinline__ double half_sum(double x) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// One half's cell: vertex slots hl and hl + 32 of lane hl; L0w, L1w are the
+// wavefront's live masks (this half's bits by hbits); np, rmax2 uniform per
+// half.
+struct PairRegs {
+  unsigned long long L0w, L1w;
+  uint32_t t0, t1;
+  double v0x, v0y, v0z, v1x, v1y, v1z;
+  double rmax2;
+  int np;
+};
+
+__device__ void init_box_pair(PairLds& S, const GridParams& g, PairRegs& C) {
+  const int hl = hlane();
+  if (hl < 6) {
+    const int ax = hl >> 1;
+    const double sg = (hl & 1) ? -1.0 : 1.0;
+    double d[3] = {0.0, 0.0, 0.0};
+    d[ax] = sg * g.L[ax];
+    S.pl[hl] = make_double4(d[0], d[1], d[2], 0.5 * (g.L[ax] * g.L[ax]));
+    S.pcand[hl] = -1 - hl;
+  }
+  C.t0 = C.t1 = 0u;
+  C.v0x = C.v0y = C.v0z = C.v1x = C.v1y = C.v1z = 0.0;
+  if (hl < 8) {
+    const int sx = (hl & 1) ? -1 : 1, sy = (hl & 2) ? -1 : 1, sz = (hl & 4) ? -1 : 1;
+    const int px = sx > 0 ? 0 : 1, py = sy > 0 ? 2 : 3, pz = sz > 0 ? 4 : 5;
+    int a1 = py, a2 = pz;
+    if (sx * sy * sz < 0) { a1 = pz; a2 = py; }   // orientation: det(d_a, d_b, d_c) > 0
+    C.t0 = (uint32_t)(px | (a1 << 8) | (a2 << 16));
+    C.v0x = sx * (0.5 * g.L[0]);
+    C.v0y = sy * (0.5 * g.L[1]);
+    C.v0z = sz * (0.5 * g.L[2]);
+    S.E[px * kPlanesP + a1] = (uint8_t)hl;
+    S.E[a1 * kPlanesP + a2] = (uint8_t)hl;
+    S.E[a2 * kPlanesP + px] = (uint8_t)hl;
+  }
+  wave_sync();
+  C.L0w = __ballot(hl < 8);
+  C.L1w = 0ull;
+  C.np = 6;
+  C.rmax2 = half_max_bound(hl < 8 ? C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z : 0.0);
+}
+
+__device__ inline double farthest_bound_pair(const PairRegs& C) {
+  const int hl = hlane();
+  double m2 = 0.0;
+  if ((hbits(C.L0w) >> hl) & 1u) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
+  if ((hbits(C.L1w) >> hl) & 1u) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
+  return half_max_bound(m2);
+}
+
+// The first gather of the plain path for both halves: images with
+// |d|^2 < hi2 from each half's stencil of half-width `ring`, four stencil
+// buckets per lane at a time (the usual 125-bucket stencil in one memory
+// round trip, as in the one-cell gather).  Returns this half's candidate
+// count, -1 when its stencil holds a dense bucket, or kCandsP + 1 on
+// overflow.  Called by the whole wavefront (act: the half has a cell).
+constexpr int kPairBuckets = 4;
+
+__device__ int gather_pair(PairLds& S, const TessArgs& A, const GridParams& g, bool act, const int s,
+                           const double r[3], const int b[3], const int ring, const double hi2) {
+  const int hl = hlane();
+  const int W = 2 * ring + 1, W3 = act ? W * W * W : 0;
+  const WidthDiv D = width_div((unsigned)W);
+  const int W3max = (int)wave_umax32((unsigned)W3);
+  int nc = 0;
+  bool dense = false;
+  for (int chunk = 0; chunk < W3max; chunk += 32 * kPairBuckets) {
+    StencilBucket B[kPairBuckets];
+    bool dn = false;
+#pragma unroll
+    for (int u = 0; u < kPairBuckets; ++u) {
+      B[u] = stencil_bucket(A, g, b, ring, chunk + 32 * u + hl, W3, D);
+      dn |= B[u].cnt > kDense;
+    }
+    dense |= hbits(__ballot(dn)) != 0u;
+    int cmax = 0;
+#pragma unroll
+    for (int u = 0; u < kPairBuckets; ++u) {
+      if (dense) B[u].cnt = 0;
+      cmax = max(cmax, B[u].cnt);
+    }
+    const int maxc = (int)wave_umax32((unsigned)cmax);
+    for (int k = 0; k < maxc; ++k) {
+      double dx[kPairBuckets], dy[kPairBuckets], dz[kPairBuckets], d2[kPairBuckets];
+      bool keep[kPairBuckets];
+#pragma unroll
+      for (int u = 0; u < kPairBuckets; ++u) {
+        const int j = B[u].bst + k;
+        const bool v = k < B[u].cnt && j != s;
+        double x = 0, y = 0, z = 0;
+        if (v) {
+          x = A.spos[3 * (int64_t)j];
+          y = A.spos[3 * (int64_t)j + 1];
+          z = A.spos[3 * (int64_t)j + 2];
+        }
+        dx[u] = (x + B[u].sx) - r[0];
+        dy[u] = (y + B[u].sy) - r[1];
+        dz[u] = (z + B[u].sz) - r[2];
+        d2[u] = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
+        keep[u] = v && d2[u] < hi2;
+      }
+#pragma unroll
+      for (int u = 0; u < kPairBuckets; ++u) {
+        const unsigned mk = hbits(__ballot(keep[u]));
+        if (keep[u]) {
+          const int idx = nc + __popc(mk & hbelow());
+          if (idx < kCandsP) {
+            S.cd[idx] = make_double4(dx[u], dy[u], dz[u], 0.5 * d2[u]);
+            S.cjk[idx] = ((B[u].bst + k) << 5) | B[u].code;
+          }
+        }
+        nc += __popc(mk);
+      }
+    }
+  }
+  wave_sync();
+  if (dense) return -1;
+  return nc > kCandsP ? kCandsP + 1 : nc;
+}
+
+// Candidates of each half ordered by distance, ties by neighbour and image
+// (as sort_candidates).
+__device__ void sort_pair(PairLds& S, const int nc) {
+  const int hl = hlane();
+  const int c0 = hl, c1 = hl + 32;
+  int lt0 = 0, lt1 = 0;
+  const double k0 = c0 < nc ? S.cd[c0].w : 0.0, k1 = c1 < nc ? S.cd[c1].w : 0.0;
+  const int ncmax = (int)wave_umax32((unsigned)nc);
+  for (int m = 0; m < ncmax; ++m) {
+    if (m < nc) {
+      const double km = S.cd[m].w;
+      lt0 += km < k0;
+      lt1 += km < k1;
+    }
+  }
+  if (c0 < nc) S.order[lt0] = (uint8_t)c0;
+  if (c1 < nc) S.order[lt1] = (uint8_t)c1;
+  wave_sync();
+  const bool tie = (c0 < nc && S.order[lt0] != c0) || (c1 < nc && S.order[lt1] != c1);
+  const bool htie = hbits(__ballot(tie)) != 0u;
+  if (__ballot(htie) == 0ull) return;
+  wave_sync();
+  for (int rnd = 0; rnd < 2; ++rnd) {
+    const int c = hl + 32 * rnd;
+    if (htie && c < nc) {
+      const double key = S.cd[c].w;
+      const int id = S.cjk[c];
+      int rank = 0;
+      for (int m = 0; m < nc; ++m) {
+        const double km = S.cd[m].w;
+        rank += (km < key) || (km == key && (S.cjk[m] < id || (S.cjk[m] == id && m < c)));
+      }
+      S.order[rank] = (uint8_t)c;
+    }
+  }
+  wave_sync();
+}
+
+// Cuts each half's cell by its ordered candidates (as clip_candidates).
+// Returns 0 or a failure bit for this half's cell.
+__device__ int clip_pair(PairLds& S, const int nc, PairRegs& C) {
+  const int hl = hlane();
+  bool stale = false, done = nc <= 0;
+  int since = 0, fail = 0;
+  double lim = 2.0 * C.rmax2;
+  const int ncmax = (int)wave_umax32((unsigned)max(nc, 0));
+  for (int k = 0; k < ncmax; ++k) {
+    // A half that stopped, or ran out of candidates, stays idle: the loop
+    // ends when both are.
+    bool act = !done && k < nc;
+    if (__ballot(act) == 0ull) break;
+    double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
+    int c = 0;
+    if (act) {
+      c = S.order[k];
+      q = S.cd[c];
+    }
+    const double h = q.w;
+    // Stop test of each half: farther images cannot cut its cell.
+    const bool far = act && h >= lim;
+    if (__ballot(far)) {
+      const double nb = farthest_bound_pair(C);
+      if (far) {
+        if (!stale) {
+          act = false;
+          done = true;
+        } else {
+          C.rmax2 = nb;
+          stale = false;
+          since = 0;
+          lim = 2.0 * nb;
+          if (h >= lim) {
+            act = false;
+            done = true;
+          }
+        }
+      }
+    }
+    const unsigned M0 = hbits(__ballot(act && q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h)) & hbits(C.L0w);
+    const unsigned M1 = hbits(__ballot(act && q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h)) & hbits(C.L1w);
+    const bool cut = act && (M0 | M1) != 0u;
+    if (__ballot(cut) == 0ull) continue;
+    const bool live0 = (hbits(C.L0w) >> hl) & 1u, live1 = (hbits(C.L1w) >> hl) & 1u;
+    const bool out0 = cut && ((M0 >> hl) & 1u), out1 = cut && ((M1 >> hl) & 1u);
+    const bool kept0 = live0 && !out0, kept1 = live1 && !out1;
+
+    // Plane slot: the next unused one (a cell that needs more goes to the
+    // one-cell pass, which reuses the slots of faces cut away).
+    const int p = C.np;
+    bool go = cut;
+    if (cut && p >= kPlanesP) {
+      fail = F_PLANES;
+      done = true;
+      go = false;
+    }
+    if (go) C.np++;
+
+    if (go) {
+      S.kept[hl] = (uint8_t)kept0;
+      S.kept[hl + 32] = (uint8_t)kept1;
+    }
+    wave_sync();
+    auto boundary = [&](uint32_t T) -> int {
+      const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
+      const int m0 = S.kept[S.E[bq * kPlanesP + a] & (kVertsP - 1)];
+      const int m1 = S.kept[S.E[cq * kPlanesP + bq] & (kVertsP - 1)];
+      const int m2 = S.kept[S.E[a * kPlanesP + cq] & (kVertsP - 1)];
+      return m0 | (m1 << 1) | (m2 << 2);
+    };
+    const int bm0 = go && out0 ? boundary(C.t0) : 0;
+    const int bm1 = go && out1 ? boundary(C.t1) : 0;
+    int B;
+    const int pre = half_excl_scan_small<3>(__popc(bm0) + __popc(bm1), &B);
+    const unsigned F0 = ~hbits(C.L0w) | M0, F1 = ~hbits(C.L1w) | M1;   // free slots after the cut
+    const int nf0 = __popc(F0);
+    const bool room = B <= nf0 + __popc(F1);
+    if (go && !room) {
+      fail = F_VERTS;
+      done = true;
+    }
+    const bool doit = go && room;
+    if (doit && hl == 0) {
+      S.pl[p] = make_double4(q.x, q.y, q.z, h);
+      S.pcand[p] = S.cjk[c];
+    }
+    if (doit) {
+      int e = pre;
+      const int ta0 = C.t0 & 255, tb0 = (C.t0 >> 8) & 255, tc0 = (C.t0 >> 16) & 255;
+      if (bm0 & 1) S.elist[e++] = (uint16_t)(ta0 | (tb0 << 8));
+      if (bm0 & 2) S.elist[e++] = (uint16_t)(tb0 | (tc0 << 8));
+      if (bm0 & 4) S.elist[e++] = (uint16_t)(tc0 | (ta0 << 8));
+      const int ta1 = C.t1 & 255, tb1 = (C.t1 >> 8) & 255, tc1 = (C.t1 >> 16) & 255;
+      if (bm1 & 1) S.elist[e++] = (uint16_t)(ta1 | (tb1 << 8));
+      if (bm1 & 2) S.elist[e++] = (uint16_t)(tb1 | (tc1 << 8));
+      if (bm1 & 4) S.elist[e++] = (uint16_t)(tc1 | (ta1 << 8));
+    }
+    wave_sync();   // every E lookup above is done before any write below
+
+    // Boundary edge r goes to the free slot of rank r (the first register's
+    // slots in lane order, then the second's); that lane builds the vertex.
+    const double4 qp = make_double4(q.x, q.y, q.z, h);
+    const int r0 = __popc(F0 & hbelow());
+    const int r1 = nf0 + __popc(F1 & hbelow());
+    const bool new0 = doit && ((F0 >> hl) & 1u) && r0 < B;
+    const bool new1 = doit && ((F1 >> hl) & 1u) && r1 < B;
+    if (new0) {
+      const int xy = S.elist[r0];
+      const int x = xy & 255, y = xy >> 8;
+      C.t0 = (uint32_t)(x | (y << 8) | (p << 16));
+      intersect3(S.pl[x], S.pl[y], qp, C.v0x, C.v0y, C.v0z);
+      S.E[x * kPlanesP + y] = (uint8_t)hl;
+      S.E[y * kPlanesP + p] = (uint8_t)hl;
+      S.E[p * kPlanesP + x] = (uint8_t)hl;
+    }
+    if (new1) {
+      const int xy = S.elist[r1];
+      const int x = xy & 255, y = xy >> 8;
+      C.t1 = (uint32_t)(x | (y << 8) | (p << 16));
+      intersect3(S.pl[x], S.pl[y], qp, C.v1x, C.v1y, C.v1z);
+      S.E[x * kPlanesP + y] = (uint8_t)(hl + 32);
+      S.E[y * kPlanesP + p] = (uint8_t)(hl + 32);
+      S.E[p * kPlanesP + x] = (uint8_t)(hl + 32);
+    }
+    wave_sync();
+    C.L0w = __ballot(doit ? (kept0 || new0) : live0);
+    C.L1w = __ballot(doit ? (kept1 || new1) : live1);
+    bool refresh = false;
+    if (doit) {
+      stale = true;
+      refresh = ++since == 4;
+    }
+    if (__ballot(refresh)) {
+      const double nb = farthest_bound_pair(C);
+      if (refresh) {
+        C.rmax2 = nb;
+        lim = 2.0 * nb;
+        stale = false;
+        since = 0;
+      }
+    }
+  }
+  if (__ballot(stale)) {
+    const double nb = farthest_bound_pair(C);
+    if (stale) C.rmax2 = nb;
+  }
+  return fail;
+}
+
+// Faces, volume and centroid of each half's finished cell (as finish_cell;
+// each lane integrates planes hl and hl + 32).  Returns 0 or a failure bit.
+__device__ int finish_pair(PairLds& S, const TessArgs& A, const bool act, const int s, const PairRegs& C) {
+  const int hl = hlane();
+  const bool live0 = act && ((hbits(C.L0w) >> hl) & 1u), live1 = act && ((hbits(C.L1w) >> hl) & 1u);
+  wave_sync();
+  S.vx[hl] = C.v0x; S.vy[hl] = C.v0y; S.vz[hl] = C.v0z;
+  S.tri[hl] = C.t0;
+  S.vx[hl + 32] = C.v1x; S.vy[hl + 32] = C.v1y; S.vz[hl + 32] = C.v1z;
+  S.tri[hl + 32] = C.t1;
+  S.first[hl] = kVertsP;
+  if (hl + 32 < kPlanesP) S.first[hl + 32] = kVertsP;
+  wave_sync();
+  if (live0) {
+    atomicMin(&S.first[C.t0 & 255], hl);
+    atomicMin(&S.first[(C.t0 >> 8) & 255], hl);
+    atomicMin(&S.first[(C.t0 >> 16) & 255], hl);
+  }
+  if (live1) {
+    atomicMin(&S.first[C.t1 & 255], hl + 32);
+    atomicMin(&S.first[(C.t1 >> 8) & 255], hl + 32);
+    atomicMin(&S.first[(C.t1 >> 16) & 255], hl + 32);
+  }
+  wave_sync();
+  unsigned long long ul = 0ull;
+  if (live0) ul |= plane_bits(C.t0);
+  if (live1) ul |= plane_bits(C.t1);
+  const unsigned long long usedL = half_or(ul);
+
+  double Af[2] = {0.0, 0.0}, fx[2] = {0.0, 0.0}, fy[2] = {0.0, 0.0}, fz[2] = {0.0, 0.0}, dl[2] = {0.0, 0.0};
+  bool walk_bad = false;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int p = hl + 32 * k;
+    const bool valid = act && p < kPlanesP && ((usedL >> p) & 1ull);
+    if (valid) {
+      const double4 P = S.pl[p];
+      dl[k] = sqrt(2.0 * P.w);
+      const double idl = 1.0 / dl[k];
+      const double nx = P.x * idl, ny = P.y * idl, nz = P.z * idl;
+      const int tstart = S.first[p];
+      const double ox = S.vx[tstart], oy = S.vy[tstart], oz = S.vz[tstart];
+      int t = tstart, it = 0;
+      double as = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+      do {
+        const uint32_t T = S.tri[t];
+        const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
+        const int z = (a == p) ? cq : (bq == p ? a : bq);
+        const int tn = S.E[p * kPlanesP + z] & (kVertsP - 1);
+        const double x1 = S.vx[t] - ox, y1 = S.vy[t] - oy, z1 = S.vz[t] - oz;
+        const double x2 = S.vx[tn] - ox, y2 = S.vy[tn] - oy, z2 = S.vz[tn] - oz;
+        const double ar = 0.5 * ((y1 * z2 - z1 * y2) * nx + (z1 * x2 - x1 * z2) * ny + (x1 * y2 - y1 * x2) * nz);
+        as += ar;
+        mx += ar * (x1 + x2);
+        my += ar * (y1 + y2);
+        mz += ar * (z1 + z2);
+        t = tn;
+        ++it;
+      } while (t != tstart && it < kVertsP);
+      walk_bad |= (t != tstart);
+      Af[k] = as;
+      const double i3a = 1.0 / (3.0 * as);
+      fx[k] = ox + mx * i3a;
+      fy[k] = oy + my * i3a;
+      fz[k] = oz + mz * i3a;
+    }
+  }
+  if (hbits(__ballot(walk_bad))) return F_WALK;
+  bool keep[2];
+  double vol[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    keep[k] = Af[k] > 0.0;   // zero unless a valid plane of an active half
+    vol[k] = keep[k] ? Af[k] * dl[k] / 6.0 : 0.0;
+  }
+  const double V = half_sum(vol[0] + vol[1]);
+  const double iV = 1.0 / V;
+  const double cxr = half_sum((keep[0] ? 0.75 * vol[0] * fx[0] : 0.0) + (keep[1] ? 0.75 * vol[1] * fx[1] : 0.0)) * iV;
+  const double cyr = half_sum((keep[0] ? 0.75 * vol[0] * fy[0] : 0.0) + (keep[1] ? 0.75 * vol[1] * fy[1] : 0.0)) * iV;
+  const double czr = half_sum((keep[0] ? 0.75 * vol[0] * fz[0] : 0.0) + (keep[1] ? 0.75 * vol[1] * fz[1] : 0.0)) * iV;
+  if (act && !(V > 0.0)) return F_VOLUME;
+
+  int jj[2] = {s, s}, code[2] = {13, 13};
+  bool owned[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (keep[k]) {
+      const int pc = S.pcand[hl + 32 * k];
+      if (pc >= 0) {
+        jj[k] = pc >> 5;
+        code[k] = pc & 31;
+      } else {
+        const int bp = -1 - pc;   // box plane: axis bp/2, sign by parity
+        const int step = (bp >> 1) == 0 ? 1 : ((bp >> 1) == 1 ? 3 : 9);
+        code[k] = (bp & 1) ? 13 - step : 13 + step;
+      }
+    }
+    owned[k] = keep[k] && (jj[k] > s || (jj[k] == s && code[k] > 13));
+  }
+  // Faces staged in plane-slot order (planes 0-31 in lane order, then the rest).
+  const unsigned MK0 = hbits(__ballot(keep[0])), MK1 = hbits(__ballot(keep[1]));
+  const unsigned MO0 = hbits(__ballot(owned[0])), MO1 = hbits(__ballot(owned[1]));
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    if (keep[k]) {
+      const int idx = k ? __popc(MK0) + __popc(MK1 & hbelow()) : __popc(MK0 & hbelow());
+      const int orank = k ? __popc(MO0) + __popc(MO1 & hbelow()) : __popc(MO0 & hbelow());
+      StageNbr nb;
+      nb.j = jj[k];
+      nb.meta = code[k] | ((owned[k] ? 1 : 0) << 8) | (orank << 16);
+      A.stage_nb[(int64_t)s * kMaxFaces + idx] = nb;
+      StageGeo& F = A.stage_geo[(int64_t)s * kMaxFaces + idx];
+      F.A = Af[k];
+      F.f[0] = fx[k];
+      F.f[1] = fy[k];
+      F.f[2] = fz[k];
+    }
+  }
+  if (act && hl == 0) {
+    const int nk = __popc(MK0) + __popc(MK1), no = __popc(MO0) + __popc(MO1);
+    A.counts[s] = ((unsigned long long)nk << 32) | (unsigned long long)no;
+    double* gp = A.geo + 4 * (int64_t)s;
+    gp[0] = V;
+    gp[1] = cxr;
+    gp[2] = cyr;
+    gp[3] = czr;
+  }
+  return 0;
+}
+
+// Hands a cell to the one-cell first pass.
+__device__ inline void redo_cell(const TessArgs& A, int s) {
+  A.redo[atomicAdd(&A.st->n_redo, 1)] = s;
+}
+
+// Two cells per wavefront: cells 2w and 2w + 1 of the launch.
+__global__ __launch_bounds__(64) void k_tess_pair(TessArgs A) {
+  __shared__ PairLds lds[2];
+  const int hl = hlane();
+  const int64_t s64 = 2 * xcd_block() + (__lane_id() >> 5);
+  bool act = s64 < A.n;
+  const int s = act ? (int)s64 : 0;
+  PairLds& S = lds[__lane_id() >> 5];
+  const int seg = A.sseg[s];
+  const GridParams& g = A.segs[seg].g;
+  const double r[3] = {A.spos[3 * (int64_t)s], A.spos[3 * (int64_t)s + 1], A.spos[3 * (int64_t)s + 2]};
+  int b[3];
+  double edge[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    b[a] = bucket_coord(r[a], g.inv_hb[a], g.nb[a]);
+    const double t = r[a] - b[a] * g.hb[a];
+    edge[a] = fmax(0.0, fmin(t, g.hb[a] - t));
+  }
+  PairRegs C;
+  init_box_pair(S, g, C);
+  const unsigned cnt = own_count(A, g, b);
+  if (act && cnt > (unsigned)kDense) {
+    // Listed for the dense first pass by the sort (a bucket beyond what the
+    // sort orders fails the call).
+    if (cnt > (unsigned)kDenseMax && hl == 0) {
+      seg_fail(A.st, A.segst, seg, F_DENSE, s);
+      A.counts[s] = 0ull;
+      A.geo[4 * (int64_t)s] = 0.0;
+    }
+    act = false;
+  }
+  const double rloc = cnt > 4u ? g.r_filter * cbrt(4.0 / (double)cnt) : g.r_filter;
+  const int ring = cnt > 4u ? min(g.ring, ring_for(g, edge, rloc * rloc)) : g.ring;
+  double reach = 1e300;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) reach = fmin(reach, ring * g.hb[a] + edge[a]);
+  const double hi2 = fmin(reach * reach, rloc * rloc);
+  int nc = gather_pair(S, A, g, act, s, r, b, ring, hi2);
+  if (act && nc < 0) {
+    if (hl == 0) A.dcells[atomicAdd(&A.st->n_dense_cells, 1)] = s;
+    act = false;
+  }
+  // Few candidates (a thin region) or too many: the one-cell pass.
+  if (act && (nc < kFewCands || nc > kCandsP)) {
+    if (hl == 0) redo_cell(A, s);
+    act = false;
+  }
+  if (!act) nc = 0;
+  sort_pair(S, nc);
+  const int bad = clip_pair(S, nc, C);
+  // A failure here (plane or vertex slots) or candidates that do not reach
+  // twice the farthest vertex: the one-cell pass builds the cell again.
+  if (act && (bad || !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)))) {
+    if (hl == 0) redo_cell(A, s);
+    act = false;
+  }
+  const int bad2 = finish_pair(S, A, act, s, C);
+  if (act && bad2 && hl == 0) {
+    seg_fail(A.st, A.segst, seg, bad2, s);
+    A.counts[s] = 0ull;
+    A.geo[4 * (int64_t)s] = 0.0;
+  }
+}
+
+// The one-cell first pass over the cells the pair pass handed on.
+__global__ __launch_bounds__(64 * kWaves) void k_tess_pass1_redo(TessArgs A) {
+  __shared__ TessLds lds[kWaves];
+  const int w = threadIdx.x >> 6;
+  const int nr = A.st->n_redo;
+  for (int64_t it = (int64_t)blockIdx.x * kWaves + w; it < nr; it += (int64_t)gridDim.x * kWaves)
+    tess_cell<0>(lds[w], A, A.redo[it]);
+}
+
 }  // namespace
 
 void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
                        const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
                        StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
-                       double* rmax2, int32_t* deferred, int32_t* dcells, DevStatus* st_dev, SegStatus* segst,
-                       hipStream_t st) {
+                       double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, DevStatus* st_dev,
+                       SegStatus* segst, hipStream_t st) {
   if (n <= 0) return;
-  TessArgs A{spos,     n,   segs,  sseg,  boff,  sbase,    soffs,  stage_nb, stage_geo,
-             counts,   geo, rmax2, deferred, dcells, st_dev, segst};
-  const unsigned blocks = (unsigned)((n + kWaves - 1) / kWaves);
-  hipLaunchKernelGGL(k_tess_pass1, dim3(blocks), dim3(64 * kWaves), 0, st, A);
-  // The deferred counts are known on the device only: enough blocks for a
-  // large share of the cells, each exits at once when there is none.  Cells
-  // of these lists differ widely in cost, so each block takes few of them
-  // (65536 blocks: the polytropes' cell construction 15% faster than with
-  // 16384; 262144 no faster, and the empty launches cost the Sod tube 1%).
-  const unsigned blocks2 = (unsigned)std::min<int64_t>(blocks, 65536);
+  TessArgs A{spos,     n,   segs,  sseg,  boff,  sbase,    soffs, stage_nb, stage_geo,
+             counts,   geo, rmax2, deferred, dcells, redo, st_dev, segst};
+  hipLaunchKernelGGL(k_tess_pair, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, A);
+  // The handed-on and deferred counts are known on the device only: enough
+  // blocks for a large share of the cells, each exits at once when there is
+  // none.  Cells of these lists differ widely in cost, so each block takes
+  // few of them (65536 blocks: the polytropes' cell construction 15% faster
+  // than with 16384; 262144 no faster, and the empty launches cost the Sod
+  // tube 1%).
+  const unsigned blocks2 = (unsigned)std::min<int64_t>((n + kWaves - 1) / kWaves, 65536);
+  hipLaunchKernelGGL(k_tess_pass1_redo, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
   hipLaunchKernelGGL(k_tess_pass1_dense, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
   hipLaunchKernelGGL(k_tess_pass2, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
 }

@@ -37,7 +37,7 @@ struct Engine {
   hipStream_t stream = nullptr;
   int device = 0;
   // Sort and tessellation.
-  int32_t *key = nullptr, *perm = nullptr, *sseg = nullptr, *deferred = nullptr, *dcells = nullptr;
+  int32_t *key = nullptr, *perm = nullptr, *sseg = nullptr, *deferred = nullptr, *dcells = nullptr, *redo = nullptr;
   double *spos = nullptr, *geo = nullptr, *rmax2 = nullptr, *minv = nullptr;
   unsigned long long *bcount = nullptr, *boff = nullptr, *scan_tmp = nullptr, *counts = nullptr, *off = nullptr;
   unsigned long long* sbase = nullptr;   // sub-table base of each bucket (dense buckets)

@@ -47,7 +47,7 @@ __global__ void k_put_segment(SegDesc d, SegDesc* dst) {
 
 int64_t engine_bytes_per_cell(int precision) {
   const int64_t r = precision == MM_MIXED ? 4 : 8;
-  const int64_t per_cell = 4 * 5                                       // key, perm, sseg, deferred, dcells
+  const int64_t per_cell = 4 * 6                                       // key, perm, sseg, deferred, dcells, redo
                            + 8 * (3 + 4 + 1 + 6 + 1 + 1)               // spos, geo, rmax2, minv, counts, off
                            + 16 + 8 + 4                                // bucket count, offset, sub-table base; sub-offsets
                            + (int64_t)kMaxFaces * (sizeof(StageNbr) + sizeof(StageGeo))
@@ -153,6 +153,7 @@ void reserve_buffers(Engine& E, Res& R, bool single) {
   R(&E.sseg, N);
   R(&E.deferred, N);
   R(&E.dcells, N);
+  R(&E.redo, N);
   R(&E.spos, 3 * N);
   R(&E.geo, 4 * N);
   R(&E.rmax2, N);
@@ -264,7 +265,7 @@ void Engine::release() {
     *this = Engine();
     return;
   }
-  void* ptrs[] = {key, perm, sseg, deferred, dcells, spos, geo, rmax2, minv, bcount, boff, sbase, soffs, scan_tmp, counts, off, sw, soff,
+  void* ptrs[] = {key, perm, sseg, deferred, dcells, redo, spos, geo, rmax2, minv, bcount, boff, sbase, soffs, scan_tmp, counts, off, sw, soff,
                   stage_nb, stage_geo, faces, csr, nbr, U, G, Uh, rec, phi, w, Qs, pn, pos_half, Uh_slots,
                   Xe, Xh, recx, phiX, machF, machs, Ss, segs, segst, st};
   for (void* q : ptrs)
@@ -312,7 +313,7 @@ void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int3
               sseg, spos, dcells, st, segst, stream);
   mark(1);
   launch_tessellate(spos, n_cells, segs, sseg, boff, sbase, soffs, stage_nb, stage_geo, counts, geo, rmax2, deferred,
-                    dcells, st, segst, stream);
+                    dcells, redo, st, segst, stream);
   mark(2);
   scan_u64(counts, off, n_cells, scan_tmp, stream);
   launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, sw, soff, scan_tmp, fcap,

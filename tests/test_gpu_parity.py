@@ -48,6 +48,25 @@ def test_tessellation_parity(orc, name, make):
     assert info["n_faces"] * 2 == len(om.j)
 
 
+@pytest.mark.parametrize("hole", [1.0, 1.7], ids=["candidate_overflow", "slot_overflow"])
+def test_crowded_site_cells_are_handed_on(orc, hole):
+    """Cells that the two-cells-per-wavefront first pass cannot hold are built
+    again by the one-cell first pass.  Around the crowded site with the small
+    hole, the shell and its neighbours see more than 48 candidates; with the
+    large hole the centre sees 36, and its 36 faces (68 vertices) need more
+    plane and vertex slots than a half-wavefront keeps, so it is handed on in
+    the middle of its cuts.  Either way the tessellation matches the
+    oracle's."""
+    pos = W.crowded_site(hole=hole)
+    _print_case("crowded site", hole=hole, n=pos.shape[0])
+    mm, info, om = mesh_pair(orc, pos, (1, 1, 1))
+    assert om.status == 0
+    assert om.delta_min > 1e-12, "input not certified non-degenerate"
+    assert int(np.diff(om.off)[pos.shape[0] - 37]) == 36
+    compare_mesh(mm, om)
+    assert info["rebuilt_cells"] > 0 and info["n_faces"] * 2 == len(om.j)
+
+
 def test_bcc_closed_form_on_gpu():
     # Exact body-centred cubic lattice: every cell is the truncated
     # octahedron (volume a^3/2, 6 squares a^2/8, 8 hexagons 3 sqrt(3) a^2/16,

@@ -96,6 +96,31 @@ def poisson_points(n, box, seed=0) -> np.ndarray:
     return _wrap_inside(rng.uniform(0.0, 1.0, size=(int(n), 3)) * L, box)
 
 
+def crowded_site(m=16, n_shell=36, seed=9, r_lo=0.28, r_hi=0.34, hole=1.0) -> np.ndarray:
+    """Jittered m^3 lattice in the unit box with a crowded site at the box
+    centre (a corner shared by eight lattice cells): the lattice points
+    closer than `hole` spacings to it are removed, and a point near the
+    centre is surrounded by n_shell points on a rough sphere (spiral
+    directions, radii uniform in [r_lo, r_hi] spacings, all jittered so no
+    five points are cospherical).  The centre's cell has about n_shell
+    faces; the points spread over the eight lattice cells around the centre,
+    a handful each.  Point order: the lattice (x fastest), then the centre,
+    then the shell."""
+    h = 1.0 / m
+    rng = np.random.default_rng(seed)
+    lat = jittered_lattice((m, m, m), (1.0, 1.0, 1.0), seed=seed)
+    c = np.full(3, 0.5)
+    lat = lat[np.linalg.norm(lat - c, axis=1) >= hole * h]
+    k = np.arange(n_shell) + 0.5
+    phi = np.arccos(1.0 - 2.0 * k / n_shell) + rng.uniform(-0.05, 0.05, n_shell)
+    th = np.pi * (1.0 + 5.0 ** 0.5) * k + rng.uniform(-0.05, 0.05, n_shell)
+    d = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
+    r = rng.uniform(r_lo, r_hi, n_shell) * h
+    centre = c + rng.uniform(-0.01, 0.01, 3) * h
+    shell = centre + d * r[:, None]
+    return _wrap_inside(np.concatenate([lat, centre[None, :], shell]), (1.0, 1.0, 1.0))
+
+
 def bcc_lattice(m, box=(1.0, 1.0, 1.0), offset=0.25) -> np.ndarray:
     """Body-centred cubic lattice: m^3 cube corners plus m^3 body centres
     (2 m^3 points), cubic side a = L/m.  `offset` (in units of a) shifts the
