@@ -96,6 +96,16 @@ def parse():
     return ap.parse_args()
 
 
+def copy_calibration(torch):
+    """One 512 MiB device-to-device copy: under a counter run, the scale of
+    FETCH_SIZE and WRITE_SIZE against bytes known to move."""
+    a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -678,7 +688,10 @@ def main():
 
     torch.cuda.set_device(0)
     if args.only_polytropes:
-        print(json.dumps({"polytropes": polytropes_object(M, torch, args)}))
+        obj = polytropes_object(M, torch, args)
+        if args.copy_calibration:
+            copy_calibration(torch)
+        print(json.dumps({"polytropes": obj}))
         return
     wl = make_workload(args.workload)
     n = wl.n
@@ -693,11 +706,7 @@ def main():
     log(f"device copy {copy_gbs:.0f} GB/s")
 
     if args.copy_calibration:
-        a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        copy_calibration(torch)
 
     # Dominant kernel: cell construction (FP64 ALU bound).
     t_cells = stage_ms["cells"] * 1e-3
