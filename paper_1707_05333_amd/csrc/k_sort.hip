@@ -364,7 +364,7 @@ void launch_sort(const double* pos, int64_t n_slots, const int32_t* slot_seg, in
                  unsigned long long* sbase, uint32_t* soffs, int32_t* key, int32_t* perm, int32_t* sseg,
                  double* spos, int32_t* dcells, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
   launch_fill_u64(bcount, 0ull, nbt, st);
-  launch_fill_i32(&st_dev->n_dense, 0, 3, st);   // n_dense, n_dense_cells and n_redo
+  launch_fill_i32(&st_dev->n_dense, 0, 4, st);   // n_dense, n_dense_cells, n_redo and n_dredo
   hipLaunchKernelGGL(k_hash, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, pos, n_slots, slot_seg, segs, key,
                      bcount, st_dev, segst);
   scan_u64(bcount, boff, nbt, scan_tmp, st);

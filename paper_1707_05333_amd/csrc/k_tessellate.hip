@@ -89,6 +89,7 @@ struct TessArgs {
   int32_t* deferred;
   int32_t* dcells;                   // cells for the dense first pass
   int32_t* redo;                     // cells the two-cell first pass hands to the one-cell one
+  int64_t dense_cap;                 // listed dense cells the two-cell dense pass takes (even)
   DevStatus* st;
   SegStatus* segst;
 };
@@ -1152,15 +1153,16 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
 
 // Four waves per SIMD, with some values of the two-level gather and the
 // extra shells spilled (at three, without spills, it is slower).
-// The listed cells: those of the dense buckets (listed by the sort) and
-// those the first pass met a dense bucket for.
+// The cells of dense regions that the two-cell dense pass handed on, then
+// the listed ones beyond its grid.
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_tess_pass1_dense(
     TessArgs A) {
   __shared__ TessLds lds[kWaves];
   const int w = threadIdx.x >> 6;
-  const int nd = A.st->n_dense_cells;
-  for (int64_t it = (int64_t)blockIdx.x * kWaves + w; it < nd; it += (int64_t)gridDim.x * kWaves)
-    tess_cell<1>(lds[w], A, A.dcells[it]);
+  const int64_t nr = A.st->n_dredo;
+  const int64_t nx = max((int64_t)0, (int64_t)A.st->n_dense_cells - A.dense_cap);
+  for (int64_t it = (int64_t)blockIdx.x * kWaves + w; it < nr + nx; it += (int64_t)gridDim.x * kWaves)
+    tess_cell<1>(lds[w], A, it < nr ? A.redo[it] : A.dcells[A.dense_cap + (it - nr)]);
 }
 
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))) void k_tess_pass2(TessArgs A) {
@@ -1328,16 +1330,23 @@ __device__ inline double farthest_bound_pair(const PairRegs& C) {
   return half_max_bound(m2);
 }
 
-// The first gather of the plain path for both halves: images with
-// |d|^2 < hi2 from each half's stencil of half-width `ring`, four stencil
-// buckets per lane at a time (the usual 125-bucket stencil in one memory
-// round trip, as in the one-cell gather).  Returns this half's candidate
-// count, -1 when its stencil holds a dense bucket, or kCandsP + 1 on
-// overflow.  Called by the whole wavefront (act: the half has a cell).
+// The gather of both halves: images with lo2 <= |d|^2 < hi2 from each
+// half's stencil of half-width `ring`, four stencil buckets per lane at a time (the
+// usual 125-bucket stencil in one memory round trip, as in the one-cell
+// gather).  Returns this half's candidate count, or kCandsP + 1 on overflow.
+// Without RUNS (the lean pass) a stencil that holds a dense bucket gives -1;
+// with RUNS a chunk of the stencil that holds one, in either half, is taken
+// by the two-level gather of both halves.  Called by the whole wavefront
+// (act: the half has a cell).
 constexpr int kPairBuckets = 4;
 
+__device__ int gather_runs_pair(PairLds& S, const TessArgs& A, const GridParams& g, const int s, const double r[3],
+                                const int b[3], const int ring, const int chunk, const int W3, const WidthDiv& D,
+                                const double lo2, const double hi2, int nc);
+
+template <bool RUNS>
 __device__ int gather_pair(PairLds& S, const TessArgs& A, const GridParams& g, bool act, const int s,
-                           const double r[3], const int b[3], const int ring, const double hi2) {
+                           const double r[3], const int b[3], const int ring, const double lo2, const double hi2) {
   const int hl = hlane();
   const int W = 2 * ring + 1, W3 = act ? W * W * W : 0;
   const WidthDiv D = width_div((unsigned)W);
@@ -1352,7 +1361,14 @@ __device__ int gather_pair(PairLds& S, const TessArgs& A, const GridParams& g, b
       B[u] = stencil_bucket(A, g, b, ring, chunk + 32 * u + hl, W3, D);
       dn |= B[u].cnt > kDense;
     }
-    dense |= hbits(__ballot(dn)) != 0u;
+    if constexpr (RUNS) {
+      if (__ballot(dn)) {
+        nc = gather_runs_pair(S, A, g, s, r, b, ring, chunk, W3, D, lo2, hi2, nc);
+        continue;
+      }
+    } else {
+      dense |= hbits(__ballot(dn)) != 0u;
+    }
     int cmax = 0;
 #pragma unroll
     for (int u = 0; u < kPairBuckets; ++u) {
@@ -1377,7 +1393,7 @@ __device__ int gather_pair(PairLds& S, const TessArgs& A, const GridParams& g, b
         dy[u] = (y + B[u].sy) - r[1];
         dz[u] = (z + B[u].sz) - r[2];
         d2[u] = dx[u] * dx[u] + dy[u] * dy[u] + dz[u] * dz[u];
-        keep[u] = v && d2[u] < hi2;
+        keep[u] = v && d2[u] >= lo2 && d2[u] < hi2;
       }
 #pragma unroll
       for (int u = 0; u < kPairBuckets; ++u) {
@@ -1396,6 +1412,111 @@ __device__ int gather_pair(PairLds& S, const TessArgs& A, const GridParams& g, b
   wave_sync();
   if (dense) return -1;
   return nc > kCandsP ? kCandsP + 1 : nc;
+}
+
+// The two-level gather of one chunk of 128 stencil buckets per half (as
+// gather_runs, with 32 lanes per cell): each bucket that meets the box
+// around the query sphere contributes runs of consecutive points, a sparse
+// bucket its whole range and a dense one the part of each sub-bucket row
+// inside the box; each half takes its runs 32 at a time, a lane finding the
+// bucket of its run by a binary search over the half's run prefix sums.
+// The per-point test is the plain path's, so the candidates are the same.
+__device__ int gather_runs_pair(PairLds& S, const TessArgs& A, const GridParams& g, const int s, const double r[3],
+                                const int b[3], const int ring, const int chunk, const int W3, const WidthDiv& D,
+                                const double lo2, const double hi2, int nc) {
+  const int hl = hlane();
+  const int h0 = __lane_id() & 32;   // first lane of this half
+  const double rq = sqrt(hi2) * (1.0 + 1e-9) + 1e-9 * fmin(g.hb[0], fmin(g.hb[1], g.hb[2]));
+  for (int u = 0; u < kPairBuckets; ++u) {
+    int bb[3] = {0, 0, 0};
+    int64_t key = 0;
+    const StencilBucket B = stencil_bucket(A, g, b, ring, chunk + 32 * u + hl, W3, D, bb, &key);
+    int nr = 0, pack = 0, base = 0;
+    if (B.cnt > 0) {
+      const double sh[3] = {B.sx, B.sy, B.sz};
+      double qlo[3], qhi[3];
+      bool meet = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        qlo[a] = (r[a] - rq) - sh[a];
+        qhi[a] = (r[a] + rq) - sh[a];
+        const double tlo = qlo[a] * g.inv_hb[a], thi = qhi[a] * g.inv_hb[a];
+        if (thi < (double)bb[a] || (tlo >= (double)(bb[a] + 1) && bb[a] < g.nb[a] - 1)) meet = false;
+      }
+      if (meet) {
+        if (B.cnt <= kDense || B.cnt > kDenseMax) {
+          nr = 1;
+        } else {
+          const int ss = sub_size((unsigned)B.cnt);
+          int l[3], m[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            l[a] = sub_coord(qlo[a], g.inv_hb[a], bb[a], ss);
+            m[a] = sub_coord(qhi[a], g.inv_hb[a], bb[a], ss) - l[a] + 1;
+          }
+          nr = m[1] * m[2];
+          pack = ss | l[0] << 5 | m[0] << 10 | l[1] << 15 | m[1] << 20 | l[2] << 25;
+          base = (int)A.sbase[key];
+        }
+      }
+    }
+    int total;
+    const int excl = half_excl_scan_small<15>(nr, &total);
+    const int tmax = (int)wave_umax32((unsigned)total);
+    for (int t0 = 0; t0 < tmax; t0 += 32) {
+      const int t = t0 + hl;
+      // the last lane of the half whose runs start at or before t
+      int ow = 0;
+#pragma unroll
+      for (int step = 16; step > 0; step >>= 1) {
+        const int e = __shfl(excl, h0 + ow + step, 64);
+        if (e <= t) ow += step;
+      }
+      const int src = h0 + ow;
+      const int e_o = __shfl(excl, src, 64);
+      const int bst_o = __shfl(B.bst, src, 64), cnt_o = __shfl(B.cnt, src, 64), code_o = __shfl(B.code, src, 64);
+      const int pack_o = __shfl(pack, src, 64), base_o = __shfl(base, src, 64);
+      int kx, ky, kz;
+      decode(code_o, kx, ky, kz);
+      const double sx = kx * g.L[0], sy = ky * g.L[1], sz = kz * g.L[2];
+      int start = bst_o, count = t < total ? cnt_o : 0;
+      if (pack_o != 0 && t < total) {
+        const int ss = pack_o & 31, x0 = (pack_o >> 5) & 31, nx = (pack_o >> 10) & 31;
+        const int y0 = (pack_o >> 15) & 31, ny = (pack_o >> 20) & 31, z0 = (pack_o >> 25) & 31;
+        const int jr = t - e_o;
+        const int ry = y0 + jr % ny, rz = z0 + jr / ny;
+        const int ri = (rz * ss + ry) * ss + x0;
+        const uint32_t* so = A.soffs + base_o;
+        const int a0 = (int)so[ri], a1 = (int)so[ri + nx];
+        start = bst_o + a0;
+        count = a1 - a0;
+      }
+      const int maxc = (int)wave_umax32((unsigned)count);
+      for (int k = 0; k < maxc; ++k) {
+        const int j = start + k;
+        const bool v = k < count && j != s;
+        double x = 0, y = 0, z = 0;
+        if (v) {
+          x = A.spos[3 * (int64_t)j];
+          y = A.spos[3 * (int64_t)j + 1];
+          z = A.spos[3 * (int64_t)j + 2];
+        }
+        const double dx = (x + sx) - r[0], dy = (y + sy) - r[1], dz = (z + sz) - r[2];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const bool keep = v && d2 >= lo2 && d2 < hi2;
+        const unsigned mk = hbits(__ballot(keep));
+        if (keep) {
+          const int idx = nc + __popc(mk & hbelow());
+          if (idx < kCandsP) {
+            S.cd[idx] = make_double4(dx, dy, dz, 0.5 * d2);
+            S.cjk[idx] = (j << 5) | code_o;
+          }
+        }
+        nc += __popc(mk);
+      }
+    }
+  }
+  return nc;
 }
 
 // Candidates of each half ordered by distance, ties by neighbour and image
@@ -1716,34 +1837,49 @@ __device__ int finish_pair(PairLds& S, const TessArgs& A, const bool act, const 
   return 0;
 }
 
-// Hands a cell to the one-cell first pass.
-__device__ inline void redo_cell(const TessArgs& A, int s) {
-  A.redo[atomicAdd(&A.st->n_redo, 1)] = s;
-}
-
-// Two cells per wavefront: cells 2w and 2w + 1 of the launch.
-__global__ __launch_bounds__(64) void k_tess_pair(TessArgs A) {
-  __shared__ PairLds lds[2];
-  const int hl = hlane();
-  const int64_t s64 = 2 * xcd_block() + (__lane_id() >> 5);
-  bool act = s64 < A.n;
-  const int s = act ? (int)s64 : 0;
-  PairLds& S = lds[__lane_id() >> 5];
-  const int seg = A.sseg[s];
-  const GridParams& g = A.segs[seg].g;
-  const double r[3] = {A.spos[3 * (int64_t)s], A.spos[3 * (int64_t)s + 1], A.spos[3 * (int64_t)s + 2]};
+// Generator s: its position, bucket, and distance to its bucket's nearer
+// wall per axis.
+struct CellGeom {
+  double r[3], edge[3];
   int b[3];
-  double edge[3];
+};
+
+__device__ inline void cell_geom(const TessArgs& A, const GridParams& g, const int s, CellGeom& G) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    b[a] = bucket_coord(r[a], g.inv_hb[a], g.nb[a]);
-    const double t = r[a] - b[a] * g.hb[a];
-    edge[a] = fmax(0.0, fmin(t, g.hb[a] - t));
+    G.r[a] = A.spos[3 * (int64_t)s + a];
+    G.b[a] = bucket_coord(G.r[a], g.inv_hb[a], g.nb[a]);
+    const double t = G.r[a] - G.b[a] * g.hb[a];
+    G.edge[a] = fmax(0.0, fmin(t, g.hb[a] - t));
   }
+}
+
+// Hands a cell to the one-cell first pass of its kind (lean or dense).
+template <bool DENSE>
+__device__ inline void redo_cell(const TessArgs& A, int s) {
+  A.redo[atomicAdd(DENSE ? &A.st->n_dredo : &A.st->n_redo, 1)] = s;
+}
+
+// One cell per half of the wavefront (act: the half has a cell, s).
+// DENSE = false: the lean first pass over every cell; cells of dense
+// buckets are left to the dense passes (listed by the sort), and a cell
+// whose stencil holds a dense bucket is listed for them.  DENSE = true: the
+// cells of those lists, with the two-level gather.  Either way a cell the
+// half cannot finish is handed to the one-cell pass of its kind.
+template <bool DENSE>
+__device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) {
+  const int hl = hlane();
+  const int seg = A.sseg[s];
+  const GridParams& g = A.segs[seg].g;
+  CellGeom G;
+  cell_geom(A, g, s, G);
+  const double* r = G.r;
+  const int* b = G.b;
+  const double* edge = G.edge;
   PairRegs C;
   init_box_pair(S, g, C);
   const unsigned cnt = own_count(A, g, b);
-  if (act && cnt > (unsigned)kDense) {
+  if (!DENSE && act && cnt > (unsigned)kDense) {
     // Listed for the dense first pass by the sort (a bucket beyond what the
     // sort orders fails the call).
     if (cnt > (unsigned)kDenseMax && hl == 0) {
@@ -1753,30 +1889,75 @@ __global__ __launch_bounds__(64) void k_tess_pair(TessArgs A) {
     }
     act = false;
   }
-  const double rloc = cnt > 4u ? g.r_filter * cbrt(4.0 / (double)cnt) : g.r_filter;
-  const int ring = cnt > 4u ? min(g.ring, ring_for(g, edge, rloc * rloc)) : g.ring;
+  const double rloc =
+      cnt > 4u ? g.r_filter * cbrt((cnt > (unsigned)kDense ? g.ppb : 4.0) / (double)cnt) : g.r_filter;
+  int ring = cnt > 4u ? min(g.ring, ring_for(g, edge, rloc * rloc)) : g.ring;
   double reach = 1e300;
 #pragma unroll
   for (int a = 0; a < 3; ++a) reach = fmin(reach, ring * g.hb[a] + edge[a]);
-  const double hi2 = fmin(reach * reach, rloc * rloc);
-  int nc = gather_pair(S, A, g, act, s, r, b, ring, hi2);
-  if (act && nc < 0) {
-    if (hl == 0) A.dcells[atomicAdd(&A.st->n_dense_cells, 1)] = s;
-    act = false;
-  }
-  // Few candidates (a thin region) or too many: the one-cell pass.
-  if (act && (nc < kFewCands || nc > kCandsP)) {
-    if (hl == 0) redo_cell(A, s);
-    act = false;
-  }
-  if (!act) nc = 0;
-  sort_pair(S, nc);
-  const int bad = clip_pair(S, nc, C);
-  // A failure here (plane or vertex slots) or candidates that do not reach
-  // twice the farthest vertex: the one-cell pass builds the cell again.
-  if (act && (bad || !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)))) {
-    if (hl == 0) redo_cell(A, s);
-    act = false;
+  double lo2 = 0.0, hi2 = fmin(reach * reach, rloc * rloc);
+  // The first radius, then (dense pass, for a cell whose candidates do not
+  // reach twice its farthest vertex) up to kShells1 more distance shells, as
+  // in the one-cell passes: irregular inputs need one often.  A cell still
+  // short, or whose shell needs a wider stencil than the grid has, is handed
+  // on.
+  // work: the half gathers and cuts in this round (a half whose cell is
+  // complete takes no further candidates: cutting a cell again by planes it
+  // already has can split, by rounding, the vertices that lie on them).
+  bool work = act;
+  for (int shell = 0;; ++shell) {
+    int nc = gather_pair<DENSE>(S, A, g, work, s, r, b, ring, lo2, hi2);
+    if (!DENSE && work && nc < 0) {
+      if (hl == 0) A.dcells[atomicAdd(&A.st->n_dense_cells, 1)] = s;
+      act = work = false;
+    }
+    // More candidates than slots (a compressed region): gather again with
+    // the radius that holds about 38 of them at the density found (the
+    // cell is the same at any radius; only the work changes).
+    const bool over = work && nc > kCandsP;
+    if (__ballot(over)) {
+      if (over) {
+        const double f = cbrt(38.0 / (double)nc);
+        hi2 = lo2 + (hi2 - lo2) * (f * f);
+      }
+      const int nc2 = gather_pair<DENSE>(S, A, g, over, s, r, b, ring, lo2, hi2);
+      if (over) nc = nc2;
+    }
+    // Too many candidates, or (lean pass, first radius) few: a thin region,
+    // whose radius the one-cell pass widens.
+    if (work && (nc > kCandsP || (!DENSE && shell == 0 && nc < kFewCands))) {
+      if (hl == 0) redo_cell<DENSE>(A, s);
+      act = work = false;
+    }
+    if (!work) nc = 0;
+    sort_pair(S, nc);
+    // A failure (plane or vertex slots): the one-cell pass builds the cell
+    // again.
+    if (clip_pair(S, nc, C) && work) {
+      if (hl == 0) redo_cell<DENSE>(A, s);
+      act = work = false;
+    }
+    bool go = work && !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12));
+    if constexpr (!DENSE) {
+      // (The lean pass hands such a cell on: the shells' loop would cost it
+      // a wave per SIMD, and on uniform inputs no cell needs one.)
+      if (go && hl == 0) redo_cell<DENSE>(A, s);
+      if (go) act = false;
+      break;
+    }
+    if (__ballot(go) == 0ull) break;
+    if (go) {
+      const double nhi2 = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
+      ring = ring_for(g, edge, nhi2);
+      if (shell == kShells1 || ring > g.nb[0] || ring > g.nb[1] || ring > g.nb[2]) {
+        if (hl == 0) redo_cell<DENSE>(A, s);
+        act = go = false;
+      } else {
+        lo2 = hi2;
+        hi2 = nhi2;
+      }
+    }
+    work = go;
   }
   const int bad2 = finish_pair(S, A, act, s, C);
   if (act && bad2 && hl == 0) {
@@ -1784,6 +1965,42 @@ __global__ __launch_bounds__(64) void k_tess_pair(TessArgs A) {
     A.counts[s] = 0ull;
     A.geo[4 * (int64_t)s] = 0.0;
   }
+}
+
+// Two cells per wavefront: cells 2w and 2w + 1 of the launch.
+__global__ __launch_bounds__(64) void k_tess_pair(TessArgs A) {
+  __shared__ PairLds lds[2];
+  const int64_t s64 = 2 * xcd_block() + (__lane_id() >> 5);
+  const bool act = s64 < A.n;
+  pair_cell<false>(lds[__lane_id() >> 5], A, act, act ? (int)s64 : 0);
+}
+
+// The listed cells of dense regions, two per wavefront: those of the dense
+// buckets (listed by the sort) and those the first passes met a dense
+// bucket for.  The list's length is known on the device only; the grid is
+// sized by the host from the last tessellation's length (with a margin),
+// the blocks beyond the list exit at once, and listed cells beyond the
+// grid (dense_cap) go to the one-cell dense pass.  The
+// blocks with work are spread evenly over the XCDs, each XCD taking one
+// contiguous share of the list (a bucket's cells are listed together and
+// share their neighbours).  One pair per one-wavefront block: a loop over
+// pairs holds about 50 more registers (polytropes 19% slower), and blocks of
+// two or four waves hold their LDS until the slowest wave ends (3% and 5%
+// slower).  Four waves per SIMD, with some registers spilled (at two,
+// without spills, or three the polytropes' dense cells take 30% or 7%
+// longer).
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_tess_pair_dense(TessArgs A) {
+  __shared__ PairLds lds[2];
+  const int64_t nd = min((int64_t)A.st->n_dense_cells, A.dense_cap);
+  const int64_t npair = (nd + 1) / 2;
+  const int64_t per = (npair + kXcds - 1) / kXcds;   // pairs per XCD
+  const int64_t k = blockIdx.x / kXcds;
+  if (k >= per) return;
+  const int64_t it = (blockIdx.x % kXcds) * per + k;
+  if (it >= npair) return;
+  const int64_t q = 2 * it + (__lane_id() >> 5);
+  const bool act = q < nd;
+  pair_cell<true>(lds[__lane_id() >> 5], A, act, A.dcells[act ? q : 2 * it]);
 }
 
 // The one-cell first pass over the cells the pair pass handed on.
@@ -1800,11 +2017,15 @@ __global__ __launch_bounds__(64 * kWaves) void k_tess_pass1_redo(TessArgs A) {
 void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
                        const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
                        StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
-                       double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, DevStatus* st_dev,
-                       SegStatus* segst, hipStream_t st) {
+                       double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, int64_t dense_hint,
+                       DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
   if (n <= 0) return;
-  TessArgs A{spos,     n,   segs,  sseg,  boff,  sbase,    soffs, stage_nb, stage_geo,
-             counts,   geo, rmax2, deferred, dcells, redo, st_dev, segst};
+  // Grid of the two-cell dense pass: the last tessellation's dense-list
+  // length and a quarter more (all cells when there is none yet).
+  const int64_t want = dense_hint < 0 ? n : std::min<int64_t>(n, dense_hint + dense_hint / 4 + 256);
+  const int64_t dense_cap = (want + 1) / 2 * 2;
+  TessArgs A{spos,   n,     segs,     sseg,   boff,      sbase,  soffs, stage_nb, stage_geo, counts,
+             geo,    rmax2, deferred, dcells, redo,      dense_cap, st_dev, segst};
   hipLaunchKernelGGL(k_tess_pair, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, A);
   // The handed-on and deferred counts are known on the device only: enough
   // blocks for a large share of the cells, each exits at once when there is
@@ -1814,6 +2035,9 @@ void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const
   // tube 1%).
   const unsigned blocks2 = (unsigned)std::min<int64_t>((n + kWaves - 1) / kWaves, 65536);
   hipLaunchKernelGGL(k_tess_pass1_redo, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
+  // (The hand-off list of the lean pass has been read: the dense passes'
+  // hand-offs reuse it.)
+  hipLaunchKernelGGL(k_tess_pair_dense, dim3((unsigned)(dense_cap / 2 + kXcds)), dim3(64), 0, st, A);
   hipLaunchKernelGGL(k_tess_pass1_dense, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
   hipLaunchKernelGGL(k_tess_pass2, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
 }

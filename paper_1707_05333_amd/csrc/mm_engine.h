@@ -75,6 +75,9 @@ struct Engine {
   int nseg = 0;
   // Mesh currently held.
   int64_t n = 0, n_faces = 0, nbt = 0;
+  // Dense-list length of the last tessellation read back (-1: none yet); it
+  // sizes the two-cell dense pass's grid only.
+  int64_t dense_hint = -1;
   // First-pass candidate radius in mean spacings.  It changes only the
   // work, never the cells (clipping is always in order of distance, ties
   // broken by neighbour and image).  With the first pass taking up to three

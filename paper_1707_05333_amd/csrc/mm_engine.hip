@@ -313,7 +313,7 @@ void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int3
               sseg, spos, dcells, st, segst, stream);
   mark(1);
   launch_tessellate(spos, n_cells, segs, sseg, boff, sbase, soffs, stage_nb, stage_geo, counts, geo, rmax2, deferred,
-                    dcells, redo, st, segst, stream);
+                    dcells, redo, dense_hint, st, segst, stream);
   mark(2);
   scan_u64(counts, off, n_cells, scan_tmp, stream);
   launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, sw, soff, scan_tmp, fcap,
@@ -395,6 +395,7 @@ mm_status Engine::readback() {
     e = hipMemcpyAsync(segst_host, segst, sizeof(SegStatus) * nseg, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return fail(MM_EHIP, std::string("status readback: ") + hipGetErrorString(e));
+  dense_hint = st_host->n_dense_cells;
   return MM_OK;
 }
 

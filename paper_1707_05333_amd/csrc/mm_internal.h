@@ -51,6 +51,7 @@ struct DevStatus {
   int n_dense;                   // buckets with a sub-grid (length of the sort's dense-bucket list)
   int n_dense_cells;             // cells for the dense first pass (follows n_dense: cleared together)
   int n_redo;                    // cells the two-cell first pass hands to the one-cell one (cleared with n_dense)
+  int n_dredo;                   // cells the two-cell dense pass hands to the one-cell one (cleared with n_dense)
   unsigned long long n_faces;    // unique faces (copy of the scan total)
   unsigned long long n_csr;      // directed faces (copy of the scan total)
   int asym_cell, asym_nbr;       // one face without a partner (internal cells), for diagnostics
@@ -270,12 +271,14 @@ void launch_sort(const double* pos, int64_t n_slots, const int32_t* slot_seg, in
                  unsigned long long* sbase, uint32_t* soffs, int32_t* key, int32_t* perm, int32_t* sseg,
                  double* spos, int32_t* dcells, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
-// Tessellation: pass 1 over every cell, then the deferred cells.
+// Tessellation: pass 1 over every cell, then the listed and deferred cells.
+// dense_hint: the dense-list length of an earlier tessellation (-1: none),
+// which sizes the grid of the two-cell dense pass (never its results).
 void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
                        const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
                        StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
-                       double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, DevStatus* st_dev,
-                       SegStatus* segst, hipStream_t st);
+                       double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, int64_t dense_hint,
+                       DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
 // Per-cell lists (face ids with sign, neighbour entries) use a sliced ELL
 // layout: slices of 64 consecutive internal cells, each as wide as its

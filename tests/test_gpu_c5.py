@@ -46,6 +46,28 @@ def test_c5_small_tessellation_parity(orc, c5_small):
     assert info["n_faces"] * 2 == len(om.j)
 
 
+def test_dense_cells_beyond_the_sized_grid(orc, c5_small):
+    """The two-cells-per-wavefront dense pass launches as many wavefronts as
+    the previous tessellation listed dense cells (and a quarter more); listed
+    cells beyond that go to the one-cell dense pass.  A context that first
+    tessellates uniform random points (no dense cell, so the next grid is
+    small) and then the polytropes (thousands of dense cells) builds the
+    polytropes' tessellation exactly as the oracle does."""
+    import paper_1707_05333_amd as M
+    wl = c5_small
+    _case("dense cells beyond the sized grid", n=wl.n)
+    mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, **wl.params))
+    mm.tessellate(dev(W.poisson_points(wl.n, wl.box, seed=11)))
+    info = mm.tessellate(dev(wl.pos))
+    om = orc.tessellate(wl.pos, wl.box, certificate=True)
+    assert om.status == 0 and om.delta_min > 1e-12
+    compare_mesh(mm, om)
+    assert info["n_faces"] * 2 == len(om.j)
+    # and the next call, sized from this one, as well
+    info = mm.tessellate(dev(wl.pos))
+    compare_mesh(mm, om)
+
+
 def _oracle_run(orc, wl, nsteps):
     p = orc.make_params(wl.box, **wl.params)
     om = orc.tessellate(wl.pos, wl.box)
