@@ -1939,10 +1939,52 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
     }
     bool go = work && !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12));
     if constexpr (!DENSE) {
-      // (The lean pass hands such a cell on: the shells' loop would cost it
-      // a wave per SIMD, and on uniform inputs no cell needs one.)
-      if (go && hl == 0) redo_cell<DENSE>(A, s);
-      if (go) act = false;
+      // One more shell here (the one-cell passes take up to kShells1); a
+      // cell still short is handed on.  The generator's geometry and the
+      // LDS address are taken afresh, opaque to the compiler, so that
+      // nothing derived from them stays live across the first cuts: the
+      // pass keeps 128 VGPRs and 4 waves per SIMD (146 otherwise), and a
+      // loop over shells would hold more.
+      if (__ballot(go)) {
+        int s2 = s;
+        asm volatile("" : "+v"(s2));
+        PairLds* Sp = &S;
+        asm volatile("" : "+v"(Sp));
+        PairLds& S2 = *Sp;
+        const GridParams& g2 = A.segs[A.sseg[s2]].g;
+        CellGeom G2;
+        cell_geom(A, g2, s2, G2);
+        int ring2 = 0;
+        if (go) {
+          const double nhi2 = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
+          ring2 = ring_for(g2, G2.edge, nhi2);
+          if (ring2 > g2.nb[0] || ring2 > g2.nb[1] || ring2 > g2.nb[2]) {
+            if (hl == 0) redo_cell<DENSE>(A, s);
+            act = go = false;
+          } else {
+            lo2 = hi2;
+            hi2 = nhi2;
+          }
+        }
+        int nc2 = gather_pair<DENSE>(S2, A, g2, go, s2, G2.r, G2.b, ring2, lo2, hi2);
+        if (go && (nc2 < 0 || nc2 > kCandsP)) {
+          if (hl == 0) {
+            if (nc2 < 0) A.dcells[atomicAdd(&A.st->n_dense_cells, 1)] = s;
+            else redo_cell<DENSE>(A, s);
+          }
+          act = go = false;
+        }
+        if (!go) nc2 = 0;
+        sort_pair(S2, nc2);
+        if (clip_pair(S2, nc2, C) && go) {
+          if (hl == 0) redo_cell<DENSE>(A, s);
+          act = go = false;
+        }
+        if (go && !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12))) {
+          if (hl == 0) redo_cell<DENSE>(A, s);
+          act = false;
+        }
+      }
       break;
     }
     if (__ballot(go) == 0ull) break;
