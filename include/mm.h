@@ -106,9 +106,9 @@ typedef struct {
   int64_t floor_hits[4];     /* floors fired: [0] cell states at the start, [1] half-step states,
                                 [2] face states, [3] charges after the update (Sec. 4.1) */
   int32_t flags;             /* internal failure bits (0 when the step succeeded) */
-  int32_t rebuilt_cells;     /* cells the two-cells-per-wavefront first pass handed to the one-cell
-                                first pass (too many candidates, faces or vertices for its slots, a
-                                thin region, or more than one distance shell) */
+  int32_t rebuilt_cells;     /* cells the two-cells-per-wavefront first passes handed to the one-cell
+                                first passes (too many candidates, faces or vertices for their slots,
+                                a thin region, or more distance shells than they take) */
 } mm_step_info;
 
 /* Device views of the current tessellation, in the library's internal

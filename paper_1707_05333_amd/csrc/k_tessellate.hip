@@ -1175,7 +1175,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
 }
 
 // ---------------------------------------------------------------------------
-// The lean first pass with two cells per wavefront.
+// The first passes with two cells per wavefront (lean and dense).
 //
 // One wavefront builds one cell above, and most of the work of a cut (the
 // plane slot, the cap's boundary, the new vertices of the fan) occupies a
@@ -1184,10 +1184,12 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
 // two cells.  A half holds 64 vertex slots (two per lane), 40 plane slots
 // and 48 candidates, 5 KB of LDS per cell, so 32 cells fit a CU (twice the
 // one-cell pass): the usual cell of the uniform inputs (about 16 faces, 28
-// vertices, 29 candidates) fits with room to spare.  A cell that needs
-// more, more than one distance shell, or the two-level grid (a thin region
-// or a dense bucket nearby) is handed to the one-cell pass, which builds it
-// as before.  Values that are uniform per cell are uniform per half here:
+// vertices, 29 candidates) fits with room to spare.  A cell that needs more
+// slots, more distance shells than its pass takes (one extra in the lean
+// pass, three in the dense one), or (lean pass) a thin region's wider first
+// radius is handed to the one-cell pass of its kind, which builds it as
+// before; a lean cell whose stencil holds a dense bucket is listed for the
+// dense passes.  Values that are uniform per cell are uniform per half here:
 // held in each lane of the half, and the half's 32 bits of every ballot are
 // its masks.
 // ---------------------------------------------------------------------------
@@ -1900,11 +1902,11 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
 #pragma unroll
   for (int a = 0; a < 3; ++a) reach = fmin(reach, ring * g.hb[a] + edge[a]);
   double lo2 = 0.0, hi2 = fmin(reach * reach, rloc * rloc);
-  // The first radius, then (dense pass, for a cell whose candidates do not
-  // reach twice its farthest vertex) up to kShells1 more distance shells, as
-  // in the one-cell passes: irregular inputs need one often.  A cell still
-  // short, or whose shell needs a wider stencil than the grid has, is handed
-  // on.
+  // The first radius, then, for a cell whose candidates do not reach twice
+  // its farthest vertex, more distance shells as in the one-cell passes
+  // (irregular inputs need one often): up to kShells1 in the dense pass,
+  // one in the lean pass (below).  A cell still short, or whose shell needs
+  // a wider stencil than the grid has, is handed on.
   // work: the half gathers and cuts in this round (a half whose cell is
   // complete takes no further candidates: cutting a cell again by planes it
   // already has can split, by rounding, the vertices that lie on them).

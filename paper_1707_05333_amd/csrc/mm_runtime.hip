@@ -88,7 +88,7 @@ void fill_info(const mm_ctx* c, mm_step_info* info, double dt_max) {
   info->deferred_cells = s.n_deferred;
   for (int k = 0; k < 4; ++k) info->floor_hits[k] = (int64_t)g.floor_hits[k];
   info->flags = s.flags;
-  info->rebuilt_cells = s.n_redo;
+  info->rebuilt_cells = s.n_redo + s.n_dredo;
 }
 
 mm_status check_n(mm_ctx* c, int64_t n) {
