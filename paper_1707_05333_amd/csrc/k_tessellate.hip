@@ -1067,8 +1067,8 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
     }
     // A cell whose candidates fell short of twice its farthest vertex goes
     // on with a few more shells here (irregular inputs need them often);
-    // one that still falls short, or whose next shell overflows, is
-    // deferred with its farthest-vertex bound.
+    // one that still falls short, or whose next shell overflows even when
+    // narrowed, is deferred with its farthest-vertex bound.
     double lo2 = 0.0;
     for (int shell = 0; !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)); ++shell) {
       const double nhi2 = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
@@ -1082,10 +1082,16 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
       }
       lo2 = hi2;
       hi2 = nhi2;
-      const int nc2 = gather<MODE != 0>(S, A, g, s, r, b, nring, lo2, hi2);
+      int nc2 = gather<MODE != 0>(S, A, g, s, r, b, nring, lo2, hi2);
       if (nc2 < 0) {
         defer_dense(A, s);
         return;
+      }
+      // A shell that overflows (its radius may double) is narrowed, as in
+      // the shell pass; the next shell goes on from there.
+      for (int t = 0; nc2 > kCands && t < 2; ++t) {
+        hi2 = lo2 + 0.5 * (hi2 - lo2);
+        nc2 = gather<MODE != 0>(S, A, g, s, r, b, nring, lo2, hi2);
       }
       if (nc2 > kCands) {
         defer_cell(A, s, C.rmax2);
@@ -1973,6 +1979,14 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
           }
         }
         int nc2 = gather_pair<DENSE>(S2, A, g2, go, s2, G2.r, G2.b, ring2, lo2, hi2);
+        // A shell that overflows is narrowed once (the one-cell pass takes
+        // the cell on if it still falls short).
+        const bool over2 = go && nc2 > kCandsP;
+        if (__ballot(over2)) {
+          if (over2) hi2 = lo2 + 0.5 * (hi2 - lo2);
+          const int nc3 = gather_pair<DENSE>(S2, A, g2, over2, s2, G2.r, G2.b, ring2, lo2, hi2);
+          if (over2) nc2 = nc3;
+        }
         if (go && (nc2 < 0 || nc2 > kCandsP)) {
           if (hl == 0) {
             if (nc2 < 0) A.dcells[atomicAdd(&A.st->n_dense_cells, 1)] = s;
