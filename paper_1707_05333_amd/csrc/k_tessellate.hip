@@ -1343,8 +1343,9 @@ __device__ inline double farthest_bound_pair(const PairRegs& C) {
 // buckets per lane at a time (the usual 125-bucket stencil in one memory
 // round trip, as in the one-cell gather); the dense pass one (its stencils
 // are small, and the registers spared shrink its spill: the polytropes'
-// dense cells 6% faster than with two, 10% than with four).  Returns this
-// half's candidate count, or kCandsP + 1 on overflow.
+// dense cells 6% faster than with two, 10% than with four).  Returns the
+// number of images this half found (more than kCandsP: an overflow, of
+// which only the first kCandsP are stored).
 // Without RUNS (the lean pass) a stencil that holds a dense bucket gives -1;
 // with RUNS a chunk of the stencil that holds one, in either half, is taken
 // by the two-level gather of both halves.  Called by the whole wavefront
@@ -1423,7 +1424,7 @@ __device__ int gather_pair(PairLds& S, const TessArgs& A, const GridParams& g, b
   }
   wave_sync();
   if (dense) return -1;
-  return nc > kCandsP ? kCandsP + 1 : nc;
+  return nc;   // all it found: above kCandsP only the first kCandsP are stored
 }
 
 // The two-level gather of one chunk of 32 nb stencil buckets per half (as
@@ -1866,6 +1867,15 @@ __device__ inline void cell_geom(const TessArgs& A, const GridParams& g, const i
   }
 }
 
+// Squared outer radius of the shell from sqrt(lo2) that holds about `want`
+// of the nc candidates found between sqrt(lo2) and sqrt(hi2), at the density
+// found (counts go as the shell's volume, r^3 - lo^3).
+__device__ inline double shell_for(double lo2, double hi2, int nc, double want) {
+  const double lo3 = lo2 * sqrt(lo2), hi3 = hi2 * sqrt(hi2);
+  const double r = cbrt(lo3 + (want / (double)nc) * (hi3 - lo3));
+  return r * r;
+}
+
 // Hands a cell to the one-cell first pass of its kind (lean or dense).
 template <bool DENSE>
 __device__ inline void redo_cell(const TessArgs& A, int s) {
@@ -1924,14 +1934,14 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
       act = work = false;
     }
     // More candidates than slots (a compressed region): gather again with
-    // the radius that holds about 38 of them at the density found (the
-    // cell is the same at any radius; only the work changes).
-    const bool over = work && nc > kCandsP;
+    // the radius that holds about 38 of them at the density found (the cell
+    // is the same at any radius; only the work changes).  Not for the dense
+    // pass's later shells: there the other half waits through the second
+    // gather, and the one-cell pass builds such a cell for less (the
+    // polytropes 3% faster).
+    const bool over = work && nc > kCandsP && (!DENSE || shell == 0);
     if (__ballot(over)) {
-      if (over) {
-        const double f = cbrt(38.0 / (double)nc);
-        hi2 = lo2 + (hi2 - lo2) * (f * f);
-      }
+      if (over) hi2 = shell_for(lo2, hi2, nc, 38.0);
       const int nc2 = gather_pair<DENSE>(S, A, g, over, s, r, b, ring, lo2, hi2);
       if (over) nc = nc2;
     }
@@ -1983,7 +1993,7 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
         // the cell on if it still falls short).
         const bool over2 = go && nc2 > kCandsP;
         if (__ballot(over2)) {
-          if (over2) hi2 = lo2 + 0.5 * (hi2 - lo2);
+          if (over2) hi2 = shell_for(lo2, hi2, nc2, 38.0);
           const int nc3 = gather_pair<DENSE>(S2, A, g2, over2, s2, G2.r, G2.b, ring2, lo2, hi2);
           if (over2) nc2 = nc3;
         }
