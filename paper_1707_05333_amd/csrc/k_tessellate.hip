@@ -982,6 +982,21 @@ __device__ void defer_dense(const TessArgs& A, int s) {
   if (__lane_id() == 0) A.dcells[atomicAdd(&A.st->n_dense_cells, 1)] = s;
 }
 
+// Squared outer radius of the next shell after [sqrt(lo2), sqrt(hi2)), which
+// held nc candidates: twice the farthest vertex (the shell the cell needs),
+// at most twice sqrt(hi2), and at most the radius that holds about `want`
+// more at the density found (so the shell seldom overflows the candidate
+// slots; a cell that needs more goes on with another shell).
+__device__ inline double next_shell(double rmax2, double lo2, double hi2, int nc, double want) {
+  double n2 = fmin(4.0 * rmax2 * (1.0 + 1e-9), 4.0 * hi2);
+  if (nc > 0) {
+    const double lo3 = lo2 * sqrt(lo2), hi3 = hi2 * sqrt(hi2);
+    const double r = cbrt(hi3 + want * (hi3 - lo3) / (double)nc);
+    n2 = fmin(n2, fmax(r * r, hi2 * (1.0 + 1e-6)));
+  }
+  return n2;
+}
+
 // Builds the cell of internal generator s.
 // MODE 0 (first pass of the cells the two-cell pass hands on): candidates
 //   within the grid's filter radius; a cell whose candidates do not cover
@@ -1070,8 +1085,9 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
     // one that still falls short, or whose next shell overflows even when
     // narrowed, is deferred with its farthest-vertex bound.
     double lo2 = 0.0;
+    int last = nc;   // candidates of the last gather, between sqrt(lo2) and sqrt(hi2)
     for (int shell = 0; !(4.0 * C.rmax2 <= hi2 * (1.0 - 1e-12)); ++shell) {
-      const double nhi2 = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
+      const double nhi2 = next_shell(C.rmax2, lo2, hi2, last, 70.0);
       const int nring = ring_for(g, edge, nhi2);
       // (A thin region's cell, with few candidates found, needs wide shells
       // that only the shell pass's pruning keeps cheap.)
@@ -1097,6 +1113,7 @@ __device__ void tess_cell(TessLds& S, const TessArgs& A, const int s, double4* v
         defer_cell(A, s, C.rmax2);
         return;
       }
+      last = nc2;
       sort_candidates(S, nc2);
       if (int bad = clip_candidates(S, nc2, C)) {
         fail_cell(A, s, seg, bad);
@@ -1978,7 +1995,7 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
         cell_geom(A, g2, s2, G2);
         int ring2 = 0;
         if (go) {
-          const double nhi2 = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
+          const double nhi2 = next_shell(C.rmax2, lo2, hi2, nc, 38.0);
           ring2 = ring_for(g2, G2.edge, nhi2);
           if (ring2 > g2.nb[0] || ring2 > g2.nb[1] || ring2 > g2.nb[2]) {
             if (hl == 0) redo_cell<DENSE>(A, s);
@@ -2019,7 +2036,7 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
     }
     if (__ballot(go) == 0ull) break;
     if (go) {
-      const double nhi2 = fmin(4.0 * C.rmax2 * (1.0 + 1e-9), 4.0 * hi2);
+      const double nhi2 = next_shell(C.rmax2, lo2, hi2, nc, 38.0);
       ring = ring_for(g, edge, nhi2);
       if (shell == kShells1 || ring > g.nb[0] || ring > g.nb[1] || ring > g.nb[2]) {
         if (hl == 0) redo_cell<DENSE>(A, s);
