@@ -102,6 +102,9 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ unsigned long long lanes_below() { return (1ull << __lane_id()) - 1ull; }
 
+// This lane's bit of a wavefront mask (a select on the mask itself, no shift).
+__device__ __forceinline__ bool lane_on(unsigned long long m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
 // Exclusive prefix sum over the wave of small non-negative values
 // (x < 2^BITS), from one ballot per bit; *total gets the wave's sum.
 template <int BITS>
@@ -678,10 +681,9 @@ __device__ inline int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane
 
 // Squared distance bound of the farthest live vertex (float, rounded up).
 __device__ inline double farthest_bound(const CellRegs& C) {
-  const int lane = __lane_id();
   double m2 = 0.0;
-  if ((C.L0 >> lane) & 1ull) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
-  if (C.L1 != 0ull && ((C.L1 >> lane) & 1ull)) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
+  if (lane_on(C.L0)) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
+  if (C.L1 != 0ull && lane_on(C.L1)) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
   return wave_max_bound(m2);
 }
 
@@ -720,8 +722,8 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     unsigned long long M1 = 0ull;
     if (two) M1 = __ballot(q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h) & C.L1;
     if ((M0 | M1) == 0ull) continue;
-    const bool live0 = (C.L0 >> lane) & 1ull, live1 = two && ((C.L1 >> lane) & 1ull);
-    const bool out0 = (M0 >> lane) & 1ull, out1 = (M1 >> lane) & 1ull;
+    const bool live0 = lane_on(C.L0), live1 = two && lane_on(C.L1);
+    const bool out0 = lane_on(M0), out1 = lane_on(M1);
 
     // Plane slot for the new face: the next unused slot while there is one,
     // then the lowest slot no surviving vertex uses.
@@ -786,8 +788,8 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     const double4 qp = make_double4(q.x, q.y, q.z, h);
     const int r0 = __popcll(F0 & lanes_below());
     const int r1 = nf0 + __popcll(F1 & lanes_below());
-    const bool new0 = ((F0 >> lane) & 1ull) && r0 < B;
-    const bool new1 = ((F1 >> lane) & 1ull) && r1 < B;
+    const bool new0 = lane_on(F0) && r0 < B;
+    const bool new1 = lane_on(F1) && r1 < B;
     if (new0) {
       const int xy = S.elist[r0];
       const int x = xy & 255, y = xy >> 8;
@@ -826,7 +828,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
 // Faces, volume and centroid of the finished cell; writes the cell's outputs.
 __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const CellRegs& C) {
   const int lane = __lane_id();
-  const bool live0 = (C.L0 >> lane) & 1ull, live1 = (C.L1 >> lane) & 1ull;
+  const bool live0 = lane_on(C.L0), live1 = lane_on(C.L1);
   // The candidate list is dead now: its storage takes the vertex copies.
   wave_sync();
   S.vx[lane] = C.v0x; S.vy[lane] = C.v0y; S.vz[lane] = C.v0z;
@@ -944,13 +946,12 @@ __device__ int finish_cell(TessLds& S, const TessArgs& A, const int s, const Cel
 // compacted into vl; returns their number, or 0 (no list) when there are
 // more than kPruneVerts.
 __device__ int vertex_list(const CellRegs& C, double4* vl) {
-  const int lane = __lane_id();
   const int n0 = __popcll(C.L0), n = n0 + __popcll(C.L1);
   if (n > kPruneVerts) return 0;
-  if ((C.L0 >> lane) & 1ull)
+  if (lane_on(C.L0))
     vl[__popcll(C.L0 & lanes_below())] =
         make_double4(C.v0x, C.v0y, C.v0z, C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z);
-  if ((C.L1 >> lane) & 1ull)
+  if (lane_on(C.L1))
     vl[n0 + __popcll(C.L1 & lanes_below())] =
         make_double4(C.v1x, C.v1y, C.v1z, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
   wave_sync();
@@ -1245,6 +1246,10 @@ __device__ __forceinline__ int hlane() { return __lane_id() & 31; }
 // The 32 bits of a wavefront mask that belong to this lane's half.
 __device__ __forceinline__ unsigned hbits(unsigned long long m) { return (unsigned)(m >> (__lane_id() & 32)); }
 __device__ __forceinline__ unsigned hbelow() { return (1u << hlane()) - 1u; }
+// All lanes of each half whose 32 bits of m are not all zero.
+__device__ __forceinline__ unsigned long long halves_of(unsigned long long m) {
+  return ((unsigned)m ? 0xffffffffull : 0ull) | ((m >> 32) ? 0xffffffff00000000ull : 0ull);
+}
 
 template <int BITS>
 __device__ __forceinline__ int half_excl_scan_small(int x, int* total) {
@@ -1348,10 +1353,9 @@ __device__ void init_box_pair(PairLds& S, const GridParams& g, PairRegs& C) {
 }
 
 __device__ inline double farthest_bound_pair(const PairRegs& C) {
-  const int hl = hlane();
   double m2 = 0.0;
-  if ((hbits(C.L0w) >> hl) & 1u) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
-  if ((hbits(C.L1w) >> hl) & 1u) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
+  if (lane_on(C.L0w)) m2 = C.v0x * C.v0x + C.v0y * C.v0y + C.v0z * C.v0z;
+  if (lane_on(C.L1w)) m2 = fmax(m2, C.v1x * C.v1x + C.v1y * C.v1y + C.v1z * C.v1z);
   return half_max_bound(m2);
 }
 
@@ -1627,12 +1631,15 @@ __device__ int clip_pair(PairLds& S, const int nc, PairRegs& C) {
         }
       }
     }
-    const unsigned M0 = hbits(__ballot(act && q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h)) & hbits(C.L0w);
-    const unsigned M1 = hbits(__ballot(act && q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h)) & hbits(C.L1w);
-    const bool cut = act && (M0 | M1) != 0u;
-    if (__ballot(cut) == 0ull) continue;
-    const bool live0 = (hbits(C.L0w) >> hl) & 1u, live1 = (hbits(C.L1w) >> hl) & 1u;
-    const bool out0 = cut && ((M0 >> hl) & 1u), out1 = cut && ((M1 >> hl) & 1u);
+    // The masks stay wavefront-wide (scalar): a lane reads its own bit by a
+    // select on the mask, and only ranks and counts take the half's bits.
+    const unsigned long long M0w = __ballot(act && q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h) & C.L0w;
+    const unsigned long long M1w = __ballot(act && q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h) & C.L1w;
+    const unsigned long long cutw = halves_of(M0w | M1w);   // the halves whose cell this cuts
+    if (cutw == 0ull) continue;
+    const bool cut = lane_on(cutw);
+    const bool live0 = lane_on(C.L0w), live1 = lane_on(C.L1w);
+    const bool out0 = lane_on(M0w), out1 = lane_on(M1w);   // (removed slots are live ones)
     const bool kept0 = live0 && !out0, kept1 = live1 && !out1;
 
     // Plane slot: the next unused one (a cell that needs more goes to the
@@ -1662,7 +1669,8 @@ __device__ int clip_pair(PairLds& S, const int nc, PairRegs& C) {
     const int bm1 = go && out1 ? boundary(C.t1) : 0;
     int B;
     const int pre = half_excl_scan_small<3>(__popc(bm0) + __popc(bm1), &B);
-    const unsigned F0 = ~hbits(C.L0w) | M0, F1 = ~hbits(C.L1w) | M1;   // free slots after the cut
+    const unsigned long long F0w = ~C.L0w | M0w, F1w = ~C.L1w | M1w;   // free slots after the cut
+    const unsigned F0 = hbits(F0w), F1 = hbits(F1w);
     const int nf0 = __popc(F0);
     const bool room = B <= nf0 + __popc(F1);
     if (go && !room) {
@@ -1692,8 +1700,8 @@ __device__ int clip_pair(PairLds& S, const int nc, PairRegs& C) {
     const double4 qp = make_double4(q.x, q.y, q.z, h);
     const int r0 = __popc(F0 & hbelow());
     const int r1 = nf0 + __popc(F1 & hbelow());
-    const bool new0 = doit && ((F0 >> hl) & 1u) && r0 < B;
-    const bool new1 = doit && ((F1 >> hl) & 1u) && r1 < B;
+    const bool new0 = doit && lane_on(F0w) && r0 < B;
+    const bool new1 = doit && lane_on(F1w) && r1 < B;
     if (new0) {
       const int xy = S.elist[r0];
       const int x = xy & 255, y = xy >> 8;
@@ -1741,7 +1749,7 @@ __device__ int clip_pair(PairLds& S, const int nc, PairRegs& C) {
 // each lane integrates planes hl and hl + 32).  Returns 0 or a failure bit.
 __device__ int finish_pair(PairLds& S, const TessArgs& A, const bool act, const int s, const PairRegs& C) {
   const int hl = hlane();
-  const bool live0 = act && ((hbits(C.L0w) >> hl) & 1u), live1 = act && ((hbits(C.L1w) >> hl) & 1u);
+  const bool live0 = act && lane_on(C.L0w), live1 = act && lane_on(C.L1w);
   wave_sync();
   S.vx[hl] = C.v0x; S.vy[hl] = C.v0y; S.vz[hl] = C.v0z;
   S.tri[hl] = C.t0;
