@@ -48,7 +48,7 @@ constexpr int kThinRing = 8;            // widest stencil of a thin region's fir
 constexpr int kPruneVerts = 96;
 
 // 10 KB per wavefront, so 16 cells fit the 160 KB of LDS of a CU (as many
-// as the lean pass's registers allow).  The candidate list and the cut's
+// as the one-cell first passes' registers allow, 4 waves per SIMD).  The candidate list and the cut's
 // scratch are only needed while cutting and the vertex copies only in the
 // epilogue (while cutting, vertices and their triangles live in registers),
 // so the two share storage.

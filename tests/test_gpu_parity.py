@@ -67,6 +67,32 @@ def test_crowded_site_cells_are_handed_on(orc, hole):
     assert info["rebuilt_cells"] > 0 and info["n_faces"] * 2 == len(om.j)
 
 
+def test_tessellation_parity_on_a_deformed_sod_tube(orc):
+    """The mesh of a Sod tube after 30 oracle steps: shock, contact and
+    rarefaction have compressed and stretched layers of the lattice, and the
+    jitter has turned into sliver faces (the certificate's margin is
+    7e-11).  The positions come from the oracle's own steps; the GPU
+    tessellation of them matches the oracle's: the same faces, volumes,
+    centroids and areas within 1e-10, face centroids within 1e-9 of the
+    cell scale (a sliver's centroid comes from nearly coincident vertices,
+    whose rounding the near-degeneracy amplifies in both implementations:
+    up to 5e-10 h, on faces of area 1e-5 h^2, while their areas agree to
+    1e-13 h^2)."""
+    import paper_1707_05333_amd as M
+    wl = W.c2_sod(shape=(128, 16, 16), box=(4.0, 0.5, 0.5))
+    _print_case("deformed sod tube", n=wl.n, oracle_steps=30)
+    p = orc.make_params(wl.box, **wl.params)
+    Q = orc.init_charges(orc.tessellate(wl.pos, wl.box), p, wl.prim)
+    pos = wl.pos.copy()
+    for _ in range(30):
+        pos, Q, _w, _dt, _cnt = orc.step(pos, Q, p)
+    mm, info, om = mesh_pair(orc, pos, wl.box, **wl.params)
+    assert om.status == 0
+    assert om.delta_min > 1e-12, "input not certified non-degenerate"
+    compare_mesh(mm, om, ftol=1e-9)
+    assert info["n_faces"] * 2 == len(om.j)
+
+
 def test_bcc_closed_form_on_gpu():
     # Exact body-centred cubic lattice: every cell is the truncated
     # octahedron (volume a^3/2, 6 squares a^2/8, 8 hexagons 3 sqrt(3) a^2/16,
