@@ -169,12 +169,24 @@ __device__ __forceinline__ unsigned long long plane_bits(uint32_t t) {
 }
 
 // Vertex where planes a, b, c meet: solve [a; b; c] v = (a.w, b.w, c.w).
+// The determinant's reciprocal comes from the hardware estimate refined by
+// two Newton steps (within an ulp of the quotient; the estimate's error
+// squares at each step), with correctly rounded division outside the
+// normal range, where the estimate would over- or underflow.
 __device__ __forceinline__ void intersect3(const double4 a, const double4 b, const double4 c, double& x, double& y,
                                            double& z) {
   const double bcx = b.y * c.z - b.z * c.y, bcy = b.z * c.x - b.x * c.z, bcz = b.x * c.y - b.y * c.x;
   const double cax = c.y * a.z - c.z * a.y, cay = c.z * a.x - c.x * a.z, caz = c.x * a.y - c.y * a.x;
   const double abx = a.y * b.z - a.z * b.y, aby = a.z * b.x - a.x * b.z, abz = a.x * b.y - a.y * b.x;
-  const double inv = 1.0 / (a.x * bcx + a.y * bcy + a.z * bcz);
+  const double det = a.x * bcx + a.y * bcy + a.z * bcz;
+  double inv;
+  if (fabs(det) > 1e-280 && fabs(det) < 1e280) {
+    inv = __builtin_amdgcn_rcp(det);
+    inv = fma(fma(-det, inv, 1.0), inv, inv);
+    inv = fma(fma(-det, inv, 1.0), inv, inv);
+  } else {
+    inv = 1.0 / det;
+  }
   x = (a.w * bcx + b.w * cax + c.w * abx) * inv;
   y = (a.w * bcy + b.w * cay + c.w * aby) * inv;
   z = (a.w * bcz + b.w * caz + c.w * abz) * inv;
