@@ -105,19 +105,21 @@ __device__ __forceinline__ unsigned long long lanes_below() { return (1ull << __
 // This lane's bit of a wavefront mask (a select on the mask itself, no shift).
 __device__ __forceinline__ bool lane_on(unsigned long long m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
-// Exclusive prefix sum over the wave of small non-negative values
-// (x < 2^BITS), from one ballot per bit; *total gets the wave's sum.
-template <int BITS>
-__device__ __forceinline__ int wave_excl_scan_small(int x, int* total) {
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int b = 0; b < BITS; ++b) {
-    const unsigned long long m = __ballot((x >> b) & 1);
-    pre += __popcll(m & lanes_below()) << b;
-    tot += __popcll(m) << b;
-  }
-  *total = tot;
-  return pre;
+// Exclusive prefix sum over the wave; *total gets the wave's sum.  DPP lane
+// moves: row shifts by 1, 2, 4 and 8 inside each row of 16 lanes (lanes
+// shifted in from outside the row read 0), then the last lane of row 0
+// added to row 1 and of row 2 to row 3, then lane 31 to rows 2 and 3.
+// Called by the whole wavefront.
+__device__ __forceinline__ int wave_excl_scan(int x, int* total) {
+  int v = x;
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+  *total = __builtin_amdgcn_readlane(v, 63);
+  return v - x;
 }
 
 // Wave-wide reductions with DPP lane moves (no LDS round trip): within each
@@ -482,7 +484,7 @@ __device__ int gather_runs(TessLds& S, const TessArgs& A, const GridParams& g, c
       }
     }
     int total;
-    const int excl = wave_excl_scan_small<15>(nr, &total);
+    const int excl = wave_excl_scan(nr, &total);
     for (int t0 = 0; t0 < total; t0 += 64) {
       const int t = t0 + lane;
       // the last bucket whose runs start at or before t
@@ -770,7 +772,7 @@ __device__ int clip_candidates(TessLds& S, const int nc, CellRegs& C) {
     const int bm1 = out1 ? boundary(C.t1) : 0;
     const int nbl = __popc(bm0) + __popc(bm1);
     int B;
-    const int pre = wave_excl_scan_small<3>(nbl, &B);
+    const int pre = wave_excl_scan(nbl, &B);
 
     const unsigned long long F0 = ~L0 | M0, F1 = ~L1 | M1;   // free slots after the cut
     const int nf0 = __popcll(F0);
@@ -1263,17 +1265,17 @@ __device__ __forceinline__ unsigned long long halves_of(unsigned long long m) {
   return ((unsigned)m ? 0xffffffffull : 0ull) | ((m >> 32) ? 0xffffffff00000000ull : 0ull);
 }
 
-template <int BITS>
-__device__ __forceinline__ int half_excl_scan_small(int x, int* total) {
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int b = 0; b < BITS; ++b) {
-    const unsigned m = hbits(__ballot((x >> b) & 1));
-    pre += __popc(m & hbelow()) << b;
-    tot += __popc(m) << b;
-  }
-  *total = tot;
-  return pre;
+// Inclusive prefix sum within each half: row shifts by 1, 2, 4 and 8 inside
+// each row of 16 lanes (lanes shifted in from outside the row read 0), then
+// the last lane of row 0 added to row 1 and that of row 2 to row 3.  Called
+// by the whole wavefront.
+__device__ __forceinline__ int half_incl_scan(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);
+  return x;
 }
 
 // Reductions over each half: within rows of 16 by quad permutes and row
@@ -1506,8 +1508,9 @@ __device__ int gather_runs_pair(PairLds& S, const TessArgs& A, const GridParams&
         }
       }
     }
-    int total;
-    const int excl = half_excl_scan_small<15>(nr, &total);
+    const int incl = half_incl_scan(nr);
+    const int excl = incl - nr;
+    const int total = (int)half_pick((unsigned)incl);
     const int tmax = (int)wave_umax32((unsigned)total);
     for (int t0 = 0; t0 < tmax; t0 += 32) {
       const int t = t0 + hl;
@@ -1679,8 +1682,10 @@ __device__ int clip_pair(PairLds& S, const int nc, PairRegs& C) {
     };
     const int bm0 = go && out0 ? boundary(C.t0) : 0;
     const int bm1 = go && out1 ? boundary(C.t1) : 0;
-    int B;
-    const int pre = half_excl_scan_small<3>(__popc(bm0) + __popc(bm1), &B);
+    const int nb = __popc(bm0) + __popc(bm1);
+    const int incl = half_incl_scan(nb);
+    const int pre = incl - nb;
+    const int B = (int)half_pick((unsigned)incl);
     const unsigned long long F0w = ~C.L0w | M0w, F1w = ~C.L1w | M1w;   // free slots after the cut
     const unsigned F0 = hbits(F0w), F1 = hbits(F1w);
     const int nf0 = __popc(F0);
