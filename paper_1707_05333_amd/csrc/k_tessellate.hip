@@ -1243,7 +1243,6 @@ struct __align__(16) PairLds {
       int32_t cjk[kCandsP];
       uint8_t order[kCandsP];
       uint16_t elist[kVertsP];
-      uint8_t kept[kVertsP];
     };
     struct {                           // in the epilogue
       double vx[kVertsP], vy[kVertsP], vz[kVertsP];
@@ -1584,7 +1583,9 @@ __device__ void sort_pair(PairLds& S, const int nc) {
     }
   }
   if (c0 < nc) S.order[lt0] = (uint8_t)c0;
+  else if (c0 < kCandsP) S.order[c0] = 0;
   if (c1 < nc) S.order[lt1] = (uint8_t)c1;
+  else if (c1 < kCandsP) S.order[c1] = 0;
   wave_sync();
   const bool tie = (c0 < nc && S.order[lt0] != c0) || (c1 < nc && S.order[lt1] != c1);
   const bool htie = hbits(__ballot(tie)) != 0u;
@@ -1610,156 +1611,171 @@ __device__ void sort_pair(PairLds& S, const int nc) {
 // Returns 0 or a failure bit for this half's cell.
 __device__ int clip_pair(PairLds& S, const int nc, PairRegs& C) {
   const int hl = hlane();
-  bool stale = false, done = nc <= 0;
-  int since = 0, fail = 0;
+  constexpr unsigned long long LO = 0xffffffffull, HI = ~LO;
+  // The per-half state is held as wavefront masks (a half's 32 bits all set
+  // or all clear) and per-half counters, which the compiler keeps in scalar
+  // registers: a lane's own flag is a select on the mask, and the loop's
+  // control costs no vector instructions.
+  unsigned long long donew = __ballot(nc <= 0);   // halves that stopped
+  unsigned long long stalew = 0ull;                // rmax2 older than the last cut
+  unsigned long long failp = 0ull, failv = 0ull;  // halves out of plane or vertex slots
+  int since0 = 0, since1 = 0;                      // cuts since each half's last bound
   double lim = 2.0 * C.rmax2;
   const int ncmax = (int)wave_umax32((unsigned)max(nc, 0));
   for (int k = 0; k < ncmax; ++k) {
     // A half that stopped, or ran out of candidates, stays idle: the loop
-    // ends when both are.
-    bool act = !done && k < nc;
-    if (__ballot(act) == 0ull) break;
-    double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
-    int c = 0;
-    if (act) {
-      c = S.order[k];
-      q = S.cd[c];
-    }
+    // ends when both are.  (Slots past a half's count hold candidate 0.)
+    unsigned long long actw = __ballot(k < nc) & ~donew;
+    if (actw == 0ull) break;
+    const int c = S.order[k];
+    const double4 q = S.cd[c];
     const double h = q.w;
-    // Stop test of each half: farther images cannot cut its cell.
-    const bool far = act && h >= lim;
-    if (__ballot(far)) {
+    // Stop test of each half: farther images cannot cut its cell.  A bound
+    // older than the last cut is refreshed and the test taken again.
+    const unsigned long long farw = __ballot(h >= lim) & actw;
+    if (farw) {
       const double nb = farthest_bound_pair(C);
-      if (far) {
-        if (!stale) {
-          act = false;
-          done = true;
-        } else {
-          C.rmax2 = nb;
-          stale = false;
-          since = 0;
-          lim = 2.0 * nb;
-          if (h >= lim) {
-            act = false;
-            done = true;
-          }
-        }
+      const unsigned long long refw = farw & stalew;
+      if (lane_on(refw)) {
+        C.rmax2 = nb;
+        lim = 2.0 * nb;
       }
+      stalew &= ~refw;
+      if (refw & LO) since0 = 0;
+      if (refw & HI) since1 = 0;
+      const unsigned long long stopw = (farw & ~refw) | (refw & __ballot(h >= lim));
+      donew |= stopw;
+      actw &= ~stopw;
     }
-    // The masks stay wavefront-wide (scalar): a lane reads its own bit by a
-    // select on the mask, and only ranks and counts take the half's bits.
-    const unsigned long long M0w = __ballot(act && q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h) & C.L0w;
-    const unsigned long long M1w = __ballot(act && q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h) & C.L1w;
+    const unsigned long long M0w = __ballot(q.x * C.v0x + q.y * C.v0y + q.z * C.v0z > h) & actw & C.L0w;
+    const unsigned long long M1w = __ballot(q.x * C.v1x + q.y * C.v1y + q.z * C.v1z > h) & actw & C.L1w;
     const unsigned long long cutw = halves_of(M0w | M1w);   // the halves whose cell this cuts
     if (cutw == 0ull) continue;
-    const bool cut = lane_on(cutw);
-    const bool live0 = lane_on(C.L0w), live1 = lane_on(C.L1w);
-    const bool out0 = lane_on(M0w), out1 = lane_on(M1w);   // (removed slots are live ones)
-    const bool kept0 = live0 && !out0, kept1 = live1 && !out1;
 
     // Plane slot: the next unused one (a cell that needs more goes to the
     // one-cell pass, which reuses the slots of faces cut away).
-    const int p = C.np;
-    bool go = cut;
-    if (cut && p >= kPlanesP) {
-      fail = F_PLANES;
-      done = true;
-      go = false;
-    }
-    if (go) C.np++;
-
-    if (go) {
-      S.kept[hl] = (uint8_t)kept0;
-      S.kept[hl + 32] = (uint8_t)kept1;
-    }
-    wave_sync();
+    const unsigned p = (unsigned)C.np;
+    const unsigned long long fullw = __ballot(p >= (unsigned)kPlanesP) & cutw;
+    failp |= fullw;
+    donew |= fullw;
+    const unsigned long long gow = cutw & ~fullw;
+    if (gow == 0ull) continue;
+    if (lane_on(gow)) C.np = (int)p + 1;
+    // The half's kept vertices as a set over its 64 slots (bit v: slot v,
+    // the first register's 32 slots, then the second's).
+    const unsigned long long K =
+        (unsigned long long)hbits(C.L0w & ~M0w) | ((unsigned long long)hbits(C.L1w & ~M1w) << 32);
     auto boundary = [&](uint32_t T) -> int {
-      const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
-      const int m0 = S.kept[S.E[bq * kPlanesP + a] & (kVertsP - 1)];
-      const int m1 = S.kept[S.E[cq * kPlanesP + bq] & (kVertsP - 1)];
-      const int m2 = S.kept[S.E[a * kPlanesP + cq] & (kVertsP - 1)];
-      return m0 | (m1 << 1) | (m2 << 2);
+      const unsigned a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
+      const unsigned m0 = (unsigned)(K >> (S.E[__umul24(bq, kPlanesP) + a] & (kVertsP - 1)));
+      const unsigned m1 = (unsigned)(K >> (S.E[__umul24(cq, kPlanesP) + bq] & (kVertsP - 1)));
+      const unsigned m2 = (unsigned)(K >> (S.E[__umul24(a, kPlanesP) + cq] & (kVertsP - 1)));
+      return (int)((m0 & 1u) | ((m1 & 1u) << 1) | ((m2 & 1u) << 2));
     };
-    const int bm0 = go && out0 ? boundary(C.t0) : 0;
-    const int bm1 = go && out1 ? boundary(C.t1) : 0;
+    int bm0 = 0, bm1 = 0;
+    if (lane_on(gow & M0w)) bm0 = boundary(C.t0);
+    if (lane_on(gow & M1w)) bm1 = boundary(C.t1);
     const int nb = __popc(bm0) + __popc(bm1);
     const int incl = half_incl_scan(nb);
     const int pre = incl - nb;
-    const int B = (int)half_pick((unsigned)incl);
-    const unsigned long long F0w = ~C.L0w | M0w, F1w = ~C.L1w | M1w;   // free slots after the cut
-    const unsigned F0 = hbits(F0w), F1 = hbits(F1w);
-    const int nf0 = __popc(F0);
-    const bool room = B <= nf0 + __popc(F1);
-    if (go && !room) {
-      fail = F_VERTS;
-      done = true;
-    }
-    const bool doit = go && room;
-    if (doit && hl == 0) {
+    // Boundary edges of each half, and its free slots after the cut.
+    const int B0 = __builtin_amdgcn_readlane(incl, 31), B1 = __builtin_amdgcn_readlane(incl, 63);
+    const unsigned long long F0w = ~C.L0w | M0w, F1w = ~C.L1w | M1w;
+    const int nfree0 = __popc((unsigned)F0w) + __popc((unsigned)F1w);
+    const int nfree1 = __popc((unsigned)(F0w >> 32)) + __popc((unsigned)(F1w >> 32));
+    const unsigned long long roomw = (B0 <= nfree0 ? LO : 0ull) | (B1 <= nfree1 ? HI : 0ull);
+    failv |= gow & ~roomw;
+    donew |= gow & ~roomw;
+    const unsigned long long doitw = gow & roomw;
+    if (doitw == 0ull) continue;
+    if (lane_on(doitw) && hl == 0) {
       S.pl[p] = make_double4(q.x, q.y, q.z, h);
-      S.pcand[p] = S.cjk[c];
+      // (the slot's byte offset is taken opaque: derived from the plane
+      // row's address the compiler forms it with a 64-bit multiply-add)
+      unsigned p4 = p << 2;
+      asm volatile("" : "+v"(p4));
+      *(int32_t*)((char*)S.pcand + p4) = S.cjk[c];
     }
-    if (doit) {
+    // Each removed vertex lists its boundary edges from position pre, the
+    // first register's, then the second's (only when a removed vertex
+    // lies there).
+    if (lane_on(doitw & M0w)) {
       int e = pre;
       const int ta0 = C.t0 & 255, tb0 = (C.t0 >> 8) & 255, tc0 = (C.t0 >> 16) & 255;
       if (bm0 & 1) S.elist[e++] = (uint16_t)(ta0 | (tb0 << 8));
       if (bm0 & 2) S.elist[e++] = (uint16_t)(tb0 | (tc0 << 8));
       if (bm0 & 4) S.elist[e++] = (uint16_t)(tc0 | (ta0 << 8));
-      const int ta1 = C.t1 & 255, tb1 = (C.t1 >> 8) & 255, tc1 = (C.t1 >> 16) & 255;
-      if (bm1 & 1) S.elist[e++] = (uint16_t)(ta1 | (tb1 << 8));
-      if (bm1 & 2) S.elist[e++] = (uint16_t)(tb1 | (tc1 << 8));
-      if (bm1 & 4) S.elist[e++] = (uint16_t)(tc1 | (ta1 << 8));
+    }
+    if (doitw & M1w) {
+      if (lane_on(doitw & M1w)) {
+        int e = pre + __popc(bm0);
+        const int ta1 = C.t1 & 255, tb1 = (C.t1 >> 8) & 255, tc1 = (C.t1 >> 16) & 255;
+        if (bm1 & 1) S.elist[e++] = (uint16_t)(ta1 | (tb1 << 8));
+        if (bm1 & 2) S.elist[e++] = (uint16_t)(tb1 | (tc1 << 8));
+        if (bm1 & 4) S.elist[e++] = (uint16_t)(tc1 | (ta1 << 8));
+      }
     }
     wave_sync();   // every E lookup above is done before any write below
 
     // Boundary edge r goes to the free slot of rank r (the first register's
     // slots in lane order, then the second's); that lane builds the vertex.
+    // The second register takes part only in a half with more boundary
+    // edges than free slots in the first.
     const double4 qp = make_double4(q.x, q.y, q.z, h);
+    const unsigned F0 = hbits(F0w);
     const int r0 = __popc(F0 & hbelow());
-    const int r1 = nf0 + __popc(F1 & hbelow());
-    const bool new0 = doit && lane_on(F0w) && r0 < B;
-    const bool new1 = doit && lane_on(F1w) && r1 < B;
-    if (new0) {
-      const int xy = S.elist[r0];
-      const int x = xy & 255, y = xy >> 8;
-      C.t0 = (uint32_t)(x | (y << 8) | (p << 16));
-      intersect3(S.pl[x], S.pl[y], qp, C.v0x, C.v0y, C.v0z);
-      S.E[x * kPlanesP + y] = (uint8_t)hl;
-      S.E[y * kPlanesP + p] = (uint8_t)hl;
-      S.E[p * kPlanesP + x] = (uint8_t)hl;
+    const int B = (__lane_id() & 32) ? B1 : B0;
+    const unsigned long long new0w = __ballot(r0 < B) & F0w & doitw;
+    const unsigned long long spillw = (B0 > __popc((unsigned)F0w) ? LO : 0ull) |
+                                      (B1 > __popc((unsigned)(F0w >> 32)) ? HI : 0ull);
+    unsigned long long new1w = 0ull;
+    int r1 = 0;
+    if (doitw & spillw) {
+      r1 = __popc(F0) + __popc(hbits(F1w) & hbelow());
+      new1w = __ballot(r1 < B) & F1w & doitw;
     }
-    if (new1) {
-      const int xy = S.elist[r1];
-      const int x = xy & 255, y = xy >> 8;
-      C.t1 = (uint32_t)(x | (y << 8) | (p << 16));
+    if (lane_on(new0w)) {
+      const unsigned xy = S.elist[r0];
+      const unsigned x = xy & 255, y = xy >> 8;
+      C.t0 = x | (y << 8) | (p << 16);
+      intersect3(S.pl[x], S.pl[y], qp, C.v0x, C.v0y, C.v0z);
+      S.E[__umul24(x, kPlanesP) + y] = (uint8_t)hl;
+      S.E[__umul24(y, kPlanesP) + p] = (uint8_t)hl;
+      S.E[__umul24(p, kPlanesP) + x] = (uint8_t)hl;
+    }
+    if (lane_on(new1w)) {
+      const unsigned xy = S.elist[r1];
+      const unsigned x = xy & 255, y = xy >> 8;
+      C.t1 = x | (y << 8) | (p << 16);
       intersect3(S.pl[x], S.pl[y], qp, C.v1x, C.v1y, C.v1z);
-      S.E[x * kPlanesP + y] = (uint8_t)(hl + 32);
-      S.E[y * kPlanesP + p] = (uint8_t)(hl + 32);
-      S.E[p * kPlanesP + x] = (uint8_t)(hl + 32);
+      S.E[__umul24(x, kPlanesP) + y] = (uint8_t)(hl + 32);
+      S.E[__umul24(y, kPlanesP) + p] = (uint8_t)(hl + 32);
+      S.E[__umul24(p, kPlanesP) + x] = (uint8_t)(hl + 32);
     }
     wave_sync();
-    C.L0w = __ballot(doit ? (kept0 || new0) : live0);
-    C.L1w = __ballot(doit ? (kept1 || new1) : live1);
-    bool refresh = false;
-    if (doit) {
-      stale = true;
-      refresh = ++since == 4;
-    }
-    if (__ballot(refresh)) {
-      const double nb = farthest_bound_pair(C);
-      if (refresh) {
-        C.rmax2 = nb;
-        lim = 2.0 * nb;
-        stale = false;
-        since = 0;
+    C.L0w = (C.L0w & ~(M0w & doitw)) | new0w;
+    C.L1w = (C.L1w & ~(M1w & doitw)) | new1w;
+    // The bound is refreshed every fourth cut of a half.
+    stalew |= doitw;
+    if (doitw & LO) ++since0;
+    if (doitw & HI) ++since1;
+    const unsigned long long refw = (since0 == 4 ? LO : 0ull) | (since1 == 4 ? HI : 0ull);
+    if (refw) {
+      const double nb2 = farthest_bound_pair(C);
+      if (lane_on(refw)) {
+        C.rmax2 = nb2;
+        lim = 2.0 * nb2;
       }
+      stalew &= ~refw;
+      if (refw & LO) since0 = 0;
+      if (refw & HI) since1 = 0;
     }
   }
-  if (__ballot(stale)) {
+  if (stalew) {
     const double nb = farthest_bound_pair(C);
-    if (stale) C.rmax2 = nb;
+    if (lane_on(stalew)) C.rmax2 = nb;
   }
-  return fail;
+  return lane_on(failp) ? F_PLANES : lane_on(failv) ? F_VERTS : 0;
 }
 
 // Faces, volume and centroid of each half's finished cell (as finish_cell;
