@@ -170,25 +170,39 @@ __device__ __forceinline__ unsigned long long plane_bits(uint32_t t) {
   return (1ull << (t & 255u)) | (1ull << ((t >> 8) & 255u)) | (1ull << ((t >> 16) & 255u));
 }
 
+// 1/x from the hardware estimate refined by two Newton steps (within an
+// ulp of the quotient; the estimate's error squares at each step), with
+// correctly rounded division outside the normal range, where the estimate
+// would over- or underflow.
+__device__ __forceinline__ double rcp_nr(double x) {
+  if (fabs(x) > 1e-280 && fabs(x) < 1e280) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+  }
+  return 1.0 / x;
+}
+
+// 1/sqrt(x) for x > 0 likewise: the hardware estimate and two Newton steps
+// (y <- y + y (1 - x y^2) / 2), the square root and a division outside the
+// normal range.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  if (x > 1e-280 && x < 1e280) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  }
+  return 1.0 / sqrt(x);
+}
+
 // Vertex where planes a, b, c meet: solve [a; b; c] v = (a.w, b.w, c.w).
-// The determinant's reciprocal comes from the hardware estimate refined by
-// two Newton steps (within an ulp of the quotient; the estimate's error
-// squares at each step), with correctly rounded division outside the
-// normal range, where the estimate would over- or underflow.
 __device__ __forceinline__ void intersect3(const double4 a, const double4 b, const double4 c, double& x, double& y,
                                            double& z) {
   const double bcx = b.y * c.z - b.z * c.y, bcy = b.z * c.x - b.x * c.z, bcz = b.x * c.y - b.y * c.x;
   const double cax = c.y * a.z - c.z * a.y, cay = c.z * a.x - c.x * a.z, caz = c.x * a.y - c.y * a.x;
   const double abx = a.y * b.z - a.z * b.y, aby = a.z * b.x - a.x * b.z, abz = a.x * b.y - a.y * b.x;
   const double det = a.x * bcx + a.y * bcy + a.z * bcz;
-  double inv;
-  if (fabs(det) > 1e-280 && fabs(det) < 1e280) {
-    inv = __builtin_amdgcn_rcp(det);
-    inv = fma(fma(-det, inv, 1.0), inv, inv);
-    inv = fma(fma(-det, inv, 1.0), inv, inv);
-  } else {
-    inv = 1.0 / det;
-  }
+  const double inv = rcp_nr(det);
   x = (a.w * bcx + b.w * cax + c.w * abx) * inv;
   y = (a.w * bcy + b.w * cay + c.w * aby) * inv;
   z = (a.w * bcz + b.w * caz + c.w * abz) * inv;
@@ -1573,14 +1587,19 @@ __device__ void sort_pair(PairLds& S, const int nc) {
   const int hl = hlane();
   const int c0 = hl, c1 = hl + 32;
   int lt0 = 0, lt1 = 0;
-  const double k0 = c0 < nc ? S.cd[c0].w : 0.0, k1 = c1 < nc ? S.cd[c1].w : 0.0;
+  // Keys past the half's count read as +inf while ranking: no bound test
+  // in the loop.
+  constexpr double kInf = __builtin_huge_val();
+  const double k0 = c0 < nc ? S.cd[c0].w : kInf, k1 = c1 < nc ? S.cd[c1].w : kInf;
   const int ncmax = (int)wave_umax32((unsigned)nc);
+  if (c0 >= nc && c0 < ncmax) S.cd[c0].w = kInf;
+  if (c1 >= nc && c1 < ncmax) S.cd[c1].w = kInf;
+  wave_sync();
+#pragma unroll 4
   for (int m = 0; m < ncmax; ++m) {
-    if (m < nc) {
-      const double km = S.cd[m].w;
-      lt0 += km < k0;
-      lt1 += km < k1;
-    }
+    const double km = S.cd[m].w;
+    lt0 += km < k0;
+    lt1 += km < k1;
   }
   if (c0 < nc) S.order[lt0] = (uint8_t)c0;
   else if (c0 < kCandsP) S.order[c0] = 0;
@@ -1815,31 +1834,35 @@ __device__ int finish_pair(PairLds& S, const TessArgs& A, const bool act, const 
     const bool valid = act && p < kPlanesP && ((usedL >> p) & 1ull);
     if (valid) {
       const double4 P = S.pl[p];
-      dl[k] = sqrt(2.0 * P.w);
-      const double idl = 1.0 / dl[k];
+      const double w2 = 2.0 * P.w;   // the plane's |d|^2
+      const double idl = rsqrt_nr(w2);
+      dl[k] = w2 * idl;
       const double nx = P.x * idl, ny = P.y * idl, nz = P.z * idl;
       const int tstart = S.first[p];
       const double ox = S.vx[tstart], oy = S.vy[tstart], oz = S.vz[tstart];
       int t = tstart, it = 0;
       double as = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+      double x1 = 0.0, y1 = 0.0, z1 = 0.0;   // vertex t relative to the first
       do {
         const uint32_t T = S.tri[t];
         const int a = T & 255, bq = (T >> 8) & 255, cq = (T >> 16) & 255;
         const int z = (a == p) ? cq : (bq == p ? a : bq);
         const int tn = S.E[p * kPlanesP + z] & (kVertsP - 1);
-        const double x1 = S.vx[t] - ox, y1 = S.vy[t] - oy, z1 = S.vz[t] - oz;
         const double x2 = S.vx[tn] - ox, y2 = S.vy[tn] - oy, z2 = S.vz[tn] - oz;
         const double ar = 0.5 * ((y1 * z2 - z1 * y2) * nx + (z1 * x2 - x1 * z2) * ny + (x1 * y2 - y1 * x2) * nz);
         as += ar;
         mx += ar * (x1 + x2);
         my += ar * (y1 + y2);
         mz += ar * (z1 + z2);
+        x1 = x2;
+        y1 = y2;
+        z1 = z2;
         t = tn;
         ++it;
       } while (t != tstart && it < kVertsP);
       walk_bad |= (t != tstart);
       Af[k] = as;
-      const double i3a = 1.0 / (3.0 * as);
+      const double i3a = rcp_nr(3.0 * as);
       fx[k] = ox + mx * i3a;
       fy[k] = oy + my * i3a;
       fz[k] = oz + mz * i3a;
@@ -1854,7 +1877,7 @@ __device__ int finish_pair(PairLds& S, const TessArgs& A, const bool act, const 
     vol[k] = keep[k] ? Af[k] * dl[k] / 6.0 : 0.0;
   }
   const double V = half_sum(vol[0] + vol[1]);
-  const double iV = 1.0 / V;
+  const double iV = rcp_nr(V);
   const double cxr = half_sum((keep[0] ? 0.75 * vol[0] * fx[0] : 0.0) + (keep[1] ? 0.75 * vol[1] * fx[1] : 0.0)) * iV;
   const double cyr = half_sum((keep[0] ? 0.75 * vol[0] * fy[0] : 0.0) + (keep[1] ? 0.75 * vol[1] * fy[1] : 0.0)) * iV;
   const double czr = half_sum((keep[0] ? 0.75 * vol[0] * fz[0] : 0.0) + (keep[1] ? 0.75 * vol[1] * fz[1] : 0.0)) * iV;
