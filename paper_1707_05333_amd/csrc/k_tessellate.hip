@@ -196,16 +196,19 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 }
 
 // Vertex where planes a, b, c meet: solve [a; b; c] v = (a.w, b.w, c.w).
+// By Cramer's rule v = (a.w (b x c) + b.w (c x a) + c.w (a x b)) / det with
+// det = a . (b x c) = c . (a x b); the first two terms are one cross
+// product, (a.w b - b.w a) x c, so two cross products and one dot product
+// do (c is the new plane of a cut, a and b the planes of the edge it cuts).
 __device__ __forceinline__ void intersect3(const double4 a, const double4 b, const double4 c, double& x, double& y,
                                            double& z) {
-  const double bcx = b.y * c.z - b.z * c.y, bcy = b.z * c.x - b.x * c.z, bcz = b.x * c.y - b.y * c.x;
-  const double cax = c.y * a.z - c.z * a.y, cay = c.z * a.x - c.x * a.z, caz = c.x * a.y - c.y * a.x;
   const double abx = a.y * b.z - a.z * b.y, aby = a.z * b.x - a.x * b.z, abz = a.x * b.y - a.y * b.x;
-  const double det = a.x * bcx + a.y * bcy + a.z * bcz;
+  const double det = c.x * abx + c.y * aby + c.z * abz;
+  const double ux = a.w * b.x - b.w * a.x, uy = a.w * b.y - b.w * a.y, uz = a.w * b.z - b.w * a.z;
   const double inv = rcp_nr(det);
-  x = (a.w * bcx + b.w * cax + c.w * abx) * inv;
-  y = (a.w * bcy + b.w * cay + c.w * aby) * inv;
-  z = (a.w * bcz + b.w * caz + c.w * abz) * inv;
+  x = (uy * c.z - uz * c.y + c.w * abx) * inv;
+  y = (uz * c.x - ux * c.z + c.w * aby) * inv;
+  z = (ux * c.y - uy * c.x + c.w * abz) * inv;
 }
 
 __device__ void fail_cell(const TessArgs& A, int s, int seg, int bit) {
