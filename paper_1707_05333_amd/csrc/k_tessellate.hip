@@ -1317,12 +1317,6 @@ __device__ __forceinline__ unsigned half_umax32(unsigned x) {
   return half_pick(x);
 }
 
-__device__ __forceinline__ unsigned long long half_or(unsigned long long v) {
-  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-  MM_DPP_REDUCE_HALF(op_or, lo);
-  MM_DPP_REDUCE_HALF(op_or, hi);
-  return ((unsigned long long)half_pick(hi) << 32) | half_pick(lo);
-}
 
 // Upper bound of the half's largest non-negative finite value (as
 // wave_max_bound).
@@ -1824,24 +1818,21 @@ __device__ int finish_pair(PairLds& S, const TessArgs& A, const bool act, const 
     atomicMin(&S.first[(C.t1 >> 16) & 255], hl + 32);
   }
   wave_sync();
-  unsigned long long ul = 0ull;
-  if (live0) ul |= plane_bits(C.t0);
-  if (live1) ul |= plane_bits(C.t1);
-  const unsigned long long usedL = half_or(ul);
 
+  // A plane slot is a face of the cell when a live vertex lies on it: its
+  // first vertex was set above.
   double Af[2] = {0.0, 0.0}, fx[2] = {0.0, 0.0}, fy[2] = {0.0, 0.0}, fz[2] = {0.0, 0.0}, dl[2] = {0.0, 0.0};
   bool walk_bad = false;
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int p = hl + 32 * k;
-    const bool valid = act && p < kPlanesP && ((usedL >> p) & 1ull);
-    if (valid) {
+    const int tstart = p < kPlanesP ? S.first[p] : kVertsP;
+    if (act && tstart < kVertsP) {
       const double4 P = S.pl[p];
       const double w2 = 2.0 * P.w;   // the plane's |d|^2
       const double idl = rsqrt_nr(w2);
       dl[k] = w2 * idl;
       const double nx = P.x * idl, ny = P.y * idl, nz = P.z * idl;
-      const int tstart = S.first[p];
       const double ox = S.vx[tstart], oy = S.vy[tstart], oz = S.vz[tstart];
       int t = tstart, it = 0;
       double as = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
