@@ -92,6 +92,7 @@ struct TessArgs {
   int64_t dense_cap;                 // listed dense cells the two-cell dense pass takes (even)
   DevStatus* st;
   SegStatus* segst;
+  GridParams g1;                     // the grid when there is one segment (a kernel argument)
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -1963,11 +1964,13 @@ __device__ inline void redo_cell(const TessArgs& A, int s) {
 // whose stencil holds a dense bucket is listed for them.  DENSE = true: the
 // cells of those lists, with the two-level gather.  Either way a cell the
 // half cannot finish is handed to the one-cell pass of its kind.
-template <bool DENSE>
+// ONE: one segment, whose grid comes with the kernel's arguments (scalar
+// loads at the start, instead of a load that waits for the cell's segment).
+template <bool DENSE, bool ONE>
 __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) {
   const int hl = hlane();
-  const int seg = A.sseg[s];
-  const GridParams& g = A.segs[seg].g;
+  const int seg = ONE ? 0 : A.sseg[s];
+  const GridParams& g = ONE ? A.g1 : A.segs[seg].g;
   CellGeom G;
   cell_geom(A, g, s, G);
   const double* r = G.r;
@@ -2048,7 +2051,7 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
         PairLds* Sp = &S;
         asm volatile("" : "+v"(Sp));
         PairLds& S2 = *Sp;
-        const GridParams& g2 = A.segs[A.sseg[s2]].g;
+        const GridParams& g2 = ONE ? A.g1 : A.segs[A.sseg[s2]].g;
         CellGeom G2;
         cell_geom(A, g2, s2, G2);
         int ring2 = 0;
@@ -2115,11 +2118,12 @@ __device__ void pair_cell(PairLds& S, const TessArgs& A, bool act, const int s) 
 }
 
 // Two cells per wavefront: cells 2w and 2w + 1 of the launch.
+template <bool ONE>
 __global__ __launch_bounds__(64) void k_tess_pair(TessArgs A) {
   __shared__ PairLds lds[2];
   const int64_t s64 = 2 * xcd_block() + (__lane_id() >> 5);
   const bool act = s64 < A.n;
-  pair_cell<false>(lds[__lane_id() >> 5], A, act, act ? (int)s64 : 0);
+  pair_cell<false, ONE>(lds[__lane_id() >> 5], A, act, act ? (int)s64 : 0);
 }
 
 // The listed cells of dense regions, two per wavefront: those of the dense
@@ -2136,6 +2140,7 @@ __global__ __launch_bounds__(64) void k_tess_pair(TessArgs A) {
 // slower).  Four waves per SIMD, with some registers spilled (at two,
 // without spills, or three the polytropes' dense cells take 30% or 7%
 // longer).
+template <bool ONE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_tess_pair_dense(TessArgs A) {
   __shared__ PairLds lds[2];
   const int64_t nd = min((int64_t)A.st->n_dense_cells, A.dense_cap);
@@ -2147,7 +2152,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
   if (it >= npair) return;
   const int64_t q = 2 * it + (__lane_id() >> 5);
   const bool act = q < nd;
-  pair_cell<true>(lds[__lane_id() >> 5], A, act, A.dcells[act ? q : 2 * it]);
+  pair_cell<true, ONE>(lds[__lane_id() >> 5], A, act, A.dcells[act ? q : 2 * it]);
 }
 
 // The one-cell first pass over the cells the pair pass handed on.  Four
@@ -2167,15 +2172,19 @@ void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const
                        const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
                        StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
                        double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, int64_t dense_hint,
-                       DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
+                       const GridParams* g_one, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
   if (n <= 0) return;
   // Grid of the two-cell dense pass: the last tessellation's dense-list
   // length and a quarter more (all cells when there is none yet).
   const int64_t want = dense_hint < 0 ? n : std::min<int64_t>(n, dense_hint + dense_hint / 4 + 256);
   const int64_t dense_cap = (want + 1) / 2 * 2;
   TessArgs A{spos,   n,     segs,     sseg,   boff,      sbase,  soffs, stage_nb, stage_geo, counts,
-             geo,    rmax2, deferred, dcells, redo,      dense_cap, st_dev, segst};
-  hipLaunchKernelGGL(k_tess_pair, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, A);
+             geo,    rmax2, deferred, dcells, redo,      dense_cap, st_dev, segst, GridParams{}};
+  if (g_one) A.g1 = *g_one;
+  if (g_one)
+    hipLaunchKernelGGL(k_tess_pair<true>, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, A);
+  else
+    hipLaunchKernelGGL(k_tess_pair<false>, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, A);
   // The handed-on and deferred counts are known on the device only: enough
   // blocks for a large share of the cells, each exits at once when there is
   // none.  Cells of these lists differ widely in cost, so each block takes
@@ -2186,7 +2195,10 @@ void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const
   hipLaunchKernelGGL(k_tess_pass1_redo, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
   // (The hand-off list of the lean pass has been read: the dense passes'
   // hand-offs reuse it.)
-  hipLaunchKernelGGL(k_tess_pair_dense, dim3((unsigned)(dense_cap / 2 + kXcds)), dim3(64), 0, st, A);
+  if (g_one)
+    hipLaunchKernelGGL(k_tess_pair_dense<true>, dim3((unsigned)(dense_cap / 2 + kXcds)), dim3(64), 0, st, A);
+  else
+    hipLaunchKernelGGL(k_tess_pair_dense<false>, dim3((unsigned)(dense_cap / 2 + kXcds)), dim3(64), 0, st, A);
   hipLaunchKernelGGL(k_tess_pass1_dense, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
   hipLaunchKernelGGL(k_tess_pass2, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
 }

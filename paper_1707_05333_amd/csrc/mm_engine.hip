@@ -312,8 +312,10 @@ void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int3
   launch_sort(pos, n_slots, slot_seg, n_cells, segs, n_buckets, bcount, boff, scan_tmp, sbase, soffs, key, perm,
               sseg, spos, dcells, st, segst, stream);
   mark(1);
+  // One segment: its grid (the descriptor uploaded last) travels with the
+  // pair passes' arguments.
   launch_tessellate(spos, n_cells, segs, sseg, boff, sbase, soffs, stage_nb, stage_geo, counts, geo, rmax2, deferred,
-                    dcells, redo, dense_hint, st, segst, stream);
+                    dcells, redo, dense_hint, nseg == 1 ? &segs_host[0].g : nullptr, st, segst, stream);
   mark(2);
   scan_u64(counts, off, n_cells, scan_tmp, stream);
   launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, sw, soff, scan_tmp, fcap,

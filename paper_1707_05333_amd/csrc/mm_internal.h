@@ -278,7 +278,7 @@ void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const
                        const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
                        StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
                        double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, int64_t dense_hint,
-                       DevStatus* st_dev, SegStatus* segst, hipStream_t st);
+                       const GridParams* g_one, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
 // Per-cell lists (face ids with sign, neighbour entries) use a sliced ELL
 // layout: slices of 64 consecutive internal cells, each as wide as its
