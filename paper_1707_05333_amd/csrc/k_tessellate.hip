@@ -2168,15 +2168,16 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(4))
 
 }  // namespace
 
-void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
-                       const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
-                       StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
-                       double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, int64_t dense_hint,
-                       const GridParams* g_one, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
-  if (n <= 0) return;
+int64_t launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
+                          const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
+                          StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
+                          double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, const TessHints& hints,
+                          const GridParams* g_one, DevStatus* st_dev, SegStatus* segst, hipStream_t st) {
+  if (n <= 0) return 0;
   // Grid of the two-cell dense pass: the last tessellation's dense-list
   // length and a quarter more (all cells when there is none yet).
-  const int64_t want = dense_hint < 0 ? n : std::min<int64_t>(n, dense_hint + dense_hint / 4 + 256);
+  const int64_t dh = hints.dense_cells;
+  const int64_t want = dh < 0 ? n : std::min<int64_t>(n, dh + dh / 4 + 256);
   const int64_t dense_cap = (want + 1) / 2 * 2;
   TessArgs A{spos,   n,     segs,     sseg,   boff,      sbase,  soffs, stage_nb, stage_geo, counts,
              geo,    rmax2, deferred, dcells, redo,      dense_cap, st_dev, segst, GridParams{}};
@@ -2185,22 +2186,30 @@ void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const
     hipLaunchKernelGGL(k_tess_pair<true>, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, A);
   else
     hipLaunchKernelGGL(k_tess_pair<false>, dim3((unsigned)((n + 1) / 2)), dim3(64), 0, st, A);
-  // The handed-on and deferred counts are known on the device only: enough
-  // blocks for a large share of the cells, each exits at once when there is
-  // none.  Cells of these lists differ widely in cost, so each block takes
-  // few of them (65536 blocks: the polytropes' cell construction 15% faster
-  // than with 16384; 262144 no faster, and the empty launches cost the Sod
-  // tube 1%).
-  const unsigned blocks2 = (unsigned)std::min<int64_t>((n + kWaves - 1) / kWaves, 65536);
-  hipLaunchKernelGGL(k_tess_pass1_redo, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
+  // The handed-on and deferred counts are known on the device only.  Each
+  // list pass gets blocks for the length the last tessellation's list had
+  // and a quarter more (a wavefront per cell; at least 256 blocks), at most
+  // 65536 (the cells of these lists differ widely in cost, so each block
+  // takes few of them: the polytropes' cell construction 15% faster with
+  // 65536 blocks than with 16384, 262144 no faster), and 65536 before any
+  // length is known.  A block with no cell exits at once; a list longer
+  // than its grid is walked with a grid stride.
+  auto list_blocks = [n](int64_t hint) -> unsigned {
+    const int64_t full = std::min<int64_t>((n + kWaves - 1) / kWaves, 65536);
+    if (hint < 0) return (unsigned)full;
+    const int64_t want_b = (hint + hint / 4 + kWaves - 1) / kWaves;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(full, std::max<int64_t>(want_b, 256)));
+  };
+  hipLaunchKernelGGL(k_tess_pass1_redo, dim3(list_blocks(hints.redo)), dim3(64 * kWaves), 0, st, A);
   // (The hand-off list of the lean pass has been read: the dense passes'
   // hand-offs reuse it.)
   if (g_one)
     hipLaunchKernelGGL(k_tess_pair_dense<true>, dim3((unsigned)(dense_cap / 2 + kXcds)), dim3(64), 0, st, A);
   else
     hipLaunchKernelGGL(k_tess_pair_dense<false>, dim3((unsigned)(dense_cap / 2 + kXcds)), dim3(64), 0, st, A);
-  hipLaunchKernelGGL(k_tess_pass1_dense, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
-  hipLaunchKernelGGL(k_tess_pass2, dim3(blocks2), dim3(64 * kWaves), 0, st, A);
+  hipLaunchKernelGGL(k_tess_pass1_dense, dim3(list_blocks(hints.dense_redo)), dim3(64 * kWaves), 0, st, A);
+  hipLaunchKernelGGL(k_tess_pass2, dim3(list_blocks(hints.deferred)), dim3(64 * kWaves), 0, st, A);
+  return dense_cap;
 }
 
 }  // namespace mm

@@ -75,9 +75,11 @@ struct Engine {
   int nseg = 0;
   // Mesh currently held.
   int64_t n = 0, n_faces = 0, nbt = 0;
-  // Dense-list length of the last tessellation read back (-1: none yet); it
-  // sizes the two-cell dense pass's grid only.
-  int64_t dense_hint = -1;
+  // List lengths of the last tessellation read back (none yet: -1); they
+  // size the list passes' grids only.  last_dense_cap: the listed dense
+  // cells the last two-cell dense pass took.
+  TessHints hints;
+  int64_t last_dense_cap = 0;
   // First-pass candidate radius in mean spacings.  It changes only the
   // work, never the cells (clipping is always in order of distance, ties
   // broken by neighbour and image).  With the first pass taking up to three

@@ -314,8 +314,9 @@ void Engine::enqueue_tessellation(const double* pos, int64_t n_slots, const int3
   mark(1);
   // One segment: its grid (the descriptor uploaded last) travels with the
   // pair passes' arguments.
-  launch_tessellate(spos, n_cells, segs, sseg, boff, sbase, soffs, stage_nb, stage_geo, counts, geo, rmax2, deferred,
-                    dcells, redo, dense_hint, nseg == 1 ? &segs_host[0].g : nullptr, st, segst, stream);
+  last_dense_cap = launch_tessellate(spos, n_cells, segs, sseg, boff, sbase, soffs, stage_nb, stage_geo, counts, geo,
+                                     rmax2, deferred, dcells, redo, hints, nseg == 1 ? &segs_host[0].g : nullptr, st,
+                                     segst, stream);
   mark(2);
   scan_u64(counts, off, n_cells, scan_tmp, stream);
   launch_build_mesh(spos, geo, n_cells, segs, sseg, stage_nb, stage_geo, counts, off, sw, soff, scan_tmp, fcap,
@@ -397,7 +398,11 @@ mm_status Engine::readback() {
     e = hipMemcpyAsync(segst_host, segst, sizeof(SegStatus) * nseg, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return fail(MM_EHIP, std::string("status readback: ") + hipGetErrorString(e));
-  dense_hint = st_host->n_dense_cells;
+  const DevStatus& s = *st_host;
+  hints.dense_cells = s.n_dense_cells;
+  hints.redo = s.n_redo;
+  hints.dense_redo = s.n_dredo + std::max<int64_t>(0, (int64_t)s.n_dense_cells - last_dense_cap);
+  hints.deferred = s.n_deferred;
   return MM_OK;
 }
 

@@ -271,14 +271,24 @@ void launch_sort(const double* pos, int64_t n_slots, const int32_t* slot_seg, in
                  unsigned long long* sbase, uint32_t* soffs, int32_t* key, int32_t* perm, int32_t* sseg,
                  double* spos, int32_t* dcells, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
+// Lengths of an earlier tessellation's cell lists (-1: none yet).  They size
+// the grids of the passes that read the lists, never their results (those
+// passes walk their lists with a grid stride; the two-cell dense pass hands
+// listed cells beyond its grid to the one-cell dense pass).
+struct TessHints {
+  int64_t dense_cells = -1;   // cells listed for the dense passes
+  int64_t redo = -1;          // cells the lean two-cell pass handed on
+  int64_t dense_redo = -1;    // cells of the one-cell dense pass
+  int64_t deferred = -1;      // cells of the shell pass
+};
+
 // Tessellation: pass 1 over every cell, then the listed and deferred cells.
-// dense_hint: the dense-list length of an earlier tessellation (-1: none),
-// which sizes the grid of the two-cell dense pass (never its results).
-void launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
-                       const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
-                       StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
-                       double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, int64_t dense_hint,
-                       const GridParams* g_one, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
+// Returns the number of listed dense cells the two-cell dense pass takes.
+int64_t launch_tessellate(const double* spos, int64_t n, const SegDesc* segs, const int32_t* sseg,
+                          const unsigned long long* boff, const unsigned long long* sbase, const uint32_t* soffs,
+                          StageNbr* stage_nb, StageGeo* stage_geo, unsigned long long* counts, double* geo,
+                          double* rmax2, int32_t* deferred, int32_t* dcells, int32_t* redo, const TessHints& hints,
+                          const GridParams* g_one, DevStatus* st_dev, SegStatus* segst, hipStream_t st);
 
 // Per-cell lists (face ids with sign, neighbour entries) use a sliced ELL
 // layout: slices of 64 consecutive internal cells, each as wide as its
