@@ -49,16 +49,22 @@ def test_c5_small_tessellation_parity(orc, c5_small):
 def test_dense_cells_beyond_the_sized_grid(orc, c5_small):
     """The two-cells-per-wavefront dense pass launches as many wavefronts as
     the previous tessellation listed dense cells (and a quarter more); listed
-    cells beyond that go to the one-cell dense pass.  A context that first
-    tessellates uniform random points (no dense cell, so the next grid is
-    small) and then the polytropes (thousands of dense cells) builds the
-    polytropes' tessellation exactly as the oracle does."""
+    cells beyond that go to the one-cell dense pass.  The passes over the
+    other lists get grids sized from the previous lists' lengths (256 blocks
+    of 4 wavefronts at least) and walk longer lists with a grid stride.  A
+    context that first tessellates uniform random points (no dense cell and
+    no cell for the shell pass, so those grids are small) and then the
+    polytropes (thousands of dense cells, and more cells for the shell pass
+    than its grid has wavefronts) builds the polytropes' tessellation
+    exactly as the oracle does."""
     import paper_1707_05333_amd as M
     wl = c5_small
     _case("dense cells beyond the sized grid", n=wl.n)
     mm = M.MovingMesh(wl.n, M.make_params(box=wl.box, **wl.params))
-    mm.tessellate(dev(W.poisson_points(wl.n, wl.box, seed=11)))
+    first = mm.tessellate(dev(W.poisson_points(wl.n, wl.box, seed=11)))
+    assert first["deferred_cells"] == 0
     info = mm.tessellate(dev(wl.pos))
+    assert info["deferred_cells"] > 256 * 4   # the shell pass's list outgrows its grid
     om = orc.tessellate(wl.pos, wl.box, certificate=True)
     assert om.status == 0 and om.delta_min > 1e-12
     compare_mesh(mm, om)
