@@ -19,7 +19,7 @@ namespace {
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-constexpr int kGroup = 16;                       // lanes per cell in the assembly
+constexpr int kGroup = 8;                        // lanes per cell in the assembly
 constexpr int kMeshThreads = 256;
 constexpr int kCellsPerBlock = kMeshThreads / kGroup;
 
@@ -35,7 +35,9 @@ __global__ __launch_bounds__(256) void k_slice_width(const unsigned long long* _
   if (k < nslices && __lane_id() == 0) sw[k] = 64ull * (unsigned long long)w;
 }
 
-// Sixteen lanes per cell; lane l takes the cell's faces l, l + 16, ...
+// Eight lanes per cell; lane l takes the cell's faces l, l + 8, ... (a lane
+// walks two or three faces: more cells per wavefront than with sixteen
+// lanes, whose last lanes idle while the first take a second face).
 // The packed prefix sum off[] holds, for cell s, the index of its first
 // unique face in its low 32 bits.
 template <typename R>

@@ -1247,7 +1247,8 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(3))
 // before; a lean cell whose stencil holds a dense bucket is listed for the
 // dense passes.  Values that are uniform per cell are uniform per half here:
 // held in each lane of the half, and the half's 32 bits of every ballot are
-// its masks.
+// its masks (the cut loop keeps its per-half flags as wavefront masks and
+// counters in scalar registers instead).
 // ---------------------------------------------------------------------------
 constexpr int kPlanesP = 40;
 constexpr int kVertsP = 64;
@@ -1632,7 +1633,7 @@ __device__ int clip_pair(PairLds& S, const int nc, PairRegs& C) {
   // The per-half state is held as wavefront masks (a half's 32 bits all set
   // or all clear) and per-half counters, which the compiler keeps in scalar
   // registers: a lane's own flag is a select on the mask, and the loop's
-  // control costs no vector instructions.
+  // control is scalar work apart from the compares behind its ballots.
   unsigned long long donew = __ballot(nc <= 0);   // halves that stopped
   unsigned long long stalew = 0ull;                // rmax2 older than the last cut
   unsigned long long failp = 0ull, failv = 0ull;  // halves out of plane or vertex slots
