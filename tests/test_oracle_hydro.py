@@ -306,6 +306,39 @@ def test_lsq_gradient_exact_on_linear_fields(orc):
     np.testing.assert_allclose(GL[inner], G[inner], rtol=1e-9, atol=1e-12)
 
 
+def test_lsq_weight_closed_form_on_a_bcc_lattice(orc):
+    """Pins the least-squares weight w = A / |d|^2 (reading R-grad), which
+    linear fields cannot: every positive weighting is exact on them.  On a
+    BCC lattice of cube side a every cell is a truncated octahedron: 8
+    hexagonal faces of area 3 sqrt(3) a^2 / 16 towards neighbours at
+    distance sqrt(3) a / 2, and 6 square faces of area a^2 / 8 towards
+    neighbours at distance a, so w_hex = sqrt(3) / 4 and w_sq = 1 / 8.  By
+    the cubic symmetry the LSQ matrix is m I, and for phi = (x - x_c)^3 the
+    x slope is sum w d_x^4 / sum w d_x^2 = a^2 (w_hex / 2 + 2 w_sq) /
+    (2 w_hex + 2 w_sq) = a^2 (sqrt(3) + 2) / (2 (2 sqrt(3) + 1)) = 0.41801
+    a^2.  Weights 1 / |d|^2, A / |d|, A or 1 would give 0.5714, 0.4375,
+    0.4585 or 0.625 a^2."""
+    m_side, box = 4, (1.0, 1.0, 1.0)
+    a = 1.0 / m_side
+    pos = W.bcc_lattice(m_side, box)
+    p = orc.make_params(box, gamma=5.0 / 3.0)
+    m = orc.tessellate(pos, box, method="grid")
+    assert m.status == 0
+    # a cell whose neighbours along x do not wrap across the box
+    i = int(np.argmin(np.abs(m.c[:, 0] - 0.5)))
+    assert abs(m.c[i, 0] - 0.5) <= 0.5 * a
+    # its faces: 8 hexagons and 6 squares of the stated areas
+    A = np.sort(m.A[m.off[i]:m.off[i + 1]])
+    np.testing.assert_allclose(A, [a * a / 8] * 6 + [3 * np.sqrt(3) * a * a / 16] * 8, rtol=1e-12)
+    U = np.ones((m.n, 5))
+    U[:, 0] = 1.0 + (m.c[:, 0] - m.c[i, 0]) ** 3
+    G = orc.gradient(m, p, U, limit=False)
+    expect = a * a * (np.sqrt(3.0) + 2.0) / (2.0 * (2.0 * np.sqrt(3.0) + 1.0))
+    assert abs(G[i, 0, 0] - expect) <= 1e-12 * expect
+    assert abs(G[i, 0, 1]) <= 1e-14 and abs(G[i, 0, 2]) <= 1e-14
+    np.testing.assert_allclose(G[i, 1:], 0.0, atol=1e-14)
+
+
 def test_s10_limiter_bound(orc):
     # After limiting, the extrapolation from c_i to every neighbour centroid
     # stays within the extrema of the cell and its neighbours (Sec. 4.1).
