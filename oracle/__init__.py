@@ -5,10 +5,9 @@ ctypes wrapper around ``liboracle.so`` built from ``mm_oracle.cpp`` (see
 benchmark's CPU-baseline leg may import this package.  It shares no code
 with ``paper_1707_05333_amd``: neither imports the other.
 
-Parity unpinned: none of the functions here reproduces a worked example
-printed in the paper (it prints none, and its figures are absent); each is
-pinned instead by closed forms, invariants and brute force in
-``tests/test_oracle_*.py``.
+No function here reproduces a worked example printed in the paper (it
+prints none, and its figures are absent); each is pinned instead by closed
+forms, invariants and brute force in ``tests/test_oracle_*.py``.
 """
 from __future__ import annotations
 
