@@ -380,7 +380,7 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int nf = (int)(counts[s] >> 32);
-  const NbrEntry<R>* list = nbr + sell_slot(soff, s, 0);   // entry e at list[64 e]
+  const int64_t slot0 = sell_slot(soff, s, 0);   // entry e at slot0 + 64 e
   R ui[5], umax[5], umin[5], b[15];
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
@@ -395,8 +395,9 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
   constexpr int kUnroll = sizeof(R) == 8 ? 2 : 1;
 #pragma unroll kUnroll
   for (int e = 0; e < nf; ++e) {
-    const NbrEntry<R> E = list[64 * e];
-    const R dx = E.d[0], dy = E.d[1], dz = E.d[2], wg = E.wgt;
+    const NbrW<R> E = *nbr_w(nbr, slot0 + 64 * e);
+    const R* dd = nbr_d(nbr, slot0 + 64 * e);
+    const R dx = dd[0], dy = dd[1], dz = dd[2], wg = E.wgt;
     const R* uo = U + 5 * (int64_t)E.o;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -433,8 +434,8 @@ __global__ __launch_bounds__(kThreads) void k_gradient(const SegDesc* __restrict
 #pragma unroll
     for (int q = 0; q < 5; ++q) dpos[q] = dneg[q] = R(0);
     for (int e = 0; e < nf; ++e) {
-      const NbrEntry<R> E = list[64 * e];
-      const R dx = E.d[0], dy = E.d[1], dz = E.d[2];
+      const R* dd = nbr_d(nbr, slot0 + 64 * e);
+      const R dx = dd[0], dy = dd[1], dz = dd[2];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
         const R D = g[3 * q] * dx + g[3 * q + 1] * dy + g[3 * q + 2] * dz;
@@ -699,16 +700,17 @@ __global__ __launch_bounds__(kThreads) void k_entropy_gradient(
   const int64_t s = xcd_block() * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int nf = (int)(counts[s] >> 32);
-  const NbrEntry<R>* list = nbr + sell_slot(soff, s, 0);
+  const int64_t slot0 = sell_slot(soff, s, 0);   // entry e at slot0 + 64 e
   const R xi = X[s];
   R xmax = xi, xmin = xi, b[3] = {R(0), R(0), R(0)};
   for (int e = 0; e < nf; ++e) {
-    const NbrEntry<R> E = list[64 * e];
+    const NbrW<R> E = *nbr_w(nbr, slot0 + 64 * e);
+    const R* dd = nbr_d(nbr, slot0 + 64 * e);
     const R v = X[E.o];
     const R t = E.wgt * (v - xi);
-    b[0] += t * E.d[0];
-    b[1] += t * E.d[1];
-    b[2] += t * E.d[2];
+    b[0] += t * dd[0];
+    b[1] += t * dd[1];
+    b[2] += t * dd[2];
     xmax = v > xmax ? v : xmax;
     xmin = v < xmin ? v : xmin;
   }
@@ -723,8 +725,8 @@ __global__ __launch_bounds__(kThreads) void k_entropy_gradient(
   if (lim) {
     R dpos = R(0), dneg = R(0);
     for (int e = 0; e < nf; ++e) {
-      const NbrEntry<R> E = list[64 * e];
-      const R D = g[0] * E.d[0] + g[1] * E.d[1] + g[2] * E.d[2];
+      const R* dd = nbr_d(nbr, slot0 + 64 * e);
+      const R D = g[0] * dd[0] + g[1] * dd[1] + g[2] * dd[2];
       dpos = D > dpos ? D : dpos;
       dneg = D < dneg ? D : dneg;
     }

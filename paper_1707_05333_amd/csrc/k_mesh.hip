@@ -84,14 +84,15 @@ __global__ __launch_bounds__(kMeshThreads) void k_build_mesh(
       const double dy = dry + geo[4 * (int64_t)j + 2] - ciy;
       const double dz = drz + geo[4 * (int64_t)j + 3] - ciz;
       const double wgt = F.A / (dx * dx + dy * dy + dz * dz);
-      NbrEntry<R> E{};
-      E.o = j;
-      E.d[0] = (R)dx;
-      E.d[1] = (R)dy;
-      E.d[2] = (R)dz;
-      E.wgt = (R)wgt;
       const int64_t slot = sbase + 64ll * e;
-      nbr[slot] = E;
+      NbrW<R> E{};
+      E.o = j;
+      E.wgt = (R)wgt;
+      *nbr_w(nbr, slot) = E;
+      R* D = nbr_d(nbr, slot);
+      D[0] = (R)dx;
+      D[1] = (R)dy;
+      D[2] = (R)dz;
       m00 += wgt * dx * dx;
       m01 += wgt * dx * dy;
       m02 += wgt * dx * dz;

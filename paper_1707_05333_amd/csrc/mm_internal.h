@@ -142,9 +142,13 @@ struct __align__(16) FluxCell {
 static_assert(sizeof(StageNbr) == 8, "two staged entries per 16-byte load");
 static_assert(sizeof(FluxCell<float>) == 144 && sizeof(FluxCell<double>) == 240, "face kernel record sizes");
 
-// Per-cell neighbour entry used by the gradient kernel: neighbour index,
+// Per-cell neighbour entry used by the gradient kernels: neighbour index,
 // centroid displacement d = c_j + s - c_i and LSQ weight A / |d|^2, in the
 // precision of the gradient arithmetic (40 bytes in FP64, 20 in mixed).
+// NbrEntry is the unit of the list storage; each sliced row of 64 entries
+// holds its 64 (index, weight) pairs (NbrW), then its 64 displacements
+// (three values each), so the limiter's second pass over a list reads the
+// displacements only.
 template <typename R>
 struct NbrEntry;
 template <>
@@ -160,6 +164,39 @@ struct NbrEntry<float> {
   float d[3];
   float wgt;
 };
+template <typename R>
+struct NbrW;
+template <>
+struct NbrW<double> {
+  int32_t o;
+  int32_t pad;
+  double wgt;
+};
+template <>
+struct NbrW<float> {
+  int32_t o;
+  float wgt;
+};
+static_assert(sizeof(NbrW<double>) + 3 * sizeof(double) == sizeof(NbrEntry<double>) &&
+                  sizeof(NbrW<float>) + 3 * sizeof(float) == sizeof(NbrEntry<float>),
+              "a row of 64 entries splits into its pairs and its displacements");
+// The (index, weight) pair and the displacement of list slot `slot`.
+template <typename R>
+inline __host__ __device__ NbrW<R>* nbr_w(NbrEntry<R>* nbr, int64_t slot) {
+  return reinterpret_cast<NbrW<R>*>(nbr + (slot & ~63ll)) + (slot & 63);
+}
+template <typename R>
+inline __host__ __device__ const NbrW<R>* nbr_w(const NbrEntry<R>* nbr, int64_t slot) {
+  return reinterpret_cast<const NbrW<R>*>(nbr + (slot & ~63ll)) + (slot & 63);
+}
+template <typename R>
+inline __host__ __device__ R* nbr_d(NbrEntry<R>* nbr, int64_t slot) {
+  return reinterpret_cast<R*>(reinterpret_cast<NbrW<R>*>(nbr + (slot & ~63ll)) + 64) + 3 * (slot & 63);
+}
+template <typename R>
+inline __host__ __device__ const R* nbr_d(const NbrEntry<R>* nbr, int64_t slot) {
+  return reinterpret_cast<const R*>(reinterpret_cast<const NbrW<R>*>(nbr + (slot & ~63ll)) + 64) + 3 * (slot & 63);
+}
 
 // Bucket of one coordinate; the sort and the tessellation must agree on it.
 // Not-a-number and out-of-box coordinates land in a valid bucket (the sort
